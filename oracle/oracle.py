@@ -1,0 +1,218 @@
+"""CPU reference for exact and c-approximate reverse k-ranks queries.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product library never
+imports, links or runs anything here, and nothing here imports the product.
+
+What is computed, and where the paper defines it (arXiv 2504.13446):
+
+* ``ranks``     -- Sec. 2, Def. 1: r(q,u,P) = 1 + #{p : u.p > u.q}, strict ">".
+                   Inner products use one fixed FP64 evaluation (sequential
+                   fma in dimension order, see rkr_oracle.c).
+* ``topk``      -- Sec. 2, Def. 2: the k users of smallest rank ("highest
+                   rank" in the introduction means rank 1 is best); users
+                   tied on rank are ordered by id, and the answer is listed by
+                   (rank, id) ascending.
+* ``def3_check``-- Sec. 2, Def. 3: the i-th user of U_c must have rank at most
+                   c times the rank of the i-th user of U_rr.  Also the
+                   abstract's weaker form (every rank <= c * tau, with tau the
+                   k-th exact rank).
+* ``accuracy``, ``overall_ratio`` -- Sec. 5, the two quality criteria.
+* ``certify``   -- a checker for a claimed exact answer on all users or a
+                   sample of them (see orc_certify).
+* ``norm_order``, ``stratified_sample``, ``sketch`` -- the per-user score
+                   sketch: P ordered by norm, descending (Sec. 4.2 step 1),
+                   split into equal buckets with one sample from the middle
+                   of each (the norm-stratified sampling of Sec. 4.2 step 3
+                   with one sample per bucket), spec scores of the user
+                   against the samples, sorted, read at fixed positions.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rkr_oracle.c")
+_LIB = os.path.join(_HERE, "librkr_oracle.so")
+
+_CFLAGS = ["-O2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-shared", "-fPIC", "-std=c11"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle into oracle/librkr_oracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        d, i64, i32, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_dots.argtypes = [vp, i64, vp, i64, ctypes.c_int, vp]
+        L.orc_norms.argtypes = [vp, i64, ctypes.c_int, vp]
+        L.orc_ranks.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.c_int, vp, i64, vp, ctypes.c_int]
+        L.orc_certify.argtypes = [vp, i64, vp, i64, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                  i64, vp, ctypes.c_int]
+        L.orc_norm_order.argtypes = [vp, i64, vp]
+        L.orc_sketch.argtypes = [vp, i64, vp, vp, i64, ctypes.c_int, vp, ctypes.c_int, vp,
+                                 ctypes.c_int]
+        for f in (L.orc_dots, L.orc_norms, L.orc_ranks, L.orc_certify, L.orc_norm_order,
+                  L.orc_sketch):
+            f.restype = None
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+# master values -> float64 (exact widening)
+# --------------------------------------------------------------------------
+def widen(x, dtype: str | None = None) -> np.ndarray:
+    """Exact float64 copy of master values.
+
+    ``dtype='bf16'`` reads uint16 bit patterns as bfloat16; float32 and
+    float64 arrays widen directly.  Both widenings are exact.
+    """
+    x = np.asarray(x)
+    if dtype == "bf16" or x.dtype == np.uint16:
+        bits = x.astype(np.uint32) << np.uint32(16)
+        return np.ascontiguousarray(bits.view(np.float32).astype(np.float64))
+    return np.ascontiguousarray(x.astype(np.float64))
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def dots(X, Y) -> np.ndarray:
+    X = widen(X); Y = widen(Y)
+    out = np.empty((X.shape[0], Y.shape[0]), np.float64)
+    lib().orc_dots(_p(X), X.shape[0], _p(Y), Y.shape[0], X.shape[1], _p(out))
+    return out
+
+
+def norms(X) -> np.ndarray:
+    X = widen(X)
+    out = np.empty(X.shape[0], np.float64)
+    lib().orc_norms(_p(X), X.shape[0], X.shape[1], _p(out))
+    return out
+
+
+def ranks(U, P, Qv, uids=None, threads: int = 0) -> np.ndarray:
+    """Def. 1 ranks, shape [nq, nu] (nu = len(uids) or n)."""
+    U = widen(U); P = widen(P); Qv = widen(np.atleast_2d(Qv))
+    n, d = U.shape
+    assert P.shape[1] == d and Qv.shape[1] == d
+    if uids is None:
+        nu, up = n, None
+        uarr = None
+    else:
+        uarr = np.ascontiguousarray(np.asarray(uids, np.int64))
+        nu, up = uarr.shape[0], _p(uarr)
+    out = np.empty((Qv.shape[0], nu), np.int32)
+    lib().orc_ranks(_p(U), n, _p(P), P.shape[0], _p(Qv), Qv.shape[0], d, up, nu, _p(out),
+                    int(threads))
+    return out
+
+
+def topk(rank_row, k: int, uids=None):
+    """Def. 2 answer from a row of ranks: k users by (rank, id) ascending."""
+    r = np.asarray(rank_row, np.int64)
+    ids = np.arange(r.shape[0], dtype=np.int64) if uids is None else np.asarray(uids, np.int64)
+    order = np.lexsort((ids, r))[:k]
+    return ids[order], r[order]
+
+
+def certify(U, P, q, k, ids, rks, check=None, threads: int = 0):
+    """Check a claimed exact answer; returns (rank mismatches, set violations, examined)."""
+    U = widen(U); P = widen(P); q = widen(np.asarray(q).reshape(1, -1))
+    ids = np.ascontiguousarray(np.asarray(ids, np.int64))
+    rks = np.ascontiguousarray(np.asarray(rks, np.int32))
+    chk = np.arange(U.shape[0], dtype=np.int64) if check is None else \
+        np.ascontiguousarray(np.asarray(check, np.int64))
+    out = np.zeros(3, np.int64)
+    lib().orc_certify(_p(U), U.shape[0], _p(P), P.shape[0], _p(q), U.shape[1], int(k), _p(ids),
+                      _p(rks), _p(chk), chk.shape[0], _p(out), int(threads))
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def norm_order(P) -> np.ndarray:
+    nrm = norms(P)
+    out = np.empty(nrm.shape[0], np.int64)
+    lib().orc_norm_order(_p(nrm), nrm.shape[0], _p(out))
+    return out
+
+
+def stratified_sample(P, S: int) -> np.ndarray:
+    """One item from the middle of each of S equal norm buckets (ids into P)."""
+    order = norm_order(P)
+    m = order.shape[0]
+    S = min(S, m)
+    mid = ((2 * np.arange(S, dtype=np.int64) + 1) * m) // (2 * S)
+    return order[mid]
+
+
+def sketch_positions(S: int, levels: int = 16) -> np.ndarray:
+    """1-based positions spaced geometrically from 1 to S: ceil(S ** (i / (levels-1)))."""
+    i = np.arange(levels, dtype=np.float64)
+    pos = np.ceil(np.power(float(S), i / (levels - 1)) - 1e-9).astype(np.int32)
+    return np.clip(pos, 1, S)
+
+
+def sketch(U, P, sample, pos, threads: int = 0) -> np.ndarray:
+    U = widen(U); P = widen(P)
+    sample = np.ascontiguousarray(np.asarray(sample, np.int64))
+    pos = np.ascontiguousarray(np.asarray(pos, np.int32))
+    out = np.empty((U.shape[0], pos.shape[0]), np.float64)
+    lib().orc_sketch(_p(U), U.shape[0], _p(P), _p(sample), sample.shape[0], U.shape[1], _p(pos),
+                     pos.shape[0], _p(out), int(threads))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Def. 3 and the quality criteria of Sec. 5
+# --------------------------------------------------------------------------
+def def3_check(true_ranks_c, exact_ranks_rr, c: float):
+    """Return (violations, abstract-form violations).
+
+    true_ranks_c: the exact ranks of the k users returned as U_c.
+    exact_ranks_rr: the k ranks of U_rr (Def. 2).
+    The i-th user of each set is taken in rank order (Def. 3 pairs the
+    i-th user of U_c with the i-th user of U_rr).
+    """
+    a = np.sort(np.asarray(true_ranks_c, np.float64))
+    b = np.sort(np.asarray(exact_ranks_rr, np.float64))
+    assert a.shape == b.shape
+    viol = int(np.sum(a > c * b))
+    tau = b[-1] if b.size else 0.0
+    weak = int(np.sum(a > c * tau))
+    return viol, weak
+
+
+def accuracy(true_ranks_c, exact_ranks_rr, c: float) -> float:
+    a = np.sort(np.asarray(true_ranks_c, np.float64))
+    b = np.sort(np.asarray(exact_ranks_rr, np.float64))
+    return float(np.mean(a <= c * b))
+
+
+def overall_ratio(true_ranks_c, exact_ranks_rr) -> float:
+    a = np.sort(np.asarray(true_ranks_c, np.float64))
+    b = np.sort(np.asarray(exact_ranks_rr, np.float64))
+    return float(np.mean(a / b))
