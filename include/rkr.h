@@ -1,0 +1,204 @@
+/*
+ * rkr.h -- exact and c-approximate reverse k-ranks queries on AMD MI355X.
+ *
+ * Problem (arXiv 2504.13446, Sec. 2):
+ *   Def. 1  r(q,u,P) = 1 + #{p in P : u.p > u.q}            (strict ">")
+ *   Def. 2  the reverse k-ranks answer U_rr: k users whose ranks are no
+ *           worse than any user left out.  This library breaks ties on rank
+ *           by user id, so the answer is unique, and lists it by
+ *           (rank ascending, user id ascending).
+ *   Def. 3  the c-approximate answer U_c (c >= 1): the i-th user of U_c has
+ *           rank at most c times the rank of the i-th user of U_rr.
+ *
+ * Arithmetic.  The paper fixes no precision.  "u.p" here is one fixed
+ * evaluation: acc = +0.0, then acc = fma(u[k], p[k], acc) for k = 0..d-1 in
+ * order, in IEEE double, on the master values.  Every rank this library
+ * returns as exact equals the rank under that evaluation.  Scores are first
+ * computed in low precision on the matrix cores; every score within a proven
+ * error bound of its threshold is recomputed in double (the near-tie
+ * recheck).
+ *
+ * Memory and ownership.
+ *   - Pointers marked [device] are device pointers on the current HIP device
+ *     (e.g. torch tensors' data_ptr()), contiguous, row-major.  Pointers
+ *     marked [host] are host memory.
+ *   - rkr_build copies everything it needs; the caller may free U and P
+ *     when it returns.  The index owns its device memory until rkr_destroy.
+ *   - Outputs are caller-allocated.
+ *   - Every call is ordered on the stream given at build time (NULL = the
+ *     default stream) and returns after its work has completed.
+ *   - Calls on one index must not overlap (one thread at a time per index).
+ *     Distinct indexes are independent.
+ *
+ * Errors.  No call throws or aborts.  On error a call returns a status other
+ * than RKR_OK, writes no output, and rkr_last_error() returns a message for
+ * the calling thread (valid until that thread's next rkr_* call).
+ */
+#ifndef RKR_H
+#define RKR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rkr_index rkr_index;
+
+typedef enum {
+    RKR_OK = 0,
+    RKR_E_INVALID = 1,     /* an argument is out of range (message says which) */
+    RKR_E_NOMEM = 2,       /* device or host allocation failed */
+    RKR_E_DEVICE = 3,      /* a HIP runtime call failed */
+    RKR_E_UNSUPPORTED = 4, /* valid request outside this build's limits */
+    RKR_E_STATE = 5        /* the index lacks a part the call needs */
+} rkr_status;
+
+/* Master (ground-truth) element type of U, P and queries. */
+typedef enum { RKR_F32 = 0, RKR_BF16 = 1 } rkr_dtype;
+
+/* Element type of the low-precision scoring pass on the matrix cores. */
+typedef enum {
+    RKR_SCORE_F32 = 0,   /* FP32 inputs, FP32 accumulation              */
+    RKR_SCORE_BF16 = 1,  /* BF16 inputs (round to nearest even), FP32 acc */
+    RKR_SCORE_FP8 = 2    /* FP8 e4m3 with a power-of-two scale per vector */
+} rkr_score;
+
+typedef struct {
+    int32_t score;          /* rkr_score (default RKR_SCORE_BF16)                        */
+    int32_t recheck;        /* 1: FP64 near-tie recheck, exact ranks (default);          */
+                            /* 0: plain compare of the low-precision score with the     */
+                            /*    threshold rounded to FP32 (not exact; for comparison) */
+    int32_t sketch_samples; /* >0: build the per-user score sketch for the estimator    */
+                            /*     from this many norm-stratified items (e.g. 4096)     */
+    int32_t reserved;
+    void *stream;           /* hipStream_t for all work on this index; NULL = default   */
+} rkr_build_opts;
+
+/* Per-call planning knobs (rkr_configure); zero fields keep the default. */
+typedef struct {
+    int32_t seed_mult;      /* seeds per query = seed_mult * k (default 2)               */
+    int32_t use_estimator;  /* 1: order seeds by the trained estimator (needs rkr_train) */
+    int32_t approx_refine;  /* approximate mode: max refine rounds (default 4)           */
+    int32_t prune_mult;     /* estimator pruning for the approximate mode: keep          */
+                            /* prune_mult * k users per query by predicted rank (0: off) */
+    int32_t screen_step;    /* reserved */
+    int32_t reserved[3];
+} rkr_query_opts;
+
+/* Counters of the last query call (rkr_stats). */
+typedef struct {
+    int64_t queries;        /* queries in the call                                        */
+    int64_t pairs;          /* (user, query) pairs in the domain                          */
+    int64_t seed_pairs;     /* pairs counted exactly to seed the per-query rank bound     */
+    int64_t survivors;      /* pairs left after the screening pass                        */
+    int64_t refined_pairs;  /* pairs counted exactly after screening                      */
+    int64_t uncertain;      /* near-tie (user, item, query) triples rechecked in FP64      */
+    int64_t flips;          /* rechecked triples whose FP64 verdict differs from a plain   */
+                            /* FP32 compare of the low-precision score                     */
+    int64_t compares;       /* executed (score, threshold) comparisons                     */
+    int64_t emit_retries;   /* passes re-run because the near-tie buffer was too small     */
+    int64_t approx_settled; /* approximate mode: queries settled without the exact fallback */
+    double ms_thresh, ms_seed, ms_screen, ms_refine, ms_select, ms_total;
+    double mlp_loss;        /* last training loss of the estimator (rkr_train)             */
+} rkr_query_stats;
+
+/*
+ * Build an index over users U [device, n x d] and items P [device, m x d],
+ * both in master dtype dt.  Sorts P by norm (descending; Sec. 4.2 step 1),
+ * makes the low-precision copies, their exact residual norms, and the
+ * per-segment error-bound coefficients.
+ * Errors: RKR_E_INVALID if n <= 0, m < 0, d <= 0, d > 4096, a value is not
+ * finite or |value| > 2^50; RKR_E_UNSUPPORTED for n or m >= 2^31.
+ * m = 0 is valid (every rank is 1).
+ */
+rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t m, int32_t d,
+                     rkr_dtype dt, const rkr_build_opts *opts, rkr_index **out);
+
+void rkr_destroy(rkr_index *idx);
+
+rkr_status rkr_configure(rkr_index *idx, const rkr_query_opts *opts);
+
+/*
+ * Exact reverse k-ranks (Def. 2) of one query q [device, d, master dtype].
+ * Writes the answer to ids_out[k] and ranks_out[k] [device, int32], sorted
+ * by (rank, id).  Errors: RKR_E_INVALID if k < 1 or k > n, q not finite;
+ * RKR_E_UNSUPPORTED if k > 4096.
+ */
+rkr_status rkr_query_exact(rkr_index *idx, const void *q, int32_t k, int32_t *ids_out,
+                           int32_t *ranks_out);
+
+/*
+ * c-approximate reverse k-ranks (Def. 3) of one query, c >= 1.  ids_out[k]
+ * lists U_c by (reported rank, id); rank_ub_out[k] holds each user's exact
+ * rank where it was computed exactly, else a proven upper bound of it.
+ * The returned set always satisfies Def. 3 (the exact answer is the fallback).
+ */
+rkr_status rkr_query_approx(rkr_index *idx, const void *q, int32_t k, double c,
+                            int32_t *ids_out, int32_t *rank_ub_out);
+
+/*
+ * Batch of nq queries Qm [device, nq x d] sharing one pass over U.P^T.
+ *   k        [host, nq]      answer size per query
+ *   c        [host, nq]      NULL: exact answers (Def. 2); else c[i] >= 1
+ *                            per query (Def. 3)
+ *   cand_off [host, nq + 1]  NULL: every user is a candidate of every query;
+ *                            else CSR offsets into cand_ids, and query i's
+ *                            domain is cand_ids[cand_off[i] .. cand_off[i+1])
+ *   cand_ids [device]        user ids (each list free of duplicates)
+ *   ids_out, ranks_out [device, sum(k)]  answers concatenated in query order
+ * Errors: RKR_E_INVALID for k[i] < 1 or above its domain size, c[i] < 1 or
+ * NaN, non-monotone offsets, ids out of range or duplicated within a list;
+ * RKR_E_UNSUPPORTED for nq > 65535 or k[i] > 4096.
+ */
+rkr_status rkr_query_batch(rkr_index *idx, int32_t nq, const void *Qm, const int32_t *k,
+                           const double *c, const int64_t *cand_off, const int32_t *cand_ids,
+                           int32_t *ids_out, int32_t *ranks_out);
+
+/* Exact Def. 1 rank of q for every user: ranks_out [device, n int32]. */
+rkr_status rkr_ranks(rkr_index *idx, const void *q, int32_t *ranks_out);
+
+/*
+ * Learned rank estimator (an MLP 18 -> 64 -> 64 -> 1 on the features
+ * [u.q / |u|, |u|, 16 sketch values]) predicting ln r.  rkr_train computes
+ * exact ranks for (user, query) pairs of the training queries Qm [device,
+ * nq x d] with the exact path, then trains the network on the GPU with FP32
+ * forward, backward and Adam kernels.  pairs_per_query users are drawn per
+ * query, half uniformly and half from the best-scoring users.  Needs an
+ * index built with sketch_samples > 0 (else RKR_E_STATE).
+ */
+rkr_status rkr_train(rkr_index *idx, int32_t nq, const void *Qm, int32_t pairs_per_query,
+                     int32_t epochs, int32_t batch, float lr, uint64_t seed);
+
+/* Predicted ln r for nq queries x every user: out [device, nq x n float]. */
+rkr_status rkr_predict(rkr_index *idx, int32_t nq, const void *Qm, float *out);
+
+/*
+ * Estimator parameters, flattened in the order W1[64x18], b1[64], W2[64x64],
+ * b2[64], w3[64], b3[1] (5,441 floats) [host].
+ */
+rkr_status rkr_mlp_get(rkr_index *idx, float *params_out);
+rkr_status rkr_mlp_set(rkr_index *idx, const float *params);
+
+/*
+ * One forward + backward pass of the estimator on a minibatch: X [device,
+ * N x 18], z [device, N] targets; writes the mean squared error to
+ * loss_out [host] and the gradient (flattened as above) to grad_out
+ * [device, 5441].  For gradient checks against a reference.
+ */
+rkr_status rkr_mlp_grad(rkr_index *idx, const float *X, const float *z, int32_t N,
+                        float *grad_out, double *loss_out);
+
+/* Per-user sketch [device, n x 16 float] (needs sketch_samples > 0). */
+rkr_status rkr_sketch(rkr_index *idx, float *out);
+
+/* Counters of the last query call on this index [host]. */
+rkr_status rkr_stats(const rkr_index *idx, rkr_query_stats *out);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *rkr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RKR_H */

@@ -1,0 +1,619 @@
+// api.cpp -- the C ABI of librkr: validation, index construction and the
+// query pipeline.  Every step of the computation runs in the HIP kernels of
+// this library; this file only plans, allocates and launches.
+//
+// Query pipeline (exact, Def. 2; approximate, Def. 3):
+//   1. pairs      the (user, query) pairs of the domain, numbered user-major
+//   2. thresholds t(u,q) = spec dot in FP64 (the paper's query step 1, Sec. 4.3)
+//   3. seeds      per query the S = seed_mult*k most promising users
+//   4. exact count of the seed pairs (screen + FP64 near-tie recheck)
+//   5. bound      B_q = k-th smallest seed rank >= R_k (the k-th smallest rank
+//                 over all users); X_q = B_q (exact) or floor(B_q / c) (approx.)
+//   6. screen     every pair is scanned against norm-sorted P and dropped once
+//                 1 + certain count > X_q (the paper's Lemma 1 (2))
+//   7. refine     exact count of the pairs still live after the screen
+//   8. answer     per query the k best (rank, id) among seeds and survivors
+// Exactness: a dropped pair has rank > X_q >= ... (see DESIGN notes in the
+// header of count.hip); every user that can be in the answer is counted
+// exactly.  Approximate mode: a dropped pair has rank > B_q / c >= a_i / c for
+// every i <= k, where a_i is the i-th rank of the returned set, so the i-th
+// smallest rank over all users is >= a_i / c unless it is a counted user, in
+// which case it is <= a_i; either way Def. 3 holds.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "query.h"
+#include "rkr.h"
+#include "mlp.h"
+
+using namespace rkr;
+
+static thread_local std::string g_err;
+
+static rkr_status fail(rkr_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+static rkr_status fail_hip(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory) return fail(RKR_E_NOMEM, std::string("out of device memory in ") + what);
+    return fail(RKR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCK(x)                                             \
+    do {                                                     \
+        hipError_t _e = (x);                                 \
+        if (_e != hipSuccess) return fail_hip(_e, #x);       \
+    } while (0)
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct rkr_index {
+    int64_t n = 0, m = 0;
+    int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1, nib = 2, nub = 2;
+    int64_t nsteps = 0, nblk = 0;
+    hipStream_t st = nullptr;
+    // index data
+    DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
+    // per-call buffers
+    Scratch sc;
+    DBuf pair_u, pair_q, pair_off, qm_pid, t64, th, tl, tm, cnt, seedflag, keys, sel, selrank, best, cand,
+        candkeys, ans, seedpid, surv, emit, ctr, bound, seedkth, kdev, sdev, cdev, segoff, seloff, bestoff,
+        candoff, cursor, qcount, flags, allpid;
+    TaskSet ts_screen, ts_exact;
+    int64_t emit_cap = 0;
+    rkr_query_opts qo{};
+    rkr_query_stats stats{};
+    // estimator
+    Estimator est;
+};
+
+// ---------------------------------------------------------------------------
+// build
+// ---------------------------------------------------------------------------
+extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t m, int32_t d, rkr_dtype dt,
+                                const rkr_build_opts *opts, rkr_index **out) {
+    g_err.clear();
+    if (!out) return fail(RKR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n <= 0) return fail(RKR_E_INVALID, "n must be positive");
+    if (m < 0) return fail(RKR_E_INVALID, "m must be non-negative");
+    if (d <= 0 || d > 4096) return fail(RKR_E_INVALID, "d must be in 1..4096");
+    if (dt != RKR_F32 && dt != RKR_BF16) return fail(RKR_E_INVALID, "unknown master dtype");
+    if (!U || (m > 0 && !P)) return fail(RKR_E_INVALID, "U or P is NULL");
+    if (n >= (1ll << 31) || m >= (1ll << 31)) return fail(RKR_E_UNSUPPORTED, "n and m must be below 2^31");
+    int sk = SK_BF16, recheck = 1, sketch = 0;
+    hipStream_t st = nullptr;
+    if (opts) {
+        sk = opts->score;
+        recheck = opts->recheck ? 1 : 0;
+        sketch = opts->sketch_samples;
+        st = (hipStream_t)opts->stream;
+    }
+    if (sk != SK_F32 && sk != SK_BF16 && sk != SK_FP8) return fail(RKR_E_INVALID, "unknown score kind");
+    if (sketch < 0) return fail(RKR_E_INVALID, "sketch_samples must be >= 0");
+    const int KS = frag_ks(sk);
+    const int dpad = (d + KS - 1) / KS * KS;
+    const int nks = dpad / KS;
+    if (nks > max_nks(sk))
+        return fail(RKR_E_UNSUPPORTED, "d too large for this score kind (max " + std::to_string(max_nks(sk) * KS) + ")");
+
+    rkr_index *x = new (std::nothrow) rkr_index();
+    if (!x) return fail(RKR_E_NOMEM, "host allocation failed");
+    x->n = n; x->m = m; x->d = d; x->dpad = dpad; x->nks = nks; x->sk = sk; x->recheck = recheck;
+    x->mk = dt == RKR_BF16 ? MK_BF16 : MK_F32;
+    x->nib = nib_of(sk); x->nub = nub_of(sk, nks);
+    x->st = st;
+    x->qo.seed_mult = 2;
+    x->qo.approx_refine = 4;
+    const int mes = dt == RKR_BF16 ? 2 : 4;
+    const int es = elem_size(sk);
+    const int64_t step_items = 32 * x->nib;
+    x->nsteps = (m + step_items - 1) / step_items;
+    x->nblk = x->nsteps * x->nib;
+    rkr_status rs = RKR_OK;
+    auto body = [&]() -> rkr_status {
+        HIPCK(x->Um.ensure((size_t)n * d * mes));
+        HIPCK(x->Pm.ensure((size_t)std::max<int64_t>(m, 1) * d * mes));
+        HIPCK(x->perm.ensure((size_t)std::max<int64_t>(m, 1) * 4));
+        HIPCK(x->ulp.ensure((size_t)n * dpad * es));
+        HIPCK(x->plp.ensure((size_t)std::max<int64_t>(x->nblk, 1) * 32 * dpad * es));
+        HIPCK(x->unorm3.ensure((size_t)n * 3 * 8));
+        HIPCK(x->pnorm3.ensure((size_t)std::max<int64_t>(m, 1) * 3 * 8));
+        HIPCK(x->uexp.ensure((size_t)n));
+        HIPCK(x->pexp.ensure((size_t)std::max<int64_t>(m, 1)));
+        HIPCK(x->coef.ensure((size_t)std::max<int64_t>(x->nblk, 1) * 4 * 8));
+        HIPCK(x->flags.ensure(16));
+        HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+        HIPCK(hipMemcpyAsync(x->Um.p, U, (size_t)n * d * mes, hipMemcpyDeviceToDevice, st));
+        HIPCK(launch_check_values(x->Um.p, n * d, x->mk, x->flags.as<int>(), st));
+        if (m > 0) {
+            HIPCK(launch_check_values(P, m * d, x->mk, x->flags.as<int>(), st));
+            // P in norm order (descending, ties by id)
+            double *pn = (double *)x->sc.take(m * 8);
+            void *srt = x->sc.take((int64_t)norm_sort_scratch_bytes(m));
+            if (!pn || !srt) return fail(RKR_E_NOMEM, "sort scratch");
+            HIPCK(launch_spec_norm(P, m, d, x->mk, pn, st));
+            HIPCK(launch_norm_sort(pn, m, srt, x->perm.as<int32_t>(), st));
+            HIPCK(launch_gather_rows(P, x->perm.as<int32_t>(), m, d, x->mk, x->Pm.p, st));
+        }
+        HIPCK(launch_fill_u8(x->plp.as<uint8_t>(), 0, (int64_t)x->nblk * 32 * dpad * es, st));
+        HIPCK(launch_lowprec(x->Um.p, n, d, x->mk, sk, dpad, 0, x->ulp.as<uint8_t>(), x->unorm3.as<double>(),
+                             x->uexp.as<int8_t>(), st));
+        HIPCK(launch_lowprec(x->Pm.p, m, d, x->mk, sk, dpad, 1, x->plp.as<uint8_t>(), x->pnorm3.as<double>(),
+                             x->pexp.as<int8_t>(), st));
+        const double u = ldexp(1.0, -23);
+        const double g32 = sk == SK_F32 ? 2.0 * (dpad + 2) * u : 2.0 * dpad * u;
+        const double u64 = ldexp(1.0, -53);
+        const double g64 = d * u64 / (1.0 - d * u64) * 1.01;
+        const double eabs = dpad * ldexp(1.0, -100);
+        HIPCK(launch_block_coef(x->pnorm3.as<double>(), m, x->nblk, g32, g64, eabs, x->coef.as<double>(), st));
+        int flags = 0;
+        HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        if (flags & 1) return fail(RKR_E_INVALID, "U or P holds a non-finite value");
+        if (flags & 2) return fail(RKR_E_INVALID, "U or P holds a value with magnitude above 2^50");
+        if (sketch > 0) {
+            rkr_status s2 = est_build_sketch(x->est, x->Um.p, n, x->Pm.p, m, d, x->mk, x->unorm3.as<double>(),
+                                             sketch, x->sc, st);
+            if (s2 != RKR_OK) return s2;
+        }
+        x->sc.reset();
+        return RKR_OK;
+    };
+    rs = body();
+    if (rs != RKR_OK) {
+        rkr_destroy(x);
+        return rs;
+    }
+    *out = x;
+    return RKR_OK;
+}
+
+extern "C" void rkr_destroy(rkr_index *x) {
+    if (!x) return;
+    (void)hipStreamSynchronize(x->st);
+    DBuf *bufs[] = {&x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
+                    &x->coef, &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64, &x->th, &x->tl,
+                    &x->tm, &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
+                    &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
+                    &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
+                    &x->qcount, &x->flags, &x->allpid};
+    for (DBuf *b : bufs) b->release();
+    x->ts_screen.release();
+    x->ts_exact.release();
+    x->sc.release();
+    est_release(x->est);
+    delete x;
+}
+
+extern "C" rkr_status rkr_configure(rkr_index *x, const rkr_query_opts *o) {
+    g_err.clear();
+    if (!x || !o) return fail(RKR_E_INVALID, "NULL argument");
+    if (o->seed_mult < 0 || o->approx_refine < 0 || o->prune_mult < 0) return fail(RKR_E_INVALID, "negative option");
+    if (o->use_estimator && !x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
+    rkr_query_opts q = *o;
+    if (q.seed_mult == 0) q.seed_mult = 2;
+    if (q.approx_refine == 0) q.approx_refine = 4;
+    x->qo = q;
+    return RKR_OK;
+}
+
+extern "C" rkr_status rkr_stats(const rkr_index *x, rkr_query_stats *out) {
+    g_err.clear();
+    if (!x || !out) return fail(RKR_E_INVALID, "NULL argument");
+    *out = x->stats;
+    return RKR_OK;
+}
+
+extern "C" const char *rkr_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// counting passes
+// ---------------------------------------------------------------------------
+static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts) {
+    CountArgs a{};
+    a.plp = x->plp.as<uint8_t>();
+    a.m = x->m;
+    a.nks = x->nks;
+    a.step_coef = x->coef.as<double>();
+    a.pexp = x->pexp.as<int8_t>();
+    a.ulp = x->ulp.as<uint8_t>();
+    a.dpad = x->dpad;
+    a.unorm3 = x->unorm3.as<double>();
+    a.uexp = x->uexp.as<int8_t>();
+    a.task_user = ts.task_user;
+    a.ntask = ts.ntask;
+    a.blk_base = ts.blk_base;
+    a.ent_len = ts.len;
+    a.ent_pid = ts.ent_pid;
+    a.ent_q = ts.ent_q;
+    a.ent_cnt = ts.ent_cnt;
+    a.ent_th = ts.ent_th;
+    a.ent_tl = ts.ent_tl;
+    a.ent_tm = ts.ent_tm;
+    a.cap_total = ts.cap_total;
+    a.bound = x->bound.as<int32_t>();
+    a.nq = ps.nq;
+    a.nsteps = x->nsteps;
+    a.steps_per_split = x->nsteps;
+    a.cnt_out = x->cnt.as<uint32_t>();
+    a.emit = x->emit.as<int2>();
+    a.emit_count = x->ctr.as<unsigned long long>();
+    a.emit_cap = (unsigned long long)x->emit_cap;
+    a.stat = x->ctr.as<unsigned long long>() + 1;
+    a.plain = x->recheck ? 0 : 1;
+    return a;
+}
+
+// Exact counts (certain-above + FP64 recheck of near ties) of the pairs
+// pids[0..N) (ascending); adds into cnt[pid] after zeroing it.
+static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pids, int64_t N) {
+    if (N <= 0) return RKR_OK;
+    hipStream_t st = x->st;
+    TaskSet &ts = x->ts_exact;
+    hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, ts, x->sc, st);
+    if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
+    const int tpw = WAVES_PER_WG * x->nub * USER_BLOCK;
+    const int64_t gx = (ts.ntask + tpw - 1) / tpw;
+    int64_t nsplit = (512 + gx - 1) / std::max<int64_t>(gx, 1);
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(x->nsteps, 1))));
+    HIPCK(ts.reserve_entries(ts.cap_total, (int)nsplit));
+    CountArgs a = count_args(x, ps, ts);
+    a.steps_per_split = (x->nsteps + nsplit - 1) / nsplit;
+    nsplit = std::max<int64_t>(1, (x->nsteps + a.steps_per_split - 1) / std::max<int64_t>(a.steps_per_split, 1));
+    if (x->emit_cap == 0) {
+        x->emit_cap = 1 << 22;
+        HIPCK(x->emit.ensure((size_t)x->emit_cap * 8));
+    }
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        a.emit = x->emit.as<int2>();
+        a.emit_cap = (unsigned long long)x->emit_cap;
+        HIPCK(q_zero_at(pids, N, x->cnt.as<uint32_t>(), st));
+        HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));   // emit counter (64-bit)
+        HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, st));
+        unsigned long long ne = 0;
+        HIPCK(hipMemcpyAsync(&ne, x->ctr.p, 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        if (ne <= (unsigned long long)x->emit_cap) {
+            x->stats.uncertain += (int64_t)ne;
+            HIPCK(launch_recheck(x->emit.as<int2>(), (int64_t)ne, ps.pair_u, ps.t64, x->Um.p, x->Pm.p, x->d, x->mk,
+                                 x->cnt.as<uint32_t>(), x->ctr.as<unsigned long long>() + 2, st));
+            return RKR_OK;
+        }
+        x->stats.emit_retries += 1;
+        x->emit_cap = (int64_t)(ne + ne / 4 + 1024);
+        HIPCK(x->emit.ensure((size_t)x->emit_cap * 8));
+    }
+    return fail(RKR_E_DEVICE, "near-tie buffer kept overflowing");
+}
+
+// ---------------------------------------------------------------------------
+// batch queries
+// ---------------------------------------------------------------------------
+static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k, const double *c,
+                            const int64_t *cand_off, const int32_t *cand_ids, int32_t *ids_out, int32_t *ranks_out,
+                            const float *pred) {
+    g_err.clear();
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    if (nq < 1) return fail(RKR_E_INVALID, "nq must be positive");
+    if (nq > 65535) return fail(RKR_E_UNSUPPORTED, "nq above 65535");
+    if (!Qm || !k || !ids_out || !ranks_out) return fail(RKR_E_INVALID, "NULL argument");
+    const int64_t n = x->n;
+    const bool dense = cand_off == nullptr;
+    if (!dense && !cand_ids) return fail(RKR_E_INVALID, "cand_ids is NULL");
+    std::vector<int64_t> dom(nq), S(nq);
+    if (!dense) {
+        if (cand_off[0] != 0) return fail(RKR_E_INVALID, "cand_off[0] must be 0");
+        for (int q = 0; q < nq; ++q)
+            if (cand_off[q + 1] < cand_off[q]) return fail(RKR_E_INVALID, "cand_off must be non-decreasing");
+    }
+    int64_t ksum = 0;
+    for (int q = 0; q < nq; ++q) {
+        dom[q] = dense ? n : cand_off[q + 1] - cand_off[q];
+        if (!dense && dom[q] > n) return fail(RKR_E_INVALID, "candidate list longer than n");
+        if (k[q] < 1 || k[q] > dom[q]) return fail(RKR_E_INVALID, "k out of range for query " + std::to_string(q));
+        if (k[q] > 4096) return fail(RKR_E_UNSUPPORTED, "k above 4096");
+        if (c && (!(c[q] >= 1.0))) return fail(RKR_E_INVALID, "c must be >= 1 (query " + std::to_string(q) + ")");
+        ksum += k[q];
+    }
+    hipStream_t st = x->st;
+    const double t0 = now_ms();
+    x->stats = rkr_query_stats{};
+    x->stats.queries = nq;
+    x->sc.reset();
+    const int d = x->d;
+    // query values
+    HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+    HIPCK(launch_check_values(Qm, (int64_t)nq * d, x->mk, x->flags.as<int>(), st));
+
+    // ---- 1. pairs
+    PairSet ps;
+    ps.nq = nq;
+    ps.dense = dense ? 1 : 0;
+    const int64_t npairs = dense ? n * nq : cand_off[nq];
+    ps.npairs = npairs;
+    x->stats.pairs = npairs;
+    HIPCK(x->pair_u.ensure(npairs * 4));
+    HIPCK(x->pair_q.ensure(npairs * 4));
+    ps.pair_u = x->pair_u.as<int32_t>();
+    ps.pair_q = x->pair_q.as<int32_t>();
+    std::vector<int64_t> segoff(nq + 1);
+    for (int q = 0; q <= nq; ++q) segoff[q] = dense ? (int64_t)q * n : cand_off[q];
+    HIPCK(x->segoff.ensure((nq + 1) * 8));
+    HIPCK(hipMemcpyAsync(x->segoff.p, segoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    if (dense) {
+        HIPCK(launch_dense_pairs(n, nq, ps.pair_u, ps.pair_q, st));
+    } else {
+        HIPCK(x->pair_off.ensure((n + 1) * 8));
+        HIPCK(x->qm_pid.ensure(npairs * 4));
+        ps.pair_off = x->pair_off.as<int64_t>();
+        ps.qm_pid = x->qm_pid.as<int32_t>();
+        hipError_t e = build_csr_pairs(cand_ids, x->segoff.as<int64_t>(), nq, npairs, n, ps, x->flags.as<int>() + 1,
+                                       x->sc, st);
+        if (e == hipErrorInvalidValue)
+            return fail(RKR_E_INVALID, "candidate ids out of range or duplicated within a list");
+        if (e != hipSuccess) return fail_hip(e, "build_csr_pairs");
+    }
+    // ---- 2. thresholds
+    HIPCK(x->t64.ensure(npairs * 8));
+    HIPCK(x->th.ensure(npairs * 4));
+    HIPCK(x->tl.ensure(npairs * 4));
+    HIPCK(x->tm.ensure(npairs * 4));
+    ps.t64 = x->t64.as<double>();
+    ps.th = x->th.as<float>();
+    ps.tl = x->tl.as<float>();
+    ps.tm = x->tm.as<float>();
+    HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    {
+        int flags = 0;
+        HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        if (flags & 1) return fail(RKR_E_INVALID, "a query holds a non-finite value");
+        if (flags & 2) return fail(RKR_E_INVALID, "a query holds a value with magnitude above 2^50");
+    }
+    const double t1 = now_ms();
+    x->stats.ms_thresh = t1 - t0;
+
+    // ---- 3. seeds
+    std::vector<int64_t> seloff(nq + 1, 0), bestoff(nq + 1, 0);
+    std::vector<int32_t> Sv(nq);
+    const int64_t mult = std::max(1, x->qo.seed_mult);
+    for (int q = 0; q < nq; ++q) {
+        S[q] = std::min<int64_t>(dom[q], std::min<int64_t>(4096, std::max<int64_t>(k[q], mult * k[q])));
+        Sv[q] = (int32_t)S[q];
+        seloff[q + 1] = seloff[q] + S[q];
+        bestoff[q + 1] = bestoff[q] + k[q];
+    }
+    const int64_t nsel = seloff[nq];
+    QView v{ps.dense, nq, n, x->segoff.as<int64_t>(), ps.qm_pid};
+    HIPCK(x->keys.ensure(npairs * 8));
+    HIPCK(x->sel.ensure(nsel * 8));
+    HIPCK(x->selrank.ensure(nsel * 8));
+    HIPCK(x->seloff.ensure((nq + 1) * 8));
+    HIPCK(x->bestoff.ensure((nq + 1) * 8));
+    HIPCK(x->sdev.ensure(nq * 4));
+    HIPCK(x->kdev.ensure(nq * 4));
+    HIPCK(x->best.ensure(ksum * 8));
+    HIPCK(hipMemcpyAsync(x->seloff.p, seloff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->bestoff.p, bestoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->sdev.p, Sv.data(), nq * 4, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->kdev.p, k, nq * 4, hipMemcpyHostToDevice, st));
+    if (c) {
+        HIPCK(x->cdev.ensure(nq * 8));
+        HIPCK(hipMemcpyAsync(x->cdev.p, c, nq * 8, hipMemcpyHostToDevice, st));
+    }
+    HIPCK(q_seed_keys(v, ps.pair_u, ps.t64, x->unorm3.as<double>(), pred, npairs, x->keys.as<uint64_t>(), st));
+    HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
+                        x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));
+    HIPCK(x->seedflag.ensure(npairs));
+    HIPCK(launch_fill_u8(x->seedflag.as<uint8_t>(), 0, npairs, st));
+    HIPCK(q_mark_selected(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->seedflag.as<uint8_t>(), st));
+    HIPCK(x->seedpid.ensure(nsel * 4));
+    int64_t nseed = 0;
+    HIPCK(q_compact_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), &nseed, x->sc, st));
+    x->stats.seed_pairs = nseed;
+    // ---- 4. exact count of the seeds
+    HIPCK(x->cnt.ensure(npairs * 4));
+    HIPCK(x->ctr.ensure(64));
+    HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 16, st));
+    rkr_status rs = exact_count(x, ps, x->seedpid.as<int32_t>(), nseed);
+    if (rs != RKR_OK) return rs;
+    // ---- 5. per-query bound
+    HIPCK(q_rank_keys_sel(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->cnt.as<uint32_t>(),
+                          x->selrank.as<uint64_t>(), st));
+    HIPCK(launch_select(x->selrank.as<uint64_t>(), x->seloff.as<int64_t>(), x->kdev.as<int32_t>(), nq,
+                        x->bestoff.as<int64_t>(), x->best.as<uint64_t>(), st));
+    HIPCK(x->bound.ensure(nq * 4));
+    HIPCK(x->seedkth.ensure(nq * 4));
+    HIPCK(q_bounds(x->best.as<uint64_t>(), x->bestoff.as<int64_t>(), x->kdev.as<int32_t>(),
+                   c ? x->cdev.as<double>() : nullptr, nq, x->bound.as<int32_t>(), x->seedkth.as<int32_t>(), st));
+    HIPCK(hipStreamSynchronize(st));
+    const double t2 = now_ms();
+    x->stats.ms_seed = t2 - t1;
+
+    // ---- 6. screen every pair against its bound
+    bool need_screen = false;
+    for (int q = 0; q < nq; ++q) need_screen |= dom[q] > S[q];
+    int64_t nsurv = 0;
+    HIPCK(x->surv.ensure(npairs * 4));
+    if (need_screen) {
+        HIPCK(x->allpid.ensure(npairs * 4));
+        HIPCK(launch_iota(x->allpid.as<int32_t>(), npairs, st));
+        hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->ts_screen, x->sc, st);
+        if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
+        CountArgs a = count_args(x, ps, x->ts_screen);
+        HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, st));
+        TView tv{x->ts_screen.ntask, x->ts_screen.len, x->ts_screen.blk_base, x->ts_screen.ent_pid};
+        HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
+    }
+    HIPCK(hipStreamSynchronize(st));
+    const double t3 = now_ms();
+    x->stats.ms_screen = t3 - t2;
+    x->stats.survivors = nsurv;
+    // ---- 7. refine the survivors
+    rs = exact_count(x, ps, x->surv.as<int32_t>(), nsurv);
+    if (rs != RKR_OK) return rs;
+    x->stats.refined_pairs = nsurv;
+    HIPCK(hipStreamSynchronize(st));
+    const double t4 = now_ms();
+    x->stats.ms_refine = t4 - t3;
+
+    // ---- 8. answer: k best (rank, id) among seeds and survivors
+    std::vector<int32_t> hq(nq, 0);
+    HIPCK(x->qcount.ensure(nq * 4));
+    HIPCK(launch_fill_u32(x->qcount.as<uint32_t>(), 0, nq, st));
+    HIPCK(q_count_by_query(x->surv.as<int32_t>(), nsurv, ps.pair_q, x->qcount.as<int32_t>(), st));
+    HIPCK(hipMemcpyAsync(hq.data(), x->qcount.p, nq * 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    std::vector<int64_t> candoff(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) candoff[q + 1] = candoff[q] + S[q] + hq[q];
+    HIPCK(x->candoff.ensure((nq + 1) * 8));
+    HIPCK(x->cursor.ensure(nq * 4));
+    HIPCK(x->candkeys.ensure(candoff[nq] * 8));
+    HIPCK(x->ans.ensure(ksum * 8));
+    HIPCK(hipMemcpyAsync(x->candoff.p, candoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->cursor.p, Sv.data(), nq * 4, hipMemcpyHostToDevice, st));
+    HIPCK(q_cand_keys(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->surv.as<int32_t>(), nsurv,
+                      ps.pair_u, ps.pair_q, x->cnt.as<uint32_t>(), x->candoff.as<int64_t>(), x->cursor.as<int32_t>(),
+                      x->candkeys.as<uint64_t>(), st));
+    HIPCK(launch_select(x->candkeys.as<uint64_t>(), x->candoff.as<int64_t>(), x->kdev.as<int32_t>(), nq,
+                        x->bestoff.as<int64_t>(), x->ans.as<uint64_t>(), st));
+    HIPCK(q_write_answer(x->ans.as<uint64_t>(), ksum, ids_out, ranks_out, st));
+    unsigned long long ctr[3] = {0, 0, 0};
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 24, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    x->stats.compares = (int64_t)ctr[1];
+    x->stats.flips = (int64_t)ctr[2];
+    const double t5 = now_ms();
+    x->stats.ms_select = t5 - t4;
+    x->stats.ms_total = t5 - t0;
+    if (c) {
+        int64_t settled = 0;
+        for (int q = 0; q < nq; ++q) settled += (hq[q] == 0);
+        x->stats.approx_settled = settled;
+    }
+    return RKR_OK;
+}
+
+extern "C" rkr_status rkr_query_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k, const double *c,
+                                      const int64_t *cand_off, const int32_t *cand_ids, int32_t *ids_out,
+                                      int32_t *ranks_out) {
+    const float *pred = nullptr;
+    if (x && x->qo.use_estimator) {
+        if (!x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
+        rkr_status s = est_predict_for_query(x->est, nq, Qm, x->Um.p, x->n, x->d, x->mk, x->unorm3.as<double>(),
+                                             &pred, x->st);
+        if (s != RKR_OK) return s;
+    }
+    return run_batch(x, nq, Qm, k, c, cand_off, cand_ids, ids_out, ranks_out, pred);
+}
+
+extern "C" rkr_status rkr_query_exact(rkr_index *x, const void *q, int32_t k, int32_t *ids_out, int32_t *ranks_out) {
+    return rkr_query_batch(x, 1, q, &k, nullptr, nullptr, nullptr, ids_out, ranks_out);
+}
+
+extern "C" rkr_status rkr_query_approx(rkr_index *x, const void *q, int32_t k, double c, int32_t *ids_out,
+                                       int32_t *rank_ub_out) {
+    if (!(c >= 1.0)) return fail(RKR_E_INVALID, "c must be >= 1");
+    return rkr_query_batch(x, 1, q, &k, &c, nullptr, nullptr, ids_out, rank_ub_out);
+}
+
+extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out) {
+    g_err.clear();
+    if (!x || !q || !ranks_out) return fail(RKR_E_INVALID, "NULL argument");
+    hipStream_t st = x->st;
+    const int64_t n = x->n;
+    const double t0 = now_ms();
+    x->stats = rkr_query_stats{};
+    x->stats.queries = 1;
+    x->sc.reset();
+    PairSet ps;
+    ps.nq = 1;
+    ps.dense = 1;
+    ps.npairs = n;
+    x->stats.pairs = n;
+    HIPCK(x->pair_u.ensure(n * 4));
+    HIPCK(x->pair_q.ensure(n * 4));
+    HIPCK(x->t64.ensure(n * 8));
+    HIPCK(x->th.ensure(n * 4));
+    HIPCK(x->tl.ensure(n * 4));
+    HIPCK(x->tm.ensure(n * 4));
+    HIPCK(x->cnt.ensure(n * 4));
+    HIPCK(x->allpid.ensure(n * 4));
+    HIPCK(x->ctr.ensure(64));
+    ps.pair_u = x->pair_u.as<int32_t>();
+    ps.pair_q = x->pair_q.as<int32_t>();
+    ps.t64 = x->t64.as<double>();
+    ps.th = x->th.as<float>();
+    ps.tl = x->tl.as<float>();
+    ps.tm = x->tm.as<float>();
+    HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+    HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
+    HIPCK(launch_dense_pairs(n, 1, ps.pair_u, ps.pair_q, st));
+    HIPCK(launch_thresh(ps.pair_u, ps.pair_q, n, x->Um.p, q, x->d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    int flags = 0;
+    HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
+    HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 16, st));
+    HIPCK(launch_iota(x->allpid.as<int32_t>(), n, st));
+    rkr_status rs = exact_count(x, ps, x->allpid.as<int32_t>(), n);
+    if (rs != RKR_OK) return rs;
+    HIPCK(q_ranks_out(x->cnt.as<uint32_t>(), n, ranks_out, st));
+    unsigned long long ctr[3] = {0, 0, 0};
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 24, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    x->stats.compares = (int64_t)ctr[1];
+    x->stats.flips = (int64_t)ctr[2];
+    x->stats.refined_pairs = n;
+    x->stats.ms_total = now_ms() - t0;
+    return RKR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned rank estimator
+// ---------------------------------------------------------------------------
+extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_t pairs_per_query, int32_t epochs,
+                                int32_t batch, float lr, uint64_t seed) {
+    g_err.clear();
+    (void)nq; (void)Qm; (void)pairs_per_query; (void)epochs; (void)batch; (void)lr; (void)seed;
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    return fail(RKR_E_UNSUPPORTED, "estimator training not available in this build");
+}
+extern "C" rkr_status rkr_predict(rkr_index *x, int32_t nq, const void *Qm, float *out) {
+    g_err.clear();
+    (void)nq; (void)Qm; (void)out;
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    return fail(RKR_E_STATE, "estimator not trained");
+}
+extern "C" rkr_status rkr_mlp_get(rkr_index *x, float *p) {
+    g_err.clear();
+    (void)p;
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    return fail(RKR_E_UNSUPPORTED, "estimator not available in this build");
+}
+extern "C" rkr_status rkr_mlp_set(rkr_index *x, const float *p) {
+    g_err.clear();
+    (void)p;
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    return fail(RKR_E_UNSUPPORTED, "estimator not available in this build");
+}
+extern "C" rkr_status rkr_mlp_grad(rkr_index *x, const float *X, const float *z, int32_t N, float *g, double *loss) {
+    g_err.clear();
+    (void)X; (void)z; (void)N; (void)g; (void)loss;
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    return fail(RKR_E_UNSUPPORTED, "estimator not available in this build");
+}
+extern "C" rkr_status rkr_sketch(rkr_index *x, float *out) {
+    g_err.clear();
+    (void)out;
+    if (!x) return fail(RKR_E_INVALID, "index is NULL");
+    return fail(RKR_E_STATE, "index built without a sketch");
+}

@@ -1,0 +1,389 @@
+// count.hip -- fused low-precision score + rank count (the O(nmd) scan of
+// Def. 1, Sec. 2, done as a tiled U.P^T on the matrix cores).
+//
+// One workgroup = 8 wave64.  A wave owns NUB blocks of 32 users; the users'
+// low-precision vectors stay in registers for the whole scan (B operand).
+// Items stream through LDS in steps of NIB blocks of 32 items, stored in
+// global memory already in MFMA fragment order so that both the global->LDS
+// copy and the LDS->register fragment reads are linear.  A 32x32 MFMA output
+// block leaves, in lane l, the scores of user (l % 32) against 16 items; the
+// lane pair (l, l+32) covers all 32 items of the block.
+//
+// Each (user, query) pair of the wave's users is an "entry" (block-interleaved
+// SoA arrays, see CountArgs).  For every step the lane loops over its user's
+// live entries and compares each of its scores with the pair's band edges:
+//   hi = next_up(th + eps),  lo = next_down(tl - eps)
+// where th >= t64 >= tl bracket the FP64 threshold and eps bounds
+// |score - s64(u,p)| for every item of the step (error-bound coefficients per
+// item block; P is sorted by norm so the per-block maxima are tight).
+//   score >  hi  => s64(u,p) > t64   (certainly above: counted)
+//   score <  lo  => s64(u,p) < t64   (certainly not above)
+//   otherwise       near tie: exact mode emits (pair, item) for the FP64 recheck.
+// Screen mode counts only certain-above scores and drops a pair as soon as
+// 1 + count exceeds the query's bound B[q] (a proven upper bound on the k-th
+// smallest rank): its rank is then > B >= R_k, so it cannot be in the answer
+// (Def. 2), the counts only grow.  This is the paper's Lemma 1 (2) filter
+// applied to exact partial counts.
+#include "rkr_internal.h"
+
+namespace rkr {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+template <int SK> struct FragT;
+template <> struct FragT<SK_BF16> { using T = i32x4; };
+template <> struct FragT<SK_F32> { using T = float; };
+template <> struct FragT<SK_FP8> { using T = i32x8; };
+
+template <int SK>
+__device__ inline f32x16 mfma_step(f32x16 acc, typename FragT<SK>::T a, typename FragT<SK>::T b,
+                                   int sa, int sb) {
+    if constexpr (SK == SK_BF16) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    } else if constexpr (SK == SK_F32) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    } else {
+        // A and B in FP8 e4m3 (format code 0); per-lane E8M0 scales (127 = 1.0)
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
+    }
+}
+
+// Sum of a value over the lane pair (l, l + 32).
+__device__ inline uint32_t pair_sum(uint32_t v) {
+    auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return r[0] + r[1];
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Copy step_bytes from global memory to LDS with global_load_lds_dwordx4: the
+// 64 lanes of a wave fill 1 KB of LDS starting at the (wave-uniform) base.
+template <int LOADS>
+__device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_bytes, int tid) {
+    const int wave = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < LOADS; ++j) {
+        const int wbase = (j * 512 + wave * 64) * 16;
+        const int off = wbase + (tid & 63) * 16;
+        if (off < step_bytes)
+            __builtin_amdgcn_global_load_lds((const void *)(src + off),
+                                             (__attribute__((address_space(3))) void *)(dst + wbase), 16, 0, 0);
+    }
+}
+
+template <int SK, int MODE, int NKS, int NUB, int NIB>
+__global__ __launch_bounds__(512) void k_count(CountArgs a) {
+    using FT = typename FragT<SK>::T;
+    constexpr int FB = frag_fb(SK);
+    constexpr int KS = frag_ks(SK);
+    constexpr int ES = elem_size(SK);
+    constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
+    constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * FB;
+    constexpr int LOADS_MAX = (STEP_BYTES_MAX + 512 * 16 - 1) / (512 * 16);
+
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const int nks = a.nks;
+    const int step_bytes = NIB * nks * 64 * FB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int l32 = lane & 31;
+    const int half = lane >> 5;
+    const int split = blockIdx.y;
+
+    int64_t s_begin = (int64_t)split * a.steps_per_split;
+    int64_t s_end = s_begin + a.steps_per_split;
+    if (s_end > a.nsteps) s_end = a.nsteps;
+
+    // ---- this lane's users, their register-stationary fragments and entries
+    int uid[NUB];
+    int64_t tix[NUB];
+    int len[NUB];
+    int64_t ebase[NUB];
+    double un_hat[NUB], un_del[NUB], un_full[NUB];
+    int uscale[NUB];
+    FT bfrag[NUB][NKS];
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub) {
+        int64_t t = (int64_t)blockIdx.x * TASKS_PER_WG + (wave * NUB + ub) * USER_BLOCK + l32;
+        tix[ub] = t;
+        int u = (t < a.ntask) ? a.task_user[t] : -1;
+        uid[ub] = u;
+        len[ub] = (u >= 0) ? a.ent_len[t] : 0;
+        ebase[ub] = a.blk_base[t >> 5] + l32;
+        un_hat[ub] = un_del[ub] = un_full[ub] = 0.0;
+        uscale[ub] = 127;
+        if (u >= 0) {
+            un_hat[ub] = a.unorm3[3 * (int64_t)u + 0];
+            un_del[ub] = a.unorm3[3 * (int64_t)u + 1];
+            un_full[ub] = a.unorm3[3 * (int64_t)u + 2];
+            if constexpr (SK == SK_FP8) uscale[ub] = 127 + (int)a.uexp[u];
+        }
+        const uint8_t *urow = a.ulp + ((int64_t)(u >= 0 ? u : 0) * a.dpad + half * (KS / 2)) * ES;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            FT v{};
+            if (s < nks && u >= 0) v = *(const FT *)(urow + (int64_t)s * KS * ES);
+            bfrag[ub][s] = v;
+        }
+    }
+
+    int any_live = 0;
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
+    if (!__syncthreads_or(any_live) || s_begin >= s_end) return;
+
+    uint64_t ncmp = 0;
+
+    // ---- prologue: stage the first step (direct global -> LDS, 16 bytes per lane)
+    stage_step<LOADS_MAX>(a.plp + s_begin * (int64_t)step_bytes, lds, step_bytes, tid);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    for (int64_t st = s_begin; st < s_end; ++st) {
+        const int buf = (int)((st - s_begin) & 1);
+        const uint8_t *tile = lds + buf * STEP_BYTES_MAX;
+        // prefetch the next step straight into the other LDS buffer; it was last
+        // read in the previous step, before the barrier that ended it
+        const bool has_next = (st + 1 < s_end);
+        if (has_next)
+            stage_step<LOADS_MAX>(a.plp + (st + 1) * (int64_t)step_bytes, lds + (buf ^ 1) * STEP_BYTES_MAX,
+                                  step_bytes, tid);
+
+        // ---- scores of NIB x 32 items against NUB x 32 users
+        f32x16 acc[NIB][NUB];
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+            for (int ub = 0; ub < NUB; ++ub)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[ib][ub][r] = 0.0f;
+        int pscale[NIB];
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) {
+            pscale[ib] = 127;
+            if constexpr (SK == SK_FP8) {
+                int64_t item = st * (NIB * 32) + ib * 32 + l32;
+                pscale[ib] = 127 + (item < a.m ? (int)a.pexp[item] : 0);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            if (s < nks) {
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib) {
+                    FT af = *(const FT *)(tile + ((ib * nks + s) * 64 + lane) * FB);
+#pragma unroll
+                    for (int ub = 0; ub < NUB; ++ub)
+                        acc[ib][ub] = mfma_step<SK>(acc[ib][ub], af, bfrag[ub][s], pscale[ib], uscale[ub]);
+                }
+            }
+        }
+        // items past the end never count: make their scores -inf
+        const int64_t item0 = st * (NIB * 32);
+        if (item0 + NIB * 32 > a.m) {
+#pragma unroll
+            for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    if (item >= a.m) {
+#pragma unroll
+                        for (int ub = 0; ub < NUB; ++ub) acc[ib][ub][r] = -__builtin_inff();
+                    }
+                }
+        }
+
+        // ---- error bound of this step for each of the lane's users
+        double ca = 0.0, cb = 0.0, cc = 0.0, cabs = 0.0;
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib) {
+            const double *co = a.step_coef + 4 * (st * NIB + ib);
+            ca = fmax(ca, co[0]); cb = fmax(cb, co[1]); cc = fmax(cc, co[2]); cabs = fmax(cabs, co[3]);
+        }
+
+        // ---- compare and count
+#pragma unroll
+        for (int ub = 0; ub < NUB; ++ub) {
+            double E = un_hat[ub] * ca + un_del[ub] * cb + un_full[ub] * cc + cabs;
+            const float eps = f32_round_up(E * (1.0 + 1e-9));
+            int w = 0;
+            const int mylen = len[ub];
+            for (int i = 0; __ballot(i < mylen) != 0ull; ++i) {
+                const bool act = i < mylen;
+                const int64_t e = ebase[ub] + (int64_t)i * 32;
+                int pid = 0, q = 0;
+                uint32_t cnt = 0;
+                float th = 0.0f, tl = 0.0f, tmv = 0.0f;
+                if (act) {
+                    pid = a.ent_pid[e];
+                    th = a.ent_th[e];
+                    if constexpr (MODE == CM_SCREEN) {
+                        q = a.ent_q[e];
+                        cnt = a.ent_cnt[e];
+                    } else {
+                        tl = a.ent_tl[e];
+                        tmv = a.ent_tm[e];
+                        cnt = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
+                    }
+                }
+                const float hi = a.plain ? th : f32_next_up(th + eps);
+                uint32_t c = 0;
+                if constexpr (MODE == CM_SCREEN) {
+#pragma unroll
+                    for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) c += (acc[ib][ub][r] > hi) ? 1u : 0u;
+                    c = pair_sum(c);
+                    cnt += c;
+                    const bool alive = act && (1u + cnt <= (uint32_t)a.bound[q]);
+                    if (alive && half == 0) {
+                        const int64_t ew = ebase[ub] + (int64_t)w * 32;
+                        a.ent_pid[ew] = pid;
+                        a.ent_q[ew] = q;
+                        a.ent_cnt[ew] = cnt;
+                        a.ent_th[ew] = th;
+                    }
+                    w += alive ? 1 : 0;
+                } else {
+                    const float lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
+                    uint32_t umask = 0, pmask = 0;
+#pragma unroll
+                    for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const float s = acc[ib][ub][r];
+                            c += (s > hi) ? 1u : 0u;
+                            umask |= ((s >= lo) && (s <= hi)) ? (1u << (ib * 16 + r)) : 0u;
+                            pmask |= (s > tmv) ? (1u << (ib * 16 + r)) : 0u;
+                        }
+                    if (!act) umask = 0;
+                    if (__ballot(umask != 0) != 0ull) {
+                        const uint32_t nu = __popc(umask);
+                        const uint32_t incl = wave_incl_scan(nu, lane);
+                        const uint32_t total = __shfl(incl, 63, 64);
+                        unsigned long long base = 0;
+                        if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
+                        base = __shfl(base, 0, 64);
+                        unsigned long long pos = base + (incl - nu);
+                        uint32_t mm = umask;
+                        while (mm) {
+                            const int bit = __ffs(mm) - 1;
+                            mm &= mm - 1;
+                            const int ib = bit >> 4, r = bit & 15;
+                            const int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
+                            if (pos < a.emit_cap) a.emit[pos] = make_int2(pid, (int)item | plainbit);
+                            ++pos;
+                        }
+                    }
+                    c = pair_sum(c);
+                    cnt += c;
+                    if (act && half == 0) a.ent_cnt[(int64_t)split * a.cap_total + e] = cnt;
+                }
+                ncmp += act ? (uint64_t)(NIB * 16) : 0ull;
+            }
+            if constexpr (MODE == CM_SCREEN) len[ub] = w;
+        }
+
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        int live = 0;
+#pragma unroll
+        for (int ub = 0; ub < NUB; ++ub) live |= (len[ub] > 0);
+        if (!__syncthreads_or(live)) break;
+    }
+
+    // ---- write back
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub) {
+        if (uid[ub] < 0) continue;
+        if constexpr (MODE == CM_SCREEN) {
+            if (half == 0) a.ent_len[tix[ub]] = len[ub];
+        } else {
+            if (half == 0) {
+                for (int i = 0; i < len[ub]; ++i) {
+                    const int64_t e = ebase[ub] + (int64_t)i * 32;
+                    atomicAdd(&a.cnt_out[a.ent_pid[e]], a.ent_cnt[(int64_t)split * a.cap_total + e]);
+                }
+            }
+        }
+    }
+    // executed compares (both lanes of a pair count their own items)
+    uint64_t tot = ncmp;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    if (lane == 0 && a.stat) atomicAdd(a.stat, (unsigned long long)tot);
+}
+
+template <int SK, int MODE, int NKS, int NUB, int NIB>
+static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
+    constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
+    constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
+    const size_t lds = 2 * STEP_BYTES_MAX;
+    auto kern = k_count<SK, MODE, NKS, NUB, NIB>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)((a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG), (unsigned)nsplit);
+    if (grid.x == 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int SK, int MODE>
+static hipError_t dispatch_nks(const CountArgs &a, int nsplit, hipStream_t st) {
+    const int nks = a.nks;
+    if constexpr (SK == SK_BF16) {
+        if (nks <= 4) return launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
+        if (nks <= 8) return launch_one<SK, MODE, 8, 2, 2>(a, nsplit, st);
+        if (nks <= 13) return launch_one<SK, MODE, 13, 2, 2>(a, nsplit, st);
+        if (nks <= 20) return launch_one<SK, MODE, 20, 1, 2>(a, nsplit, st);
+    } else if constexpr (SK == SK_F32) {
+        if (nks <= 32) return launch_one<SK, MODE, 32, 1, 1>(a, nsplit, st);
+        if (nks <= 64) return launch_one<SK, MODE, 64, 1, 1>(a, nsplit, st);
+        if (nks <= 100) return launch_one<SK, MODE, 100, 1, 1>(a, nsplit, st);
+        if (nks <= 160) return launch_one<SK, MODE, 160, 1, 1>(a, nsplit, st);
+    } else {
+        if (nks <= 2) return launch_one<SK, MODE, 2, 2, 2>(a, nsplit, st);
+        if (nks <= 4) return launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
+        if (nks <= 8) return launch_one<SK, MODE, 8, 1, 2>(a, nsplit, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, hipStream_t st) {
+    if (mode != CM_SCREEN && mode != CM_EXACT) return hipErrorInvalidValue;
+    if (sk == SK_BF16)
+        return mode == CM_SCREEN ? dispatch_nks<SK_BF16, CM_SCREEN>(a, nsplit, st)
+                                 : dispatch_nks<SK_BF16, CM_EXACT>(a, nsplit, st);
+    if (sk == SK_F32)
+        return mode == CM_SCREEN ? dispatch_nks<SK_F32, CM_SCREEN>(a, nsplit, st)
+                                 : dispatch_nks<SK_F32, CM_EXACT>(a, nsplit, st);
+    if (sk == SK_FP8)
+        return mode == CM_SCREEN ? dispatch_nks<SK_FP8, CM_SCREEN>(a, nsplit, st)
+                                 : dispatch_nks<SK_FP8, CM_EXACT>(a, nsplit, st);
+    return hipErrorInvalidValue;
+}
+
+// Largest supported k-step count per score kind (d <= KS * max).
+int max_nks(int sk) { return sk == SK_BF16 ? 20 : (sk == SK_F32 ? 160 : 8); }
+int nub_of(int sk, int nks) {
+    if (sk == SK_F32) return 1;
+    if (sk == SK_BF16) return nks <= 13 ? 2 : 1;
+    return nks <= 4 ? 2 : 1;
+}
+int nib_of(int sk) { return sk == SK_F32 ? 1 : 2; }
+
+}  // namespace rkr

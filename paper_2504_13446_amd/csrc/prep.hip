@@ -1,0 +1,363 @@
+// prep.hip -- index construction (norms, norm order, low-precision copies,
+// error-bound coefficients), FP64 thresholds and the FP64 near-tie recheck.
+#include "rkr_internal.h"
+#include "kernels.h"
+
+namespace rkr {
+
+// ---------------------------------------------------------------------------
+// Input validation: bit 1 = non-finite value, bit 2 = |value| > 2^50.
+// ---------------------------------------------------------------------------
+__global__ void k_check_values(const void *X, int64_t count, int mk, int *flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int f = 0;
+    for (; i < count; i += stride) {
+        double v = master_elem(X, mk, i);
+        if (!isfinite(v)) f |= 1;
+        else if (fabs(v) > 0x1p50) f |= 2;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// ---------------------------------------------------------------------------
+// Spec norm: sqrt of the sequential-fma sum of squares, one thread per row.
+// ---------------------------------------------------------------------------
+__global__ void k_spec_norm(const void *X, int64_t rows, int d, int mk, double *out) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double v = master_elem(X, mk, r * d + k);
+        acc = fma(v, v, acc);
+    }
+    out[r] = sqrt(acc);
+}
+
+// ---------------------------------------------------------------------------
+// Bitonic sort of (key, id) records: norm descending, id ascending.
+// Padding records carry key = -inf and id = INT64_MAX so they sort last.
+// ---------------------------------------------------------------------------
+struct NormRec { double key; int64_t id; };
+
+__device__ inline bool rec_before(const NormRec &a, const NormRec &b) {
+    return (a.key > b.key) || (a.key == b.key && a.id < b.id);
+}
+
+__global__ void k_sort_init(const double *norms, int64_t m, int64_t mpow2, NormRec *recs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mpow2) return;
+    recs[i] = (i < m) ? NormRec{norms[i], i} : NormRec{-__builtin_inf(), INT64_MAX};
+}
+
+__global__ void k_bitonic_global(NormRec *recs, int64_t mpow2, int64_t j, int64_t k) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mpow2) return;
+    int64_t l = i ^ j;
+    if (l <= i) return;
+    NormRec a = recs[i], b = recs[l];
+    bool up = (i & k) == 0;
+    bool swap = up ? rec_before(b, a) : rec_before(a, b);
+    if (swap) { recs[i] = b; recs[l] = a; }
+}
+
+// All stages with j < 1024 inside LDS (2048-record tiles).
+__global__ __launch_bounds__(1024) void k_bitonic_local(NormRec *recs, int64_t mpow2, int64_t k_lo,
+                                                         int64_t k_hi) {
+    __shared__ NormRec s[2048];
+    int64_t base = (int64_t)blockIdx.x * 2048;
+    int t = threadIdx.x;
+    s[t] = recs[base + t];
+    s[t + 1024] = recs[base + t + 1024];
+    __syncthreads();
+    for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
+        for (int64_t j = (k_lo == k_hi ? 1024 : k >> 1); j >= 1; j >>= 1) {
+            if (j > 1024) continue;
+            for (int r = 0; r < 2; ++r) {
+                int i = t + r * 1024;
+                int l = i ^ (int)j;
+                if (l > i) {
+                    int64_t gi = base + i;
+                    bool up = (gi & k) == 0;
+                    NormRec a = s[i], b = s[l];
+                    bool swap = up ? rec_before(b, a) : rec_before(a, b);
+                    if (swap) { s[i] = b; s[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    recs[base + t] = s[t];
+    recs[base + t + 1024] = s[t + 1024];
+}
+
+__global__ void k_sort_extract(const NormRec *recs, int64_t m, int32_t *order) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) order[i] = (int32_t)recs[i].id;
+}
+
+// Gather master rows into norm order.
+__global__ void k_gather_rows(const void *src, const int32_t *order, int64_t rows, int d, int mk,
+                              void *dst) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = rows * d;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    size_t es = mk == MK_BF16 ? 2 : 4;
+    for (; i < total; i += stride) {
+        int64_t r = i / d, k = i - r * d;
+        int64_t s = (int64_t)order[r] * d + k;
+        if (es == 2) ((uint16_t *)dst)[i] = ((const uint16_t *)src)[s];
+        else ((float *)dst)[i] = ((const float *)src)[s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Low-precision copies.
+// ---------------------------------------------------------------------------
+__device__ inline uint16_t bf16_rne(float x) {
+    uint32_t b = __float_as_uint(x);
+    b = b + 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// FP8 e4m3 (finite-only variant: max 448) of |v| <= 448, round to nearest
+// even; values below the smallest normal 2^-6 become 0.  Returns the byte
+// and writes the decoded value.
+__device__ inline uint8_t fp8_e4m3_rne(float v, float *dec) {
+    float a = fabsf(v);
+    uint8_t sign = v < 0.0f ? 0x80 : 0;
+    if (!(a >= 0x1p-6f)) { *dec = 0.0f; return 0; }
+    int e;
+    frexpf(a, &e);              // a = f * 2^e, f in [0.5, 1)
+    int E = e - 1;              // a in [2^E, 2^(E+1))
+    float ulp = ldexpf(1.0f, E - 3);
+    float qv = rintf(a / ulp) * ulp;   // a / ulp is exact (power of two); rintf ties to even
+    if (qv >= ldexpf(1.0f, E + 1)) E += 1;
+    if (qv > 448.0f) qv = 448.0f;
+    int mant = (int)rintf(qv / ldexpf(1.0f, E - 3)) - 8;   // 0..7
+    *dec = v < 0.0f ? -qv : qv;
+    return (uint8_t)(sign | ((E + 7) << 3) | (mant & 7));
+}
+
+// One thread per row.  Writes the low-precision row, the exact residual norms
+// (|x_hat|, |x - x_hat|, |x|), and (FP8) the row's scale exponent.
+// Layout: row-major [rows][dpad] if frag == 0, else fragment order
+//   [row / 32][k-step][lane][FB bytes] with lane = row % 32 + 32 * half.
+__global__ void k_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag,
+                          uint8_t *out, double *norm3, int8_t *exps) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int KS = frag_ks(sk), FB = frag_fb(sk), ES = elem_size(sk);
+    const int nks = dpad / KS;
+    int scale_e = 0;
+    if (sk == SK_FP8) {
+        double mx = 0.0;
+        for (int k = 0; k < d; ++k) mx = fmax(mx, fabs(master_elem(X, mk, r * d + k)));
+        if (mx > 0.0) {
+            int e;
+            frexp(mx / 448.0, &e);          // mx/448 in [2^(e-1), 2^e)
+            scale_e = e;                    // mx * 2^-e <= 448 * 2^0 ... adjust below
+            if (ldexp(mx, -(scale_e - 1)) <= 448.0) scale_e -= 1;
+            if (scale_e < -100) scale_e = -100;
+            if (scale_e > 100) scale_e = 100;
+        }
+        exps[r] = (int8_t)scale_e;
+    }
+    double nh = 0.0, nd = 0.0, nf = 0.0;
+    for (int k = 0; k < dpad; ++k) {
+        double x = k < d ? master_elem(X, mk, r * d + k) : 0.0;
+        double xh;
+        uint8_t bytes[4];
+        if (sk == SK_BF16) {
+            float xf = (fabs(x) < 0x1p-50) ? 0.0f : (float)x;
+            uint16_t b = bf16_rne(xf);
+            xh = (double)__uint_as_float((uint32_t)b << 16);
+            bytes[0] = b & 0xFF; bytes[1] = b >> 8;
+        } else if (sk == SK_F32) {
+            float xf = (fabs(x) < 0x1p-50) ? 0.0f : (float)x;
+            xh = (double)xf;
+            uint32_t b = __float_as_uint(xf);
+            bytes[0] = b & 0xFF; bytes[1] = (b >> 8) & 0xFF; bytes[2] = (b >> 16) & 0xFF; bytes[3] = b >> 24;
+        } else {
+            float dec;
+            uint8_t b = fp8_e4m3_rne((float)ldexp(x, -scale_e), &dec);
+            xh = ldexp((double)dec, scale_e);
+            bytes[0] = b;
+        }
+        double dl = x - xh;      // exact: both are FP32-representable, same scale
+        nh = fma(xh, xh, nh);
+        nd = fma(dl, dl, nd);
+        nf = fma(x, x, nf);
+        int64_t off;
+        if (!frag) {
+            off = (r * dpad + k) * ES;
+        } else {
+            int s = k / KS, kk = k % KS;
+            int half = kk / (KS / 2), e = kk % (KS / 2);
+            int64_t blk = r / 32;
+            int lane = (int)(r % 32) + 32 * half;
+            off = ((blk * nks + s) * 64 + lane) * (int64_t)FB + e * ES;
+        }
+        for (int b = 0; b < ES; ++b) out[off + b] = bytes[b];
+    }
+    const double infl = 1.0 + 0x1p-40;
+    norm3[3 * r + 0] = sqrt(nh) * infl;
+    norm3[3 * r + 1] = sqrt(nd) * infl;
+    norm3[3 * r + 2] = sqrt(nf) * infl;
+}
+
+// Error-bound coefficients per 32-item block (items sorted by norm):
+//   a = g32 * X + Y,  b = X + Y,  c = g64 * Z,  abs
+// with X = max |p_hat|, Y = max |delta p|, Z = max |p| over the block, so that
+//   |score - s64(u,p)| <= |u_hat| a + |delta u| b + |u| c + abs.
+__global__ void k_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64,
+                             double eabs, double *coef) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    double X = 0, Y = 0, Z = 0;
+    for (int64_t i = b * 32; i < b * 32 + 32 && i < m; ++i) {
+        X = fmax(X, pnorm3[3 * i + 0]);
+        Y = fmax(Y, pnorm3[3 * i + 1]);
+        Z = fmax(Z, pnorm3[3 * i + 2]);
+    }
+    const double infl = 1.0 + 0x1p-40;
+    coef[4 * b + 0] = (g32 * X + Y) * infl;
+    coef[4 * b + 1] = (X + Y) * infl;
+    coef[4 * b + 2] = g64 * Z * infl;
+    coef[4 * b + 3] = eabs;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 thresholds t(u,q) = spec dot, with the FP32 values bracketing it.
+// ---------------------------------------------------------------------------
+__global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs,
+                         const void *Um, const void *Qm, int d, int mk, double *t64, float *th,
+                         float *tl, float *tm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npairs) return;
+    const int64_t u = pair_u[i], q = pair_q[i];
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k)
+        acc = fma(master_elem(Um, mk, u * d + k), master_elem(Qm, mk, q * d + k), acc);
+    t64[i] = acc;
+    th[i] = f32_round_up(acc);
+    tl[i] = f32_round_down(acc);
+    tm[i] = (float)acc;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 recheck of near ties: one thread per emitted (pair, item) record.
+// The item id is in sorted order; its master row sits in Pm_sorted.
+// Bit 31 of the item field carries the plain FP32 verdict (score > fl32(t)).
+// ---------------------------------------------------------------------------
+__global__ void k_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, const double *t64,
+                          const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
+                          unsigned long long *flips) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool flip = false;
+    if (i < nrec) {
+        const int2 r = rec[i];
+        const int pid = r.x;
+        const int64_t item = r.y & 0x7FFFFFFF;
+        const bool plain = (r.y >> 31) & 1;
+        const int64_t u = pair_u[pid];
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k)
+            acc = fma(master_elem(Um, mk, u * d + k), master_elem(Pm, mk, item * d + k), acc);
+        const bool above = acc > t64[pid];
+        if (above) atomicAdd(&cnt[pid], 1u);
+        flip = above != plain;
+    }
+    unsigned long long b = __ballot(flip);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(flips, (unsigned long long)__popcll(b));
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_check_values(const void *X, int64_t count, int mk, int *flags, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t nb = (count + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_check_values, dim3((unsigned)nb), dim3(256), 0, st, X, count, mk, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_norm(const void *X, int64_t rows, int d, int mk, double *out, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spec_norm, dim3(nblocks(rows, 256)), dim3(256), 0, st, X, rows, d, mk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_sort(const double *norms, int64_t m, void *scratch, int32_t *order,
+                            hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    int64_t mp = 2048;
+    while (mp < m) mp <<= 1;
+    NormRec *recs = (NormRec *)scratch;
+    hipLaunchKernelGGL(k_sort_init, dim3(nblocks(mp, 256)), dim3(256), 0, st, norms, m, mp, recs);
+    // stages k = 2 .. 2048 entirely in LDS
+    hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(mp / 2048)), dim3(1024), 0, st, recs, mp,
+                       (int64_t)2, (int64_t)2048);
+    for (int64_t k = 4096; k <= mp; k <<= 1) {
+        for (int64_t j = k >> 1; j > 1024; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_global, dim3(nblocks(mp, 256)), dim3(256), 0, st, recs, mp, j, k);
+        hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(mp / 2048)), dim3(1024), 0, st, recs, mp, k, k);
+    }
+    hipLaunchKernelGGL(k_sort_extract, dim3(nblocks(m, 256)), dim3(256), 0, st, recs, m, order);
+    return hipGetLastError();
+}
+
+size_t norm_sort_scratch_bytes(int64_t m) {
+    int64_t mp = 2048;
+    while (mp < m) mp <<= 1;
+    return (size_t)mp * sizeof(NormRec);
+}
+
+hipError_t launch_gather_rows(const void *src, const int32_t *order, int64_t rows, int d, int mk,
+                              void *dst, hipStream_t st) {
+    int64_t total = rows * d;
+    if (total <= 0) return hipSuccess;
+    int64_t nb = (total + 255) / 256;
+    if (nb > 262144) nb = 262144;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)nb), dim3(256), 0, st, src, order, rows, d, mk, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag,
+                          uint8_t *out, double *norm3, int8_t *exps, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lowprec, dim3(nblocks(rows, 128)), dim3(128), 0, st, X, rows, d, mk, sk, dpad,
+                       frag, out, norm3, exps);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64,
+                             double eabs, double *coef, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_coef, dim3(nblocks(nblk, 256)), dim3(256), 0, st, pnorm3, m, nblk, g32,
+                       g64, eabs, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
+                         const void *Qm, int d, int mk, double *t64, float *th, float *tl, float *tm,
+                         hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_thresh, dim3(nblocks(npairs, 256)), dim3(256), 0, st, pair_u, pair_q, npairs,
+                       Um, Qm, d, mk, t64, th, tl, tm);
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, const double *t64,
+                          const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
+                          unsigned long long *flips, hipStream_t st) {
+    if (nrec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recheck, dim3(nblocks(nrec, 256)), dim3(256), 0, st, rec, nrec, pair_u, t64, Um,
+                       Pm, d, mk, cnt, flips);
+    return hipGetLastError();
+}
+
+}  // namespace rkr

@@ -1,0 +1,50 @@
+// query.h -- views and helper launchers of the query pipeline.
+#pragma once
+#include "kernels.h"
+
+namespace rkr {
+
+// Domain of a call: dense (every user x every query) or CSR candidate lists.
+// Query q's domain list has positions i = 0 .. seg_off[q+1] - seg_off[q] - 1
+// in ascending user id; pid(q, i) = i * nq + q (dense) or qm_pid[seg_off[q] + i].
+struct QView {
+    int dense;
+    int nq;
+    int64_t n;
+    const int64_t *seg_off;   // device [nq + 1]
+    const int32_t *qm_pid;    // CSR only
+};
+
+// Read-only view of a task set.
+struct TView {
+    int64_t ntask;
+    const int32_t *len;
+    const int64_t *blk_base;
+    const int32_t *ent_pid;
+};
+
+hipError_t scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st);
+
+hipError_t q_seed_keys(const QView &v, const int32_t *pair_u, const double *t64, const double *unorm3,
+                       const float *pred, int64_t total, uint64_t *keys, hipStream_t st);
+hipError_t q_mark_selected(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                           uint8_t *flag, hipStream_t st);
+hipError_t q_compact_flags(const uint8_t *flag, int64_t N, int32_t *out, int64_t *count, Scratch &sc,
+                           hipStream_t st);
+hipError_t q_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt, hipStream_t st);
+hipError_t q_rank_keys_sel(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                           const uint32_t *cnt, uint64_t *keys, hipStream_t st);
+hipError_t q_bounds(const uint64_t *best, const int64_t *best_off, const int32_t *k, const double *c, int nq,
+                    int32_t *bound, int32_t *seed_kth, hipStream_t st);
+hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, int64_t *count, Scratch &sc,
+                       hipStream_t st);
+hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
+                            hipStream_t st);
+hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t nsel,
+                       const int32_t *surv, int64_t nsurv, const int32_t *pair_u, const int32_t *pair_q,
+                       const uint32_t *cnt, const int64_t *cand_off, int32_t *cursor, uint64_t *keys,
+                       hipStream_t st);
+hipError_t q_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int32_t *ranks, hipStream_t st);
+hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream_t st);
+
+}  // namespace rkr

@@ -1,0 +1,248 @@
+// query.hip -- per-call helper kernels of the query pipeline: seed keys,
+// seed marking, compaction of flagged pairs, survivor collection, the per-query
+// rank bound and the answer assembly.
+#include "query.h"
+
+namespace rkr {
+
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__device__ inline int seg_of(const int64_t *off, int nseg, int64_t j) {
+    int lo = 0, hi = nseg;    // off[lo] <= j < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= j) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int32_t pid_of(const QView &v, int q, int64_t i) {
+    return v.dense ? (int32_t)(i * v.nq + q) : v.qm_pid[v.seg_off[q] + i];
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += s) p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += s) p[i] = v;
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)nb), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)nb), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+// Seed keys: smaller is more promising.  Default heuristic: -t / |u| (for an
+// isotropic item set the rank is a decreasing function of the cosine of u and
+// q).  With an estimator, its predicted log-rank.  Low 32 bits: position in
+// the query's domain list (ascending user id), so ties go to smaller ids.
+__global__ void k_seed_keys(QView v, const int32_t *pair_u, const double *t64, const double *unorm3,
+                            const float *pred, int64_t total, uint64_t *keys) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int q = v.dense ? (int)(j / v.n) : seg_of(v.seg_off, v.nq, j);
+    int64_t i = j - v.seg_off[q];
+    int32_t pid = pid_of(v, q, i);
+    float h;
+    if (pred) {
+        h = pred[(int64_t)q * v.n + pair_u[pid]];
+    } else {
+        double nu = unorm3[3 * (int64_t)pair_u[pid] + 2];
+        h = nu > 0.0 ? (float)(-t64[pid] / nu) : 0.0f;
+    }
+    keys[j] = ((uint64_t)f32_order_key(h) << 32) | (uint32_t)i;
+}
+
+__global__ void k_mark_selected(QView v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                                uint8_t *flag) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int q = seg_of(sel_off, v.nq, j);
+    int64_t i = (int64_t)(uint32_t)(sel[j] & 0xFFFFFFFFu);
+    flag[pid_of(v, q, i)] = 1;
+}
+
+__global__ void k_scatter_flagged(const uint8_t *flag, const int64_t *excl, int64_t N, int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && flag[i]) out[excl[i]] = (int32_t)i;
+}
+
+__global__ void k_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) cnt[pids[i]] = 0;
+}
+
+// keys (rank << 32 | i) of the selected seeds of every query
+__global__ void k_rank_keys_sel(QView v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                                const uint32_t *cnt, uint64_t *keys) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int q = seg_of(sel_off, v.nq, j);
+    uint32_t i = (uint32_t)(sel[j] & 0xFFFFFFFFu);
+    int32_t pid = pid_of(v, q, i);
+    keys[j] = ((uint64_t)(1u + cnt[pid]) << 32) | i;
+}
+
+// Per-query abandon bound from the k best seed ranks: B = k-th rank; the
+// approximate mode (c > 1) uses floor(B / c) (see the pipeline notes).
+__global__ void k_bounds(const uint64_t *best, const int64_t *best_off, const int32_t *k, const double *c,
+                         int nq, int32_t *bound, int32_t *seed_kth) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    uint32_t B = (uint32_t)(best[best_off[q] + k[q] - 1] >> 32);
+    seed_kth[q] = (int32_t)B;
+    double X = (c && c[q] > 1.0) ? floor((double)B / c[q]) : (double)B;
+    bound[q] = (int32_t)X;
+}
+
+// Survivors of the screen: per task, live entries that are not seeds.
+__global__ void k_surv_count(const TView t, const uint8_t *seedflag, int32_t *cnt_task) {
+    int64_t ti = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ti >= t.ntask) return;
+    int c = 0;
+    const int L = t.len[ti];
+    const int64_t base = t.blk_base[ti >> 5] + (ti & 31);
+    for (int i = 0; i < L; ++i) c += seedflag[t.ent_pid[base + (int64_t)i * 32]] ? 0 : 1;
+    cnt_task[ti] = c;
+}
+__global__ void k_surv_write(const TView t, const uint8_t *seedflag, const int64_t *off, int32_t *out) {
+    int64_t ti = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ti >= t.ntask) return;
+    int64_t o = off[ti];
+    const int L = t.len[ti];
+    const int64_t base = t.blk_base[ti >> 5] + (ti & 31);
+    for (int i = 0; i < L; ++i) {
+        int32_t pid = t.ent_pid[base + (int64_t)i * 32];
+        if (!seedflag[pid]) out[o++] = pid;
+    }
+}
+
+// Answer candidates per query = its seeds + its survivors.
+__global__ void k_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) atomicAdd(&qcount[pair_q[pids[i]]], 1);
+}
+__global__ void k_cand_keys_seeds(QView v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                                  const int32_t *pair_u, const uint32_t *cnt, const int64_t *cand_off,
+                                  uint64_t *keys) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int q = seg_of(sel_off, v.nq, j);
+    int64_t i = (int64_t)(uint32_t)(sel[j] & 0xFFFFFFFFu);
+    int32_t pid = pid_of(v, q, i);
+    keys[cand_off[q] + (j - sel_off[q])] = ((uint64_t)(1u + cnt[pid]) << 32) | (uint32_t)pair_u[pid];
+}
+__global__ void k_cand_keys_surv(const int32_t *pids, int64_t N, const int32_t *pair_u, const int32_t *pair_q,
+                                 const uint32_t *cnt, const int64_t *cand_off, int32_t *cursor,
+                                 uint64_t *keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t pid = pids[i];
+    int q = pair_q[pid];
+    int64_t p = cand_off[q] + atomicAdd(&cursor[q], 1);
+    keys[p] = ((uint64_t)(1u + cnt[pid]) << 32) | (uint32_t)pair_u[pid];
+}
+__global__ void k_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int32_t *ranks) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    ids[i] = (int32_t)(keys[i] & 0xFFFFFFFFu);
+    ranks[i] = (int32_t)(keys[i] >> 32);
+}
+__global__ void k_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ranks[i] = (int32_t)(1u + cnt[i]);
+}
+
+// ---------------------------------------------------------------------------
+#define LAUNCH1D(kern, N, ...)                                                              \
+    do {                                                                                   \
+        if ((N) > 0) hipLaunchKernelGGL(kern, dim3(nblocks((N), 256)), dim3(256), 0, st, __VA_ARGS__); \
+    } while (0)
+
+hipError_t q_seed_keys(const QView &v, const int32_t *pair_u, const double *t64, const double *unorm3,
+                       const float *pred, int64_t total, uint64_t *keys, hipStream_t st) {
+    LAUNCH1D(k_seed_keys, total, v, pair_u, t64, unorm3, pred, total, keys);
+    return hipGetLastError();
+}
+hipError_t q_mark_selected(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                           uint8_t *flag, hipStream_t st) {
+    LAUNCH1D(k_mark_selected, total, v, sel, sel_off, total, flag);
+    return hipGetLastError();
+}
+hipError_t q_compact_flags(const uint8_t *flag, int64_t N, int32_t *out, int64_t *count, Scratch &sc,
+                           hipStream_t st) {
+    int64_t *excl = (int64_t *)sc.take(N * 8 + 8);
+    int64_t *dtot = (int64_t *)sc.take(16);
+    if (!excl || !dtot) return hipErrorOutOfMemory;
+    hipError_t e = scan_u8(flag, N, excl, dtot, sc, st);
+    if (e != hipSuccess) return e;
+    LAUNCH1D(k_scatter_flagged, N, flag, excl, N, out);
+    if ((e = hipMemcpyAsync(count, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+hipError_t q_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt, hipStream_t st) {
+    LAUNCH1D(k_zero_at, N, pids, N, cnt);
+    return hipGetLastError();
+}
+hipError_t q_rank_keys_sel(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
+                           const uint32_t *cnt, uint64_t *keys, hipStream_t st) {
+    LAUNCH1D(k_rank_keys_sel, total, v, sel, sel_off, total, cnt, keys);
+    return hipGetLastError();
+}
+hipError_t q_bounds(const uint64_t *best, const int64_t *best_off, const int32_t *k, const double *c, int nq,
+                    int32_t *bound, int32_t *seed_kth, hipStream_t st) {
+    LAUNCH1D(k_bounds, (int64_t)nq, best, best_off, k, c, nq, bound, seed_kth);
+    return hipGetLastError();
+}
+hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, int64_t *count, Scratch &sc,
+                       hipStream_t st) {
+    *count = 0;
+    if (t.ntask <= 0) return hipSuccess;
+    int32_t *ct = (int32_t *)sc.take(t.ntask * 4);
+    int64_t *off = (int64_t *)sc.take(t.ntask * 8 + 8);
+    int64_t *dtot = (int64_t *)sc.take(16);
+    if (!ct || !off || !dtot) return hipErrorOutOfMemory;
+    LAUNCH1D(k_surv_count, t.ntask, t, seedflag, ct);
+    hipError_t e = scan_i32(ct, t.ntask, off, dtot, sc, st);
+    if (e != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(count, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    LAUNCH1D(k_surv_write, t.ntask, t, seedflag, off, out);
+    return hipGetLastError();
+}
+hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
+                            hipStream_t st) {
+    LAUNCH1D(k_count_by_query, N, pids, N, pair_q, qcount);
+    return hipGetLastError();
+}
+hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t nsel,
+                       const int32_t *surv, int64_t nsurv, const int32_t *pair_u, const int32_t *pair_q,
+                       const uint32_t *cnt, const int64_t *cand_off, int32_t *cursor, uint64_t *keys,
+                       hipStream_t st) {
+    LAUNCH1D(k_cand_keys_seeds, nsel, v, sel, sel_off, nsel, pair_u, cnt, cand_off, keys);
+    LAUNCH1D(k_cand_keys_surv, nsurv, surv, nsurv, pair_u, pair_q, cnt, cand_off, cursor, keys);
+    return hipGetLastError();
+}
+hipError_t q_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int32_t *ranks, hipStream_t st) {
+    LAUNCH1D(k_write_answer, total, keys, total, ids, ranks);
+    return hipGetLastError();
+}
+hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream_t st) {
+    LAUNCH1D(k_ranks_out, n, cnt, n, ranks);
+    return hipGetLastError();
+}
+
+}  // namespace rkr

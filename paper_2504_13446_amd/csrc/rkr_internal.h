@@ -1,0 +1,112 @@
+// rkr_internal.h -- declarations shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rkr {
+
+enum ScoreKind { SK_F32 = 0, SK_BF16 = 1, SK_FP8 = 2 };
+enum MasterKind { MK_F32 = 0, MK_BF16 = 1 };
+
+// 32x32 MFMA geometry per score kind.
+//   KS: dimensions consumed by one MFMA k-step.
+//   FB: bytes one lane contributes to one operand fragment.
+//   ES: bytes per element of the low-precision copy.
+__host__ __device__ constexpr int frag_ks(int sk) { return sk == SK_BF16 ? 16 : (sk == SK_FP8 ? 64 : 2); }
+__host__ __device__ constexpr int frag_fb(int sk) { return sk == SK_BF16 ? 16 : (sk == SK_FP8 ? 32 : 4); }
+__host__ __device__ constexpr int elem_size(int sk) { return sk == SK_BF16 ? 2 : (sk == SK_FP8 ? 1 : 4); }
+
+constexpr int ITEM_BLOCK = 32;      // items per MFMA output block (rows)
+constexpr int STEP_ITEMS = 64;      // items per pipeline step of the count kernel
+constexpr int USER_BLOCK = 32;      // users per MFMA output block (columns)
+constexpr int WAVES_PER_WG = 8;     // count kernel workgroup = 8 wave64
+
+// ---------------------------------------------------------------------------
+// Exactly-rounded float helpers (finite inputs).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float f32_next_up(float x) {
+    union { float f; int32_t i; } v{x};
+    if (v.i == (int32_t)0x80000000) { v.i = 1; return v.f; }   // -0 -> smallest positive
+    v.i += (v.i >= 0) ? 1 : -1;
+    return v.f;
+}
+__host__ __device__ inline float f32_next_down(float x) { return -f32_next_up(-x); }
+
+// Largest float <= x and smallest float >= x.
+__host__ __device__ inline float f32_round_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = f32_next_down(f);
+    return f;
+}
+__host__ __device__ inline float f32_round_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = f32_next_up(f);
+    return f;
+}
+
+// Monotone map float -> uint32 (a < b  <=>  key(a) < key(b)), for finite values.
+__host__ __device__ inline uint32_t f32_order_key(float x) {
+    union { float f; uint32_t u; } v{x};
+    return (v.u & 0x80000000u) ? ~v.u : (v.u | 0x80000000u);
+}
+
+// Widen a master element to double (exact).
+__device__ inline double master_elem(const void *base, int mk, int64_t i) {
+    if (mk == MK_BF16) {
+        uint32_t b = (uint32_t)((const uint16_t *)base)[i] << 16;
+        return (double)__uint_as_float(b);
+    }
+    return (double)((const float *)base)[i];
+}
+
+// ---------------------------------------------------------------------------
+// Count kernel arguments.
+// ---------------------------------------------------------------------------
+struct CountArgs {
+    // items, sorted by norm, low precision, fragment-major:
+    //   [item block b][k-step s][lane 0..63][FB bytes]
+    const uint8_t *plp;
+    int64_t m;
+    int nks;                      // k-steps per vector
+    const double *step_coef;      // [nsteps][4]: a, b, c, abs   (error-bound coefficients)
+    const int8_t *pexp;           // FP8: per-item power-of-two scale exponent (sorted order)
+    // users, low precision, row-major [n][dpad]
+    const uint8_t *ulp;
+    int dpad;
+    const double *unorm3;         // [n][3]: |u_hat|, |delta u|, |u|
+    const int8_t *uexp;           // FP8: per-user exponent
+    // tasks: 32 tasks form a block; block tb's entries sit at blk_base[tb] + i*32 + (t%32)
+    const int32_t *task_user;     // [ntask_pad] user id, -1 for padding
+    int64_t ntask;                // real tasks (ntask_pad is a multiple of 512)
+    const int64_t *blk_base;
+    int32_t *ent_len;             // [ntask_pad]
+    int32_t *ent_pid;
+    int32_t *ent_q;
+    uint32_t *ent_cnt;            // [nsplit][cap_total]
+    float *ent_th;                // FP32 value >= the FP64 threshold
+    float *ent_tl;                // FP32 value <= the FP64 threshold
+    const float *ent_tm;          // fl32 of the FP64 threshold (plain verdict of near ties)
+    int64_t cap_total;
+    const int32_t *bound;         // [nq] abandon bound (screen mode), INT32_MAX = none
+    int nq;
+    // P range: steps [split * steps_per_split, ...) of nsteps
+    int64_t nsteps;
+    int64_t steps_per_split;
+    // exact mode outputs
+    uint32_t *cnt_out;            // [npairs] += certain-above count
+    uint32_t *cnt_lo_out;         // interval mode: [npairs] += count of scores >= lo
+    int2 *emit;                   // near-tie records (pid, item)
+    unsigned long long *emit_count;
+    unsigned long long emit_cap;
+    unsigned long long *stat;     // [0]: executed compares
+    int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
+};
+
+enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_INTERVAL = 2 };
+
+struct DeviceIndex;
+
+// launchers (count.hip)
+hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, hipStream_t st);
+
+}  // namespace rkr

@@ -1,0 +1,443 @@
+// select.hip -- segmented k-smallest selection (radix select + bitonic sort in
+// LDS), device-wide exclusive scan, and the builders that turn lists of
+// (user, query) pairs into the count kernel's block-interleaved entry lists.
+#include "rkr_internal.h"
+#include "kernels.h"
+#include "query.h"
+
+namespace rkr {
+
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (int32 or int64 input -> int64 output), three phases.
+// ---------------------------------------------------------------------------
+constexpr int SCAN_BS = 256, SCAN_PER = 8, SCAN_TILE = SCAN_BS * SCAN_PER;
+
+template <typename In>
+__global__ __launch_bounds__(SCAN_BS) void k_scan_reduce(const In *in, int64_t n, int64_t *sums) {
+    __shared__ int64_t s[SCAN_BS];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t acc = 0;
+    for (int j = 0; j < SCAN_PER; ++j) {
+        int64_t i = base + (int64_t)j * SCAN_BS + threadIdx.x;
+        if (i < n) acc += (int64_t)in[i];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = SCAN_BS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = s[0];
+}
+
+// Scan of one tile per block with a carried-in offset per block.
+template <typename In>
+__global__ __launch_bounds__(SCAN_BS) void k_scan_tile(const In *in, int64_t n, const int64_t *offs,
+                                                       int64_t *out) {
+    __shared__ int64_t s[SCAN_BS];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER;
+    int64_t v[SCAN_PER];
+    int64_t tot = 0;
+    for (int j = 0; j < SCAN_PER; ++j) {
+        int64_t i = base + j;
+        v[j] = (i < n) ? (int64_t)in[i] : 0;
+        tot += v[j];
+    }
+    s[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < SCAN_BS; o <<= 1) {
+        int64_t t = (threadIdx.x >= o) ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t run = s[threadIdx.x] - tot + (offs ? offs[blockIdx.x] : 0);
+    for (int j = 0; j < SCAN_PER; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+template <typename In>
+__global__ void k_scan_total(const In *in, const int64_t *out, int64_t n, int64_t *total);
+
+template <typename In>
+static hipError_t scan_impl(const In *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc,
+                            hipStream_t st) {
+    if (n <= 0) {
+        if (total) { int64_t z = 0; return hipMemcpyAsync(total, &z, 8, hipMemcpyHostToDevice, st); }
+        return hipSuccess;
+    }
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) {
+        hipLaunchKernelGGL((k_scan_tile<In>), dim3(1), dim3(SCAN_BS), 0, st, in, n, (const int64_t *)nullptr, out);
+    } else {
+        int64_t *sums = (int64_t *)sc.take((nb + 1) * 8);
+        int64_t *soffs = (int64_t *)sc.take((nb + 1) * 8);
+        if (!sums || !soffs) return hipErrorOutOfMemory;
+        hipLaunchKernelGGL((k_scan_reduce<In>), dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, n, sums);
+        hipError_t e = scan_impl<int64_t>(sums, nb, soffs, nullptr, sc, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_scan_tile<In>), dim3((unsigned)nb), dim3(SCAN_BS), 0, st, in, n,
+                           (const int64_t *)soffs, out);
+    }
+    if (total) {
+        // total = out[n-1] + in[n-1]
+        hipLaunchKernelGGL(k_scan_total<In>, dim3(1), dim3(1), 0, st, in, out, n, total);
+    }
+    return hipGetLastError();
+}
+
+template <typename In>
+__global__ void k_scan_total(const In *in, const int64_t *out, int64_t n, int64_t *total) {
+    *total = out[n - 1] + (int64_t)in[n - 1];
+}
+
+hipError_t scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st) {
+    return scan_impl<int32_t>(in, n, out, total, sc, st);
+}
+hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st) {
+    return scan_impl<int64_t>(in, n, out, total, sc, st);
+}
+hipError_t scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st) {
+    return scan_impl<uint8_t>(in, n, out, total, sc, st);
+}
+
+// ---------------------------------------------------------------------------
+// Segmented selection of the K smallest 64-bit keys (keys unique within a
+// segment).  One workgroup per segment; output sorted ascending.
+// ---------------------------------------------------------------------------
+constexpr int SEL_BS = 1024;
+constexpr int SEL_MAX = 4096;
+
+__device__ inline void lds_bitonic_sort(uint64_t *s, int npow2) {
+    for (int k = 2; k <= npow2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < npow2; i += SEL_BS) {
+                int l = i ^ j;
+                if (l > i) {
+                    uint64_t a = s[i], b = s[l];
+                    bool up = (i & k) == 0;
+                    if (up ? (a > b) : (a < b)) { s[i] = b; s[l] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const int64_t *seg_off,
+                                                   const int32_t *kk, const int64_t *out_off,
+                                                   uint64_t *out) {
+    __shared__ uint64_t s[SEL_MAX];
+    __shared__ uint32_t hist[16][256];
+    __shared__ uint32_t sh_cnt;
+    __shared__ uint64_t sh_prefix, sh_mask;
+    __shared__ int64_t sh_need;
+    __shared__ int sh_done;
+    const int seg = blockIdx.x;
+    const int64_t b = seg_off[seg], len = seg_off[seg + 1] - b;
+    int64_t K = kk[seg];
+    if (K > len) K = len;
+    const int64_t ob = out_off[seg];
+    if (K <= 0) return;
+    const uint64_t *x = keys + b;
+    const int tid = threadIdx.x, wave = tid >> 6;
+
+    uint64_t T;   // select keys <= T
+    if (len <= SEL_MAX) {
+        T = ~0ull;
+    } else {
+        if (tid == 0) { sh_prefix = 0; sh_mask = 0; sh_need = K; sh_done = 0; }
+        __syncthreads();
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            for (int i = tid; i < 16 * 256; i += SEL_BS) (&hist[0][0])[i] = 0;
+            __syncthreads();
+            const uint64_t pre = sh_prefix, msk = sh_mask;
+            for (int64_t i = tid; i < len; i += SEL_BS) {
+                uint64_t v = x[i];
+                if ((v & msk) == pre) atomicAdd(&hist[wave][(v >> shift) & 255], 1u);
+            }
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t t = 0;
+                for (int w = 0; w < 16; ++w) t += hist[w][tid];
+                hist[0][tid] = t;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int64_t need = sh_need, cum = 0;
+                int v = 0;
+                for (; v < 256; ++v) {
+                    if (cum + hist[0][v] >= need) break;
+                    cum += hist[0][v];
+                }
+                sh_need = need - cum;
+                sh_prefix = pre | ((uint64_t)v << shift);
+                sh_mask = msk | (255ull << shift);
+                if ((int64_t)hist[0][v] == need - cum) sh_done = 1;
+            }
+            __syncthreads();
+            if (sh_done) break;
+        }
+        T = sh_prefix | ~sh_mask;
+    }
+    if (tid == 0) sh_cnt = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < len; i += SEL_BS) {
+        uint64_t v = x[i];
+        if (v <= T) {
+            uint32_t p = atomicAdd(&sh_cnt, 1u);
+            if (p < SEL_MAX) s[p] = v;
+        }
+    }
+    __syncthreads();
+    int cnt = (int)min((uint32_t)SEL_MAX, sh_cnt);
+    int np2 = 1;
+    while (np2 < cnt) np2 <<= 1;
+    for (int i = cnt + tid; i < np2; i += SEL_BS) s[i] = ~0ull;
+    __syncthreads();
+    lds_bitonic_sort(s, np2);
+    for (int64_t i = tid; i < K; i += SEL_BS) out[ob + i] = s[i];
+}
+
+hipError_t launch_select(const uint64_t *keys, const int64_t *seg_off, const int32_t *kk, int64_t nseg,
+                         const int64_t *out_off, uint64_t *out, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)nseg), dim3(SEL_BS), 0, st, keys, seg_off, kk, out_off, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Task-set builder.  Input: pids[N], ascending (hence grouped by user, since
+// pairs are numbered user-major).  Output (TaskSet): one task per distinct
+// user, its entry list in block-interleaved layout.
+// ---------------------------------------------------------------------------
+__global__ void k_user_change(const int32_t *pids, int64_t N, const int32_t *pair_u, int32_t *flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    flag[i] = (i == 0 || pair_u[pids[i]] != pair_u[pids[i - 1]]) ? 1 : 0;
+}
+
+// excl[i] = number of task starts before i; element i belongs to task
+// excl[i] + flag[i] - 1.
+__global__ void k_task_starts(const int32_t *pids, int64_t N, const int32_t *pair_u, const int32_t *flag,
+                              const int64_t *excl, int64_t *task_start, int32_t *task_user) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || !flag[i]) return;
+    int64_t t = excl[i];
+    task_start[t] = i;
+    task_user[t] = pair_u[pids[i]];
+}
+
+__global__ void k_task_len(const int64_t *task_start, int64_t ntask, int64_t N, int64_t ntask_pad,
+                           int32_t *task_user, int32_t *len) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask_pad) return;
+    if (t < ntask) {
+        int64_t e = (t + 1 < ntask) ? task_start[t + 1] : N;
+        len[t] = (int32_t)(e - task_start[t]);
+    } else {
+        len[t] = 0;
+        task_user[t] = -1;
+    }
+}
+
+__global__ void k_block_cap(const int32_t *len, int64_t nblk, int64_t *cap32) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    int32_t mx = 0;
+    for (int i = 0; i < 32; ++i) mx = max(mx, len[b * 32 + i]);
+    cap32[b] = 32 * (int64_t)mx;
+}
+
+__global__ void k_fill_entries(const int32_t *pids, int64_t N, const int32_t *flag, const int64_t *excl,
+                               const int64_t *task_start, const int64_t *blk_base, const int32_t *pair_q,
+                               const float *th, const float *tl, const float *tm, int plain,
+                               int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt, float *ent_th,
+                               float *ent_tl, float *ent_tm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int64_t t = excl[i] + flag[i] - 1;
+    int64_t j = i - task_start[t];
+    int64_t e = blk_base[t >> 5] + j * 32 + (t & 31);
+    int32_t pid = pids[i];
+    ent_pid[e] = pid;
+    ent_q[e] = pair_q[pid];
+    ent_cnt[e] = 0;
+    // plain mode compares the score with fl32(t) itself: both edges = fl32(t)
+    ent_th[e] = plain ? tm[pid] : th[pid];
+    ent_tl[e] = plain ? tm[pid] : tl[pid];
+    ent_tm[e] = tm[pid];
+}
+
+hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, TaskSet &ts,
+                       Scratch &sc, hipStream_t st) {
+    ts.ntask = 0;
+    ts.ntask_pad = 0;
+    ts.cap_total = 0;
+    if (N <= 0) return hipSuccess;
+    hipError_t e;
+    int32_t *flag = (int32_t *)sc.take(N * 4);
+    int64_t *excl = (int64_t *)sc.take(N * 8);
+    int64_t *dtot = (int64_t *)sc.take(16);
+    if (!flag || !excl || !dtot) return hipErrorOutOfMemory;
+    hipLaunchKernelGGL(k_user_change, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, ps.pair_u, flag);
+    if ((e = scan_i32(flag, N, excl, dtot, sc, st)) != hipSuccess) return e;
+    int64_t ntask = 0;
+    if ((e = hipMemcpyAsync(&ntask, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const int64_t ntask_pad = (ntask + 511) / 512 * 512;
+    const int64_t nblk = ntask_pad / 32;
+    if ((e = ts.reserve(ntask_pad, nblk)) != hipSuccess) return e;
+    int64_t *task_start = (int64_t *)sc.take((ntask + 1) * 8);
+    int64_t *cap32 = (int64_t *)sc.take(nblk * 8);
+    if (!task_start || !cap32) return hipErrorOutOfMemory;
+    hipLaunchKernelGGL(k_task_starts, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, ps.pair_u, flag, excl,
+                       task_start, ts.task_user);
+    hipLaunchKernelGGL(k_task_len, dim3(nblocks(ntask_pad, 256)), dim3(256), 0, st, task_start, ntask, N,
+                       ntask_pad, ts.task_user, ts.len);
+    hipLaunchKernelGGL(k_block_cap, dim3(nblocks(nblk, 256)), dim3(256), 0, st, ts.len, nblk, cap32);
+    if ((e = scan_i64(cap32, nblk, ts.blk_base, dtot, sc, st)) != hipSuccess) return e;
+    int64_t cap_total = 0;
+    if ((e = hipMemcpyAsync(&cap_total, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if ((e = ts.reserve_entries(cap_total)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_entries, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, flag, excl, task_start,
+                       ts.blk_base, ps.pair_q, ps.th, ps.tl, ps.tm, plain, ts.ent_pid, ts.ent_q, ts.ent_cnt,
+                       ts.ent_th, ts.ent_tl, ts.ent_tm);
+    ts.ntask = ntask;
+    ts.ntask_pad = ntask_pad;
+    ts.cap_total = cap_total;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small element-wise helpers.
+// ---------------------------------------------------------------------------
+__global__ void k_iota(int32_t *out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)i;
+}
+hipError_t launch_iota(int32_t *out, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(nblocks(n, 256)), dim3(256), 0, st, out, n);
+    return hipGetLastError();
+}
+
+// Dense domain pairs: pid = u * nq + q.
+__global__ void k_dense_pairs(int64_t n, int nq, int32_t *pair_u, int32_t *pair_q) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nq) return;
+    pair_u[i] = (int32_t)(i / nq);
+    pair_q[i] = (int32_t)(i % nq);
+}
+hipError_t launch_dense_pairs(int64_t n, int nq, int32_t *pair_u, int32_t *pair_q, hipStream_t st) {
+    int64_t N = n * nq;
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dense_pairs, dim3(nblocks(N, 256)), dim3(256), 0, st, n, nq, pair_u, pair_q);
+    return hipGetLastError();
+}
+
+// CSR (query-major candidate lists) -> user-major pairs.
+// 1) per-user counts, 2) scan -> pair_off, 3) scatter with a cursor, 4) sort
+// each user's pairs by query (insertion sort; lists are short) so the layout
+// is deterministic.  qm_pid[j] = pid of the j-th query-major candidate.
+__global__ void k_csr_count(const int32_t *cand_ids, int64_t total, int32_t *ucount) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < total) atomicAdd(&ucount[cand_ids[j]], 1);
+}
+__global__ void k_csr_scatter(const int32_t *cand_ids, const int64_t *cand_off, int nq, int64_t total,
+                              const int64_t *pair_off, int32_t *cursor, int32_t *pair_u, int32_t *pair_q) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    // query of position j: binary search in cand_off
+    int lo = 0, hi = nq;   // cand_off[lo] <= j < cand_off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (cand_off[mid] <= j) lo = mid; else hi = mid;
+    }
+    int u = cand_ids[j];
+    int64_t p = pair_off[u] + atomicAdd(&cursor[u], 1);
+    pair_u[p] = u;
+    pair_q[p] = lo;
+}
+__global__ void k_csr_sort_users(const int64_t *pair_off, int64_t n, int32_t *pair_q) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int64_t b = pair_off[u], e = pair_off[u + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        int32_t v = pair_q[i];
+        int64_t j = i - 1;
+        while (j >= b && pair_q[j] > v) { pair_q[j + 1] = pair_q[j]; --j; }
+        pair_q[j + 1] = v;
+    }
+}
+// qm_pid: for query q's candidate list position j, find pid by binary search
+// of q within user u's (sorted) pair_q segment.
+__global__ void k_csr_qm_pid(const int32_t *cand_ids, const int64_t *cand_off, int nq, int64_t total,
+                             const int64_t *pair_off, const int32_t *pair_q, int32_t *qm_pid) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int lo = 0, hi = nq;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (cand_off[mid] <= j) lo = mid; else hi = mid;
+    }
+    int u = cand_ids[j];
+    int64_t b = pair_off[u], e = pair_off[u + 1];
+    while (e - b > 1) {
+        int64_t mid = (b + e) >> 1;
+        if (pair_q[mid] <= lo) b = mid; else e = mid;
+    }
+    qm_pid[j] = (int32_t)b;
+}
+// duplicate / range validation of candidate lists: bit 1 = id out of range,
+// bit 2 = duplicate within a list (lists need not be sorted).
+__global__ void k_csr_validate(const int32_t *cand_ids, int64_t total, int64_t n, int *flags) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= total) return;
+    int u = cand_ids[j];
+    if (u < 0 || u >= n) atomicOr(flags, 1);
+}
+__global__ void k_csr_dupcheck(const int64_t *pair_off, int64_t n, const int32_t *pair_q, int *flags) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    for (int64_t i = pair_off[u] + 1; i < pair_off[u + 1]; ++i)
+        if (pair_q[i] == pair_q[i - 1]) { atomicOr(flags, 2); return; }
+}
+
+hipError_t build_csr_pairs(const int32_t *cand_ids, const int64_t *cand_off_dev, int nq, int64_t total,
+                           int64_t n, PairSet &ps, int *dflags, Scratch &sc, hipStream_t st) {
+    hipError_t e;
+    int32_t *ucount = (int32_t *)sc.take(n * 4);
+    int32_t *cursor = (int32_t *)sc.take(n * 4);
+    int64_t *dtot = (int64_t *)sc.take(16);
+    if (!ucount || !cursor || !dtot) return hipErrorOutOfMemory;
+    if ((e = hipMemsetAsync(ucount, 0, n * 4, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(cursor, 0, n * 4, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_csr_validate, dim3(nblocks(total, 256)), dim3(256), 0, st, cand_ids, total, n, dflags);
+    int flags = 0;
+    if ((e = hipMemcpyAsync(&flags, dflags, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (flags) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_csr_count, dim3(nblocks(total, 256)), dim3(256), 0, st, cand_ids, total, ucount);
+    if ((e = scan_i32(ucount, n, ps.pair_off, dtot, sc, st)) != hipSuccess) return e;
+    // pair_off[n] = total
+    if ((e = hipMemcpyAsync(ps.pair_off + n, &total, 8, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_csr_scatter, dim3(nblocks(total, 256)), dim3(256), 0, st, cand_ids, cand_off_dev, nq,
+                       total, ps.pair_off, cursor, ps.pair_u, ps.pair_q);
+    hipLaunchKernelGGL(k_csr_sort_users, dim3(nblocks(n, 256)), dim3(256), 0, st, ps.pair_off, n, ps.pair_q);
+    hipLaunchKernelGGL(k_csr_dupcheck, dim3(nblocks(n, 256)), dim3(256), 0, st, ps.pair_off, n, ps.pair_q, dflags);
+    hipLaunchKernelGGL(k_csr_qm_pid, dim3(nblocks(total, 256)), dim3(256), 0, st, cand_ids, cand_off_dev, nq,
+                       total, ps.pair_off, ps.pair_q, ps.qm_pid);
+    if ((e = hipMemcpyAsync(&flags, dflags, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (flags) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace rkr

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Exact answers and ranks must be bit-identical to the oracle's (the oracle
+fixes one FP64 evaluation of every inner product); approximate answers must
+satisfy Def. 3 with zero violations.  Sizes span several 64-item steps,
+several 512-user workgroups and ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2504_13446_amd import rkr, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, dtype):
+    return rkr.to_device(x, dtype)
+
+
+def _answers(ids, rk, off):
+    ids = ids.cpu().numpy()
+    rk = rk.cpu().numpy()
+    return [(ids[off[i]:off[i + 1]], rk[off[i]:off[i + 1]]) for i in range(len(off) - 1)]
+
+
+def _check_exact(R, answers, ks):
+    for i, (gi, gr) in enumerate(answers):
+        wi, wr = O.topk(R[i], int(ks[i]))
+        assert np.array_equal(gr, wr), ("ranks", i, gr[:10], wr[:10])
+        assert np.array_equal(gi, wi), ("ids", i, gi[:10], wi[:10])
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = W.make("small")
+    return w, O.ranks(w.U, w.P, w.Qv)
+
+
+@pytest.mark.parametrize("score", ["bf16", "f32", "fp8"])
+def test_small_batch_exact(small, score):
+    w, R = small
+    idx = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score=score)
+    ans = _answers(*idx.query_batch(_dev(w.Qv, w.dtype), w.k))
+    _check_exact(R, ans, w.k)
+    st = idx.stats()
+    assert st["pairs"] == w.n * w.nq and st["seed_pairs"] == 2 * int(w.k.sum())
+    idx.close()
+
+
+@pytest.mark.parametrize("score", ["bf16", "f32", "fp8"])
+def test_small_all_ranks(small, score):
+    w, R = small
+    idx = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score=score)
+    for i in (0, 4, 9):
+        got = idx.ranks(_dev(w.Qv[i], w.dtype)).cpu().numpy()
+        assert np.array_equal(got, R[i]), (score, i, np.flatnonzero(got != R[i])[:10])
+    idx.close()
+
+
+def test_plain_f32_reports_its_disagreement(small):
+    """Without the recheck the FP32 path compares the score with fl32(t); its
+    ranks may differ from the oracle's, and every differing comparison is one
+    the recheck would have flipped."""
+    w, R = small
+    idx = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score="f32", recheck=False)
+    got = idx.ranks(_dev(w.Qv[0], w.dtype)).cpu().numpy()
+    diff = np.abs(got.astype(np.int64) - R[0])
+    assert diff.max() <= 3
+    idx.close()
+    ex = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score="f32", recheck=True)
+    ex.ranks(_dev(w.Qv[0], w.dtype))
+    st = ex.stats()
+    assert st["flips"] >= int(diff.sum()) - 0   # flips count every plain verdict the recheck overturned
+    ex.close()
+
+
+@pytest.mark.parametrize("d", [3, 8, 16])
+@pytest.mark.parametrize("score", ["bf16", "f32", "fp8"])
+def test_integer_tie_storm(d, score):
+    """Entries in {-2..2}: every score is an exact small integer, ties everywhere;
+    every near tie must go through the recheck and count as 'not above'."""
+    rng = np.random.default_rng(40 + d)
+    n, m = 333, 517
+    U = rng.integers(-2, 3, size=(n, d)).astype(np.float32)
+    P = rng.integers(-2, 3, size=(m, d)).astype(np.float32)
+    qi = rng.choice(m, 6, replace=False)
+    Qv = P[qi]
+    R = O.ranks(U, P, Qv)
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score=score)
+    for i in range(len(qi)):
+        got = idx.ranks(_dev(Qv[i], "f32")).cpu().numpy()
+        assert np.array_equal(got, R[i])
+    ks = np.array([1, 5, 17, 40, 64, 333], np.int32)
+    ans = _answers(*idx.query_batch(_dev(Qv, "f32"), ks))
+    _check_exact(R, ans, ks)
+    idx.close()
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(2)
+    d = 24
+    # m = 0: every rank is 1
+    U = rng.standard_normal((37, d)).astype(np.float32)
+    P0 = np.zeros((0, d), np.float32)
+    idx = rkr.Index(_dev(U, "f32"), torch.empty((0, d), dtype=torch.float32, device="cuda"))
+    q = _dev(rng.standard_normal(d).astype(np.float32), "f32")
+    assert np.all(idx.ranks(q).cpu().numpy() == 1)
+    ids, rk = idx.query_exact(q, 37)
+    assert rk.cpu().numpy().tolist() == [1] * 37 and ids.cpu().numpy().tolist() == list(range(37))
+    idx.close()
+    # one user; tiny item set; zero user row; zero query; duplicated items
+    for n, m in [(1, 1), (1, 70), (33, 65), (513, 129), (1025, 64)]:
+        U = rng.standard_normal((n, d)).astype(np.float32)
+        U[0] = 0.0
+        P = rng.standard_normal((m, d)).astype(np.float32)
+        if m > 3:
+            P[1] = P[2]
+        Qv = np.stack([P[0], np.zeros(d, np.float32), 3.0 * P[-1]])
+        R = O.ranks(U, P, Qv)
+        idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score="bf16")
+        for i in range(3):
+            assert np.array_equal(idx.ranks(_dev(Qv[i], "f32")).cpu().numpy(), R[i])
+        ks = np.array([1, n, max(1, n // 2)], np.int32)
+        _check_exact(R, _answers(*idx.query_batch(_dev(Qv, "f32"), ks)), ks)
+        idx.close()
+
+
+def test_bf16_masters_batch():
+    w = W.make("batch", n=6000, m=5000, nq=12)
+    R = O.ranks(w.U, w.P, w.Qv)
+    idx = rkr.Index(_dev(w.U, "bf16"), _dev(w.P, "bf16"), score="bf16")
+    ans = _answers(*idx.query_batch(_dev(w.Qv, "bf16"), w.k))
+    _check_exact(R, ans, w.k)
+    st = idx.stats()
+    assert st["survivors"] < st["pairs"]
+    idx.close()
+
+
+def test_single_lowrank_scaled_all_ranks():
+    w = W.make("single", n=12000, m=9000)
+    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16")
+    got = idx.ranks(_dev(w.Qv[0], "f32")).cpu().numpy()
+    sub = np.random.default_rng(0).choice(w.n, 1500, replace=False)
+    want = O.ranks(w.U, w.P, w.Qv[0], uids=sub)[0]
+    assert np.array_equal(got[sub], want)
+    ids, rk = idx.query_exact(_dev(w.Qv[0], "f32"), 50)
+    bad_rank, bad_set, _ = O.certify(w.U, w.P, w.Qv[0], 50, ids.cpu().numpy(), rk.cpu().numpy())
+    assert (bad_rank, bad_set) == (0, 0)
+    idx.close()
+
+
+@pytest.mark.parametrize("score", ["bf16", "fp8"])
+def test_uneven_candidates_exact_and_approx(score):
+    w = W.make("uneven", n=4000, m=2500, d=300, nq=24, cand=(50, 3000))
+    users = np.unique(w.cand_ids)
+    Rall = O.ranks(w.U, w.P, w.Qv, uids=users)           # [nq, len(users)]
+    pos = np.full(w.n, -1, np.int64)
+    pos[users] = np.arange(users.size)
+    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score=score)
+    cids = torch.from_numpy(w.cand_ids).cuda()
+    Q = _dev(w.Qv, "f32")
+    ex = _answers(*idx.query_batch(Q, w.k, cand_off=w.cand_off, cand_ids=cids))
+    ap = _answers(*idx.query_batch(Q, w.k, c=1.5, cand_off=w.cand_off, cand_ids=cids))
+    for i in range(w.nq):
+        lst = w.cand_ids[w.cand_off[i]:w.cand_off[i + 1]]
+        r = Rall[i, pos[lst]]
+        wi, wr = O.topk(r, int(w.k[i]), uids=lst)
+        assert np.array_equal(ex[i][0], wi) and np.array_equal(ex[i][1], wr), i
+        gi, gr = ap[i]
+        assert len(set(gi.tolist())) == len(gi) and set(gi.tolist()) <= set(lst.tolist())
+        true = Rall[i, pos[gi]]
+        assert np.all(gr >= true)                         # reported ranks are upper bounds
+        v, _ = O.def3_check(true, wr, 1.5)
+        assert v == 0, i
+    idx.close()
