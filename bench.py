@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched exact reverse k-ranks path on one MI355X.
+
+A step is one rkr_query_batch call: 256 queries over |U| = |P| = 1,000,000,
+d = 200, BF16 masters, k = 100, exact answers (Def. 2), all of the hot path
+(thresholds, seeds, screening count, refine with FP64 near-tie recheck,
+top-k).  Inputs are synthetic (seeded, see workloads.py) and resident in HBM
+before the timed region; the index is built once, outside it.
+
+Printed (one JSON line on stdout):
+  value         queries/s of the BF16 + recheck path (exact)
+  gcompare_per_s dense-equivalent rank comparisons per second (n * m * Q / t)
+  fp32_plain    the same batch with FP32 scoring and a plain compare (no
+                band, no recheck), timed once, and the speed-up over it
+  roofline      the screening count kernel (the dominant kernel): algorithmic
+                2 n m d flop per launch over its HIP-event duration, against
+                the BF16 dense MFMA peak
+  cpu_baseline  the CPU oracle on a bounded sample of users (all queries),
+                scaled to queries/s
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
+METRIC = "queries/s + Gcompare/s at |U|=|P|=1M,d=200, exact top-k; BF16+recheck vs FP32 plain"
+
+
+def log(msg: str) -> None:
+    sys.stderr.write("[bench %.1fs] %s\n" % (time.time() - T0, msg))
+    sys.stderr.flush()
+
+
+T0 = time.time()
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batch")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--score", default="bf16", choices=["bf16", "fp8", "f32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (scale for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2504_13446_amd import rkr, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
+        del src, dst
+    log("generating workload %s" % args.workload)
+    w = W.make(args.workload, n=args.n, m=args.m, nq=args.nq)
+    n, m, d, nq = w.n, w.m, w.d, w.nq
+    log("n=%d m=%d d=%d nq=%d dtype=%s" % (n, m, d, nq, w.dtype))
+    U = rkr.to_device(w.U, w.dtype)
+    P = rkr.to_device(w.P, w.dtype)
+    Q = rkr.to_device(w.Qv, w.dtype)
+    torch.cuda.synchronize()
+    t = time.time()
+    idx = rkr.Index(U, P, score=args.score)
+    torch.cuda.synchronize()
+    build_ms = (time.time() - t) * 1e3
+    log("index built in %.0f ms" % build_ms)
+
+    for i in range(args.warmup):
+        idx.query_batch(Q, w.k)
+        log("warmup %d: %s" % (i, _brief(idx.stats())))
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ids, rk, off = idx.query_batch(Q, w.k)
+        per.append(idx.stats())
+        log("step %d: %s" % (i, _brief(per[-1])))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    qps = nq * args.steps / (t1 - t0)
+    gcmp = n * m * nq / (ms_step / 1e3) / 1e9
+    st = per[-1]
+    screen_ms = float(np.mean([s["ms_screen_kernel"] for s in per]))
+    flop = 2.0 * n * m * d
+    achieved = flop / (screen_ms / 1e3) / 1e12 if screen_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[args.score]
+    ids_np = ids.cpu().numpy()
+    rk_np = rk.cpu().numpy()
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.score,
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_users": n, "m_items": m, "d": d, "queries": nq,
+                   "k": int(w.k[0]), "masters": w.dtype, "score": args.score, "mode": "exact",
+                   "generator": "iid N(0,I) directions x LogNormal(0,0.5) norms, seeded"},
+        "gcompare_per_s": round(gcmp, 1),
+        "build_ms": round(build_ms, 1),
+        "breakdown_ms": {k: round(st[k], 3) for k in ("ms_thresh", "ms_seed", "ms_screen", "ms_refine",
+                                                      "ms_select", "ms_total", "ms_screen_kernel",
+                                                      "ms_exact_kernel", "ms_recheck_kernel")},
+        "counters": {k: int(st[k]) for k in ("pairs", "seed_pairs", "survivors", "refined_pairs",
+                                             "uncertain", "flips", "compares", "screen_ctas")},
+        "roofline": {"kernel": "k_count<screen>", "bound": "mfma", "achieved": round(achieved, 2),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": None, "flop_per_launch": flop,
+                     "kernel_ms": round(screen_ms, 3)},
+    }
+
+    if not args.no_fp32:
+        log("plain FP32 comparator: building")
+        idx32 = rkr.Index(U, P, score="f32", recheck=False)
+        idx32.query_batch(Q, w.k)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ids32, rk32, _ = idx32.query_batch(Q, w.k)
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t) * 1e3
+        s32 = idx32.stats()
+        agree = float(np.mean(ids32.cpu().numpy() == ids_np))
+        out["fp32_plain"] = {"ms_per_step": round(ms32, 2), "queries_per_s": round(nq / (ms32 / 1e3), 3),
+                             "screen_kernel_ms": round(s32["ms_screen_kernel"], 2),
+                             "answer_ids_agreeing_with_exact": round(agree, 5)}
+        out["speedup_vs_fp32_plain"] = round(ms32 / ms_step, 3)
+        idx32.close()
+        log("plain FP32: %.1f ms/step" % ms32)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, ids_np, rk_np, off, args.cpu_users)
+    idx.close()
+    print(json.dumps(out))
+    sys.stdout.flush()
+    return 0
+
+
+def _brief(s: dict) -> str:
+    return "total %.1f ms (thresh %.1f seed %.1f screen %.1f [kernel %.1f] refine %.1f select %.1f) " \
+           "survivors %d uncertain %d" % (s["ms_total"], s["ms_thresh"], s["ms_seed"], s["ms_screen"],
+                                          s["ms_screen_kernel"], s["ms_refine"], s["ms_select"],
+                                          s["survivors"], s["uncertain"])
+
+
+def cpu_baseline(w, ids, rk, off, users: int) -> dict:
+    """The CPU oracle on a bounded sample: exact Def. 1 ranks of `users` random
+    users for every query of the batch (each user's m scores are shared by the
+    queries), scaled to the whole batch.  The sample also cross-checks the GPU
+    answer: a sampled user outside a query's answer may not beat its k-th rank."""
+    from oracle import oracle as O
+    threads = O.num_threads()
+    if users <= 0:
+        users = max(8, 2 * threads)
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(w.n, size=min(users, w.n), replace=False))
+    log("cpu baseline: %d users x %d queries x %d items on %d threads" % (sample.size, w.nq, w.m, threads))
+    Uw = O.widen(w.U)
+    Pw = O.widen(w.P)
+    Qw = O.widen(w.Qv)
+    t = time.perf_counter()
+    R = O.ranks(Uw, Pw, Qw, uids=sample)
+    sec = time.perf_counter() - t
+    frac = sample.size / w.n
+    qps = w.nq * frac / sec
+    bad = 0
+    for i in range(w.nq):
+        a_ids = ids[off[i]:off[i + 1]]
+        a_rk = rk[off[i]:off[i + 1]]
+        Rk, last = int(a_rk[-1]), int(a_ids[-1])
+        ins = set(a_ids.tolist())
+        for j, u in enumerate(sample):
+            r = int(R[i, j])
+            if u in ins:
+                bad += int(r != int(a_rk[list(a_ids).index(u)]))
+            elif r < Rk or (r == Rk and u < last):
+                bad += 1
+    log("cpu baseline: %.1f s, sample inconsistencies with the GPU answer: %d" % (sec, bad))
+    return {"value": round(qps, 6), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random users x all %d queries x all %d items (%.3g of the batch), %.1f s"
+                      % (sample.size, w.nq, w.m, frac, sec),
+            "sample_inconsistencies": bad}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

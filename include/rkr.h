@@ -101,6 +101,10 @@ typedef struct {
     int64_t approx_settled; /* approximate mode: queries settled without the exact fallback */
     double ms_thresh, ms_seed, ms_screen, ms_refine, ms_select, ms_total;
     double mlp_loss;        /* last training loss of the estimator (rkr_train)             */
+    double ms_screen_kernel;/* duration of the screening count kernel (HIP events)         */
+    double ms_exact_kernel; /* summed duration of the exact count kernels (HIP events)     */
+    double ms_recheck_kernel; /* summed duration of the FP64 recheck kernels (HIP events)  */
+    int64_t screen_ctas;    /* workgroups of the screening launch                           */
 } rkr_query_stats;
 
 /*

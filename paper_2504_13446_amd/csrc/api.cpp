@@ -68,6 +68,7 @@ struct rkr_index {
         candoff, cursor, qcount, flags, allpid;
     TaskSet ts_screen, ts_exact;
     int64_t emit_cap = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     rkr_query_opts qo{};
     rkr_query_stats stats{};
     // estimator
@@ -188,6 +189,8 @@ extern "C" void rkr_destroy(rkr_index *x) {
     for (DBuf *b : bufs) b->release();
     x->ts_screen.release();
     x->ts_exact.release();
+    for (auto &e : x->ev)
+        if (e) (void)hipEventDestroy(e);
     x->sc.release();
     est_release(x->est);
     delete x;
@@ -217,6 +220,20 @@ extern "C" const char *rkr_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // counting passes
 // ---------------------------------------------------------------------------
+static hipError_t ensure_events(rkr_index *x) {
+    for (auto &e : x->ev)
+        if (!e) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+    return hipSuccess;
+}
+// Elapsed milliseconds between two recorded events (after a stream sync).
+static double event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
 static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts) {
     CountArgs a{};
     a.plp = x->plp.as<uint8_t>();
@@ -257,6 +274,7 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts) {
 static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pids, int64_t N) {
     if (N <= 0) return RKR_OK;
     hipStream_t st = x->st;
+    HIPCK(ensure_events(x));
     TaskSet &ts = x->ts_exact;
     hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, ts, x->sc, st);
     if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
@@ -277,14 +295,21 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
         a.emit_cap = (unsigned long long)x->emit_cap;
         HIPCK(q_zero_at(pids, N, x->cnt.as<uint32_t>(), st));
         HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));   // emit counter (64-bit)
+        HIPCK(hipEventRecord(x->ev[0], st));
         HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, st));
+        HIPCK(hipEventRecord(x->ev[1], st));
         unsigned long long ne = 0;
         HIPCK(hipMemcpyAsync(&ne, x->ctr.p, 8, hipMemcpyDeviceToHost, st));
         HIPCK(hipStreamSynchronize(st));
+        x->stats.ms_exact_kernel += event_ms(x->ev[0], x->ev[1]);
         if (ne <= (unsigned long long)x->emit_cap) {
             x->stats.uncertain += (int64_t)ne;
+            HIPCK(hipEventRecord(x->ev[2], st));
             HIPCK(launch_recheck(x->emit.as<int2>(), (int64_t)ne, ps.pair_u, ps.t64, x->Um.p, x->Pm.p, x->d, x->mk,
                                  x->cnt.as<uint32_t>(), x->ctr.as<unsigned long long>() + 2, st));
+            HIPCK(hipEventRecord(x->ev[3], st));
+            HIPCK(hipStreamSynchronize(st));
+            x->stats.ms_recheck_kernel += event_ms(x->ev[2], x->ev[3]);
             return RKR_OK;
         }
         x->stats.emit_retries += 1;
@@ -449,7 +474,14 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->ts_screen, x->sc, st);
         if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
         CountArgs a = count_args(x, ps, x->ts_screen);
+        HIPCK(ensure_events(x));
+        HIPCK(hipEventRecord(x->ev[0], st));
         HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, st));
+        HIPCK(hipEventRecord(x->ev[1], st));
+        HIPCK(hipStreamSynchronize(st));
+        x->stats.ms_screen_kernel = event_ms(x->ev[0], x->ev[1]);
+        const int tpw = WAVES_PER_WG * x->nub * USER_BLOCK;
+        x->stats.screen_ctas = (x->ts_screen.ntask + tpw - 1) / tpw;
         TView tv{x->ts_screen.ntask, x->ts_screen.len, x->ts_screen.blk_base, x->ts_screen.ent_pid};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
     }
