@@ -323,8 +323,7 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
 // batch queries
 // ---------------------------------------------------------------------------
 static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k, const double *c,
-                            const int64_t *cand_off, const int32_t *cand_ids, int32_t *ids_out, int32_t *ranks_out,
-                            const float *pred) {
+                            const int64_t *cand_off, const int32_t *cand_ids, int32_t *ids_out, int32_t *ranks_out) {
     g_err.clear();
     if (!x) return fail(RKR_E_INVALID, "index is NULL");
     if (nq < 1) return fail(RKR_E_INVALID, "nq must be positive");
@@ -409,7 +408,19 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     // ---- 3. seeds
     std::vector<int64_t> seloff(nq + 1, 0), bestoff(nq + 1, 0);
     std::vector<int32_t> Sv(nq);
-    const int64_t mult = std::max(1, x->qo.seed_mult);
+    const bool use_est = x->qo.use_estimator != 0;
+    if (use_est && !x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
+    // approximate mode with estimator pruning: the candidates are the
+    // prune_mult * k users of best predicted rank, counted exactly; no screen
+    const bool pruned = c && use_est && x->qo.prune_mult > 0;
+    const float *pred = nullptr;
+    if (use_est) {
+        HIPCK(x->est.pred.ensure(npairs * 4));
+        HIPCK(est_infer(x->est, nullptr, nullptr, npairs, ps.pair_u, ps.t64, x->unorm3.as<double>(),
+                        x->est.pred.as<float>(), 0, 0, st));
+        pred = x->est.pred.as<float>();
+    }
+    const int64_t mult = pruned ? std::max(1, x->qo.prune_mult) : std::max(1, x->qo.seed_mult);
     for (int q = 0; q < nq; ++q) {
         S[q] = std::min<int64_t>(dom[q], std::min<int64_t>(4096, std::max<int64_t>(k[q], mult * k[q])));
         Sv[q] = (int32_t)S[q];
@@ -466,6 +477,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     // ---- 6. screen every pair against its bound
     bool need_screen = false;
     for (int q = 0; q < nq; ++q) need_screen |= dom[q] > S[q];
+    if (pruned) need_screen = false;
     int64_t nsurv = 0;
     HIPCK(x->surv.ensure(npairs * 4));
     if (need_screen) {
@@ -537,14 +549,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
 extern "C" rkr_status rkr_query_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k, const double *c,
                                       const int64_t *cand_off, const int32_t *cand_ids, int32_t *ids_out,
                                       int32_t *ranks_out) {
-    const float *pred = nullptr;
-    if (x && x->qo.use_estimator) {
-        if (!x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
-        rkr_status s = est_predict_for_query(x->est, nq, Qm, x->Um.p, x->n, x->d, x->mk, x->unorm3.as<double>(),
-                                             &pred, x->st);
-        if (s != RKR_OK) return s;
-    }
-    return run_batch(x, nq, Qm, k, c, cand_off, cand_ids, ids_out, ranks_out, pred);
+    return run_batch(x, nq, Qm, k, c, cand_off, cand_ids, ids_out, ranks_out);
 }
 
 extern "C" rkr_status rkr_query_exact(rkr_index *x, const void *q, int32_t k, int32_t *ids_out, int32_t *ranks_out) {
@@ -612,40 +617,198 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
 // ---------------------------------------------------------------------------
 // learned rank estimator
 // ---------------------------------------------------------------------------
+static rkr_status ensure_params(rkr_index *x) {
+    HIPCK(x->est.params.ensure(MLP_NPARAM * 4));
+    HIPCK(x->est.grads.ensure(MLP_NPARAM * 4));
+    HIPCK(x->est.adam_m.ensure(MLP_NPARAM * 4));
+    HIPCK(x->est.adam_v.ensure(MLP_NPARAM * 4));
+    return RKR_OK;
+}
+
+// Training data: for each training query, the pairs_per_query / 2 users of
+// best t/|u| plus pairs_per_query / 2 users spread uniformly over the user
+// ids (stratified, random offset per query); their exact ranks come from the
+// exact counting path.  Then E epochs of minibatch Adam on ln r.
 extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_t pairs_per_query, int32_t epochs,
                                 int32_t batch, float lr, uint64_t seed) {
     g_err.clear();
-    (void)nq; (void)Qm; (void)pairs_per_query; (void)epochs; (void)batch; (void)lr; (void)seed;
     if (!x) return fail(RKR_E_INVALID, "index is NULL");
-    return fail(RKR_E_UNSUPPORTED, "estimator training not available in this build");
+    if (!x->est.has_sketch) return fail(RKR_E_STATE, "index built without a sketch (sketch_samples = 0)");
+    if (nq < 1 || nq > 65535 || !Qm) return fail(RKR_E_INVALID, "nq must be in 1..65535 and Qm non-NULL");
+    if (pairs_per_query < 2 || epochs < 1 || batch < 1 || !(lr > 0.0f))
+        return fail(RKR_E_INVALID, "pairs_per_query >= 2, epochs >= 1, batch >= 1 and lr > 0 required");
+    hipStream_t st = x->st;
+    const int64_t n = x->n;
+    const int d = x->d;
+    const double t0 = now_ms();
+    x->sc.reset();
+    PairSet ps;
+    ps.nq = nq;
+    ps.dense = 1;
+    const int64_t npairs = n * nq;
+    ps.npairs = npairs;
+    HIPCK(x->pair_u.ensure(npairs * 4));
+    HIPCK(x->pair_q.ensure(npairs * 4));
+    HIPCK(x->t64.ensure(npairs * 8));
+    HIPCK(x->th.ensure(npairs * 4));
+    HIPCK(x->tl.ensure(npairs * 4));
+    HIPCK(x->tm.ensure(npairs * 4));
+    HIPCK(x->cnt.ensure(npairs * 4));
+    HIPCK(x->ctr.ensure(64));
+    ps.pair_u = x->pair_u.as<int32_t>();
+    ps.pair_q = x->pair_q.as<int32_t>();
+    ps.t64 = x->t64.as<double>();
+    ps.th = x->th.as<float>();
+    ps.tl = x->tl.as<float>();
+    ps.tm = x->tm.as<float>();
+    HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+    HIPCK(launch_check_values(Qm, (int64_t)nq * d, x->mk, x->flags.as<int>(), st));
+    HIPCK(launch_dense_pairs(n, nq, ps.pair_u, ps.pair_q, st));
+    HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    // best users by t/|u| (select) + stratified users, marked in a pair flag array
+    const int top = (int)std::min<int64_t>(std::min<int64_t>(pairs_per_query / 2, 4096), n);
+    const int strat = (int)std::min<int64_t>(pairs_per_query - pairs_per_query / 2, n);
+    std::vector<int64_t> segoff(nq + 1), seloff(nq + 1);
+    std::vector<int32_t> Sv(nq, top);
+    for (int q = 0; q <= nq; ++q) { segoff[q] = (int64_t)q * n; seloff[q] = (int64_t)q * top; }
+    HIPCK(x->segoff.ensure((nq + 1) * 8));
+    HIPCK(x->seloff.ensure((nq + 1) * 8));
+    HIPCK(x->sdev.ensure(nq * 4));
+    HIPCK(x->keys.ensure(npairs * 8));
+    HIPCK(x->sel.ensure((int64_t)nq * top * 8 + 8));
+    HIPCK(x->seedflag.ensure(npairs));
+    HIPCK(hipMemcpyAsync(x->segoff.p, segoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->seloff.p, seloff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->sdev.p, Sv.data(), nq * 4, hipMemcpyHostToDevice, st));
+    QView v{1, nq, n, x->segoff.as<int64_t>(), nullptr};
+    HIPCK(q_seed_keys(v, ps.pair_u, ps.t64, x->unorm3.as<double>(), nullptr, npairs, x->keys.as<uint64_t>(), st));
+    HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
+                        x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));
+    HIPCK(launch_fill_u8(x->seedflag.as<uint8_t>(), 0, npairs, st));
+    HIPCK(q_mark_selected(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), (int64_t)nq * top,
+                          x->seedflag.as<uint8_t>(), st));
+    HIPCK(est_mark_strided(nq, n, strat, seed, x->seedflag.as<uint8_t>(), st));
+    HIPCK(x->seedpid.ensure(npairs * 4));
+    int64_t N = 0;
+    HIPCK(q_compact_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), &N, x->sc, st));
+    HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 16, st));
+    rkr_status rs = exact_count(x, ps, x->seedpid.as<int32_t>(), N);
+    if (rs != RKR_OK) return rs;
+    // features and targets
+    HIPCK(x->est.feat.ensure(N * MLP_IN * 4));
+    HIPCK(x->est.targ.ensure(N * 4));
+    HIPCK(x->est.work.ensure(N * 8));
+    float *X = x->est.feat.as<float>();
+    float *z = x->est.targ.as<float>();
+    HIPCK(est_features(x->seedpid.as<int32_t>(), N, ps.pair_u, ps.t64, x->unorm3.as<double>(),
+                       x->est.sketch.as<float>(), x->cnt.as<uint32_t>(), X, z, st));
+    rs = ensure_params(x);
+    if (rs != RKR_OK) return rs;
+    HIPCK(launch_fill_u32(x->est.adam_m.as<uint32_t>(), 0, MLP_NPARAM, st));
+    HIPCK(launch_fill_u32(x->est.adam_v.as<uint32_t>(), 0, MLP_NPARAM, st));
+    HIPCK(est_init(x->est, z, N, seed, x->sc, st));
+    // minibatch Adam; epoch e visits the samples in the order (a_e i + b_e) mod N
+    int64_t *order = x->est.work.as<int64_t>();
+    double *lossd = (double *)x->sc.take(8);
+    if (!lossd) return fail(RKR_E_NOMEM, "scratch");
+    const int64_t B = std::min<int64_t>(batch, N);
+    int step = 0;
+    double last = 0.0;
+    static const int64_t primes[] = {1000003, 999983, 1299709, 1686049, 2750159, 3497861, 4256233, 5800079};
+    for (int e = 0; e < epochs; ++e) {
+        int64_t a = primes[e % 8];
+        while (N > 1 && std::__gcd(a, N) != 1) ++a;
+        HIPCK(est_perm(order, N, a % std::max<int64_t>(N, 1), (int64_t)(seed + 7919 * e) % std::max<int64_t>(N, 1), st));
+        double esum = 0.0;
+        for (int64_t off = 0; off < N; off += B) {
+            const int64_t nb = std::min<int64_t>(B, N - off);
+            HIPCK(est_fwd_bwd(x->est, X, z, order, N, off, nb, 1.0f / (float)nb, x->est.grads.as<float>(), lossd,
+                              x->sc, st));
+            HIPCK(est_adam(x->est, lr, ++step, st));
+            if (e == epochs - 1) {
+                double l = 0.0;
+                HIPCK(hipMemcpyAsync(&l, lossd, 8, hipMemcpyDeviceToHost, st));
+                HIPCK(hipStreamSynchronize(st));
+                esum += l;
+            }
+        }
+        if (e == epochs - 1) last = esum / (double)N;
+    }
+    HIPCK(hipStreamSynchronize(st));
+    x->est.trained = true;
+    x->est.last_loss = last;
+    x->stats = rkr_query_stats{};
+    x->stats.pairs = N;
+    x->stats.mlp_loss = last;
+    x->stats.ms_total = now_ms() - t0;
+    return RKR_OK;
 }
+
 extern "C" rkr_status rkr_predict(rkr_index *x, int32_t nq, const void *Qm, float *out) {
     g_err.clear();
-    (void)nq; (void)Qm; (void)out;
-    if (!x) return fail(RKR_E_INVALID, "index is NULL");
-    return fail(RKR_E_STATE, "estimator not trained");
+    if (!x || !Qm || !out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
+    if (nq < 1 || nq > 65535) return fail(RKR_E_INVALID, "nq must be in 1..65535");
+    hipStream_t st = x->st;
+    const int64_t n = x->n, npairs = n * nq;
+    x->sc.reset();
+    HIPCK(x->pair_u.ensure(npairs * 4));
+    HIPCK(x->pair_q.ensure(npairs * 4));
+    HIPCK(x->t64.ensure(npairs * 8));
+    HIPCK(x->th.ensure(npairs * 4));
+    HIPCK(x->tl.ensure(npairs * 4));
+    HIPCK(x->tm.ensure(npairs * 4));
+    HIPCK(launch_dense_pairs(n, nq, x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), st));
+    HIPCK(launch_thresh(x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), npairs, x->Um.p, Qm, x->d, x->mk,
+                        x->t64.as<double>(), x->th.as<float>(), x->tl.as<float>(), x->tm.as<float>(), st));
+    HIPCK(est_infer(x->est, nullptr, nullptr, npairs, x->pair_u.as<int32_t>(), x->t64.as<double>(),
+                    x->unorm3.as<double>(), out, nq, n, st));
+    HIPCK(hipStreamSynchronize(st));
+    return RKR_OK;
 }
+
 extern "C" rkr_status rkr_mlp_get(rkr_index *x, float *p) {
     g_err.clear();
-    (void)p;
-    if (!x) return fail(RKR_E_INVALID, "index is NULL");
-    return fail(RKR_E_UNSUPPORTED, "estimator not available in this build");
+    if (!x || !p) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->est.trained) return fail(RKR_E_STATE, "estimator has no parameters");
+    HIPCK(hipMemcpyAsync(p, x->est.params.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost, x->st));
+    HIPCK(hipStreamSynchronize(x->st));
+    return RKR_OK;
 }
+
 extern "C" rkr_status rkr_mlp_set(rkr_index *x, const float *p) {
     g_err.clear();
-    (void)p;
-    if (!x) return fail(RKR_E_INVALID, "index is NULL");
-    return fail(RKR_E_UNSUPPORTED, "estimator not available in this build");
+    if (!x || !p) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->est.has_sketch) return fail(RKR_E_STATE, "index built without a sketch (sketch_samples = 0)");
+    rkr_status rs = ensure_params(x);
+    if (rs != RKR_OK) return rs;
+    HIPCK(hipMemcpyAsync(x->est.params.p, p, MLP_NPARAM * 4, hipMemcpyHostToDevice, x->st));
+    HIPCK(hipStreamSynchronize(x->st));
+    x->est.trained = true;
+    return RKR_OK;
 }
+
 extern "C" rkr_status rkr_mlp_grad(rkr_index *x, const float *X, const float *z, int32_t N, float *g, double *loss) {
     g_err.clear();
-    (void)X; (void)z; (void)N; (void)g; (void)loss;
-    if (!x) return fail(RKR_E_INVALID, "index is NULL");
-    return fail(RKR_E_UNSUPPORTED, "estimator not available in this build");
+    if (!x || !X || !z || !g || !loss) return fail(RKR_E_INVALID, "NULL argument");
+    if (N < 1) return fail(RKR_E_INVALID, "N must be positive");
+    if (!x->est.trained) return fail(RKR_E_STATE, "estimator has no parameters");
+    x->sc.reset();
+    double *ld = (double *)x->sc.take(8);
+    if (!ld) return fail(RKR_E_NOMEM, "scratch");
+    HIPCK(est_fwd_bwd(x->est, X, z, nullptr, N, 0, N, 1.0f / (float)N, g, ld, x->sc, x->st));
+    double l = 0.0;
+    HIPCK(hipMemcpyAsync(&l, ld, 8, hipMemcpyDeviceToHost, x->st));
+    HIPCK(hipStreamSynchronize(x->st));
+    *loss = l / (double)N;
+    return RKR_OK;
 }
+
 extern "C" rkr_status rkr_sketch(rkr_index *x, float *out) {
     g_err.clear();
-    (void)out;
-    if (!x) return fail(RKR_E_INVALID, "index is NULL");
-    return fail(RKR_E_STATE, "index built without a sketch");
+    if (!x || !out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->est.has_sketch) return fail(RKR_E_STATE, "index built without a sketch");
+    HIPCK(hipMemcpyAsync(out, x->est.sketch.p, (size_t)x->n * SKETCH_LEVELS * 4, hipMemcpyDeviceToDevice, x->st));
+    HIPCK(hipStreamSynchronize(x->st));
+    return RKR_OK;
 }

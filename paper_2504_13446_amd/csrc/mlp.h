@@ -4,6 +4,9 @@
 #include "kernels.h"
 #include "rkr.h"
 
+#include <algorithm>
+#include <cmath>
+
 namespace rkr {
 
 constexpr int SKETCH_LEVELS = 16;
@@ -23,8 +26,18 @@ struct Estimator {
 
 rkr_status est_build_sketch(Estimator &e, const void *Um, int64_t n, const void *Pm_sorted, int64_t m, int d, int mk,
                             const double *unorm3, int samples, Scratch &sc, hipStream_t st);
-rkr_status est_predict_for_query(Estimator &e, int nq, const void *Qm, const void *Um, int64_t n, int d, int mk,
-                                 const double *unorm3, const float **pred_out, hipStream_t st);
+hipError_t est_features(const int32_t *pids, int64_t N, const int32_t *pair_u, const double *t64,
+                        const double *unorm3, const float *sketch, const uint32_t *cnt, float *X, float *z,
+                        hipStream_t st);
+hipError_t est_fwd_bwd(Estimator &e, const float *X, const float *z, const int64_t *order, int64_t N, int64_t off,
+                       int64_t nb, float scale, float *grad, double *loss_dev, Scratch &sc, hipStream_t st);
+hipError_t est_adam(Estimator &e, float lr, int t, hipStream_t st);
+hipError_t est_infer(Estimator &e, const float *X, const int32_t *pids, int64_t N, const int32_t *pair_u,
+                     const double *t64, const double *unorm3, float *out, int qmajor_nq, int64_t qmajor_n,
+                     hipStream_t st);
+hipError_t est_init(Estimator &e, const float *z, int64_t N, uint64_t seed, Scratch &sc, hipStream_t st);
+hipError_t est_perm(int64_t *order, int64_t N, int64_t a, int64_t b, hipStream_t st);
+hipError_t est_mark_strided(int nq, int64_t n, int per, uint64_t seed, uint8_t *flag, hipStream_t st);
 void est_release(Estimator &e);
 
 }  // namespace rkr

@@ -58,7 +58,7 @@ __global__ void k_seed_keys(QView v, const int32_t *pair_u, const double *t64, c
     int32_t pid = pid_of(v, q, i);
     float h;
     if (pred) {
-        h = pred[(int64_t)q * v.n + pair_u[pid]];
+        h = pred[pid];
     } else {
         double nu = unorm3[3 * (int64_t)pair_u[pid] + 2];
         h = nu > 0.0 ? (float)(-t64[pid] / nu) : 0.0f;

@@ -1,0 +1,138 @@
+"""GPU tests of the learned rank estimator against the FP64 references."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2504_13446_amd import rkr, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, dtype):
+    return rkr.to_device(x, dtype)
+
+
+def _rand_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for k in M.ORDER:
+        fan = M.SHAPES[k][-1] if len(M.SHAPES[k]) == 2 else 64
+        p[k] = rng.standard_normal(M.SHAPES[k]) * scale / np.sqrt(fan)
+    p["b3"][0] = 3.0
+    return p
+
+
+@pytest.fixture(scope="module")
+def lowrank():
+    w = W.make("single", n=3000, m=4000, nq=24)
+    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16", sketch_samples=512)
+    yield w, idx
+    idx.close()
+
+
+def test_sketch_bit_exact(lowrank):
+    w, idx = lowrank
+    got = idx.sketch().cpu().numpy()
+    S = 512
+    want = O.sketch(w.U, w.P, O.stratified_sample(w.P, S), O.sketch_positions(S)).astype(np.float32)
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+
+
+def test_gradient_matches_fp64_reference(lowrank):
+    w, idx = lowrank
+    p = _rand_params(1)
+    flat = M.flatten(p).astype(np.float32)
+    rkr.rkr_mlp_set(idx.h, flat)
+    p32 = M.unflatten(flat.astype(np.float64))       # the parameters as the GPU holds them
+    rng = np.random.default_rng(2)
+    N = 777                                           # several 64-sample blocks + a ragged tail
+    X = rng.standard_normal((N, 18)).astype(np.float32)
+    z = rng.uniform(0, 12, N).astype(np.float32)
+    g, loss = rkr.rkr_mlp_grad(idx.h, torch.from_numpy(X).cuda(), torch.from_numpy(z).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    L, gr = M.loss_and_grad(p32, X.astype(np.float64), z.astype(np.float64))
+    assert loss == pytest.approx(L, rel=1e-5)
+    ref = M.flatten(gr)
+    o = 0
+    for k in M.ORDER:
+        sz = int(np.prod(M.SHAPES[k]))
+        a, b = g[o:o + sz], ref[o:o + sz]
+        o += sz
+        assert np.linalg.norm(a - b) <= 1e-4 * max(np.linalg.norm(b), 1e-12), k
+
+
+def _abs_forward(p, X):
+    a1 = np.abs(X) @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    a2 = a1 @ np.abs(p["W2"]).T + np.abs(p["b2"])
+    return a2 @ np.abs(p["w3"]) + abs(p["b3"][0])
+
+
+def test_bf16_inference_within_rounding_bound(lowrank):
+    """BF16 inference vs the FP64 forward on the same features.  Rounding the
+    inputs, weights and hidden activations to BF16 (relative 2^-9 each) and
+    accumulating in FP32 moves each layer's pre-activation by at most about
+    2^-8 of its absolute sum; ReLU is 1-Lipschitz, so over three layers
+    |y_bf16 - y| <= 4 * 2^-8 * y_abs, y_abs being the forward pass of |W|, |b|, |x|."""
+    w, idx = lowrank
+    p = _rand_params(3)
+    flat = M.flatten(p).astype(np.float32)
+    rkr.rkr_mlp_set(idx.h, flat)
+    p32 = M.unflatten(flat.astype(np.float64))
+    Q = w.Qv[:5]
+    got = idx.predict(_dev(Q, "f32")).cpu().numpy()        # [5, n]
+    T = O.dots(w.U, Q)                                        # spec t(u,q), [n, 5]
+    nu = O.norms(w.U)
+    sk = idx.sketch().cpu().numpy().astype(np.float64)
+    for qi in range(Q.shape[0]):
+        X = np.concatenate([(T[:, qi] / nu).astype(np.float32)[:, None].astype(np.float64),
+                            nu.astype(np.float32)[:, None].astype(np.float64), sk], axis=1)
+        y, _ = M.forward(p32, X)
+        tol = 4 * 2.0 ** -8 * _abs_forward(p32, X)
+        err = np.abs(got[qi] - y)
+        assert np.all(err <= tol), (qi, err.max(), tol[np.argmax(err)])
+
+
+def test_training_and_exactness_with_estimator(lowrank):
+    w, idx = lowrank
+    Qtr = _dev(w.Qv[:16], "f32")
+    idx.train(Qtr, pairs_per_query=512, epochs=30, batch=256, lr=3e-3, seed=5)
+    st = idx.stats()
+    n_train = st["pairs"]
+    assert n_train >= 16 * 400
+    # the fitted loss is well below the variance of ln r (the loss of the best constant)
+    Rtr = O.ranks(w.U, w.P, w.Qv[:16])
+    var = np.var(np.log(Rtr.astype(np.float64)))
+    assert st["mlp_loss"] < 0.5 * var, (st["mlp_loss"], var)
+    # exact answers stay exact when the estimator picks the seeds
+    Qte = w.Qv[16:]
+    R = O.ranks(w.U, w.P, Qte)
+    ks = np.full(Qte.shape[0], 25, np.int32)
+    idx.configure(use_estimator=False)
+    a0 = idx.query_batch(_dev(Qte, "f32"), ks)
+    s0 = idx.stats()
+    idx.configure(use_estimator=True)
+    a1 = idx.query_batch(_dev(Qte, "f32"), ks)
+    s1 = idx.stats()
+    for (ids, rk, off) in (a0, a1):
+        ids = ids.cpu().numpy(); rk = rk.cpu().numpy()
+        for i in range(Qte.shape[0]):
+            wi, wr = O.topk(R[i], 25)
+            assert np.array_equal(ids[off[i]:off[i + 1]], wi) and np.array_equal(rk[off[i]:off[i + 1]], wr)
+    print("compares without / with estimator:", s0["compares"], s1["compares"],
+          "survivors:", s0["survivors"], s1["survivors"])
+    # approximate mode, verified (the screen is the judge): zero Def. 3 violations
+    ids, rk, off = idx.query_batch(_dev(Qte, "f32"), ks, c=1.5)
+    ids = ids.cpu().numpy()
+    for i in range(Qte.shape[0]):
+        _, wr = O.topk(R[i], 25)
+        assert O.def3_check(R[i][ids[off[i]:off[i + 1]]], wr, 1.5)[0] == 0
+    # approximate mode pruned by the estimator: ranks are exact for returned users
+    idx.configure(use_estimator=True, prune_mult=8)
+    ids, rk, off = idx.query_batch(_dev(Qte, "f32"), ks, c=1.5)
+    ids = ids.cpu().numpy(); rk = rk.cpu().numpy()
+    for i in range(Qte.shape[0]):
+        g = ids[off[i]:off[i + 1]]
+        assert np.array_equal(rk[off[i]:off[i + 1]], R[i][g])
+    idx.configure(use_estimator=False, prune_mult=0)
