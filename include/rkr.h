@@ -80,8 +80,10 @@ typedef struct {
     int32_t seed_mult;      /* seeds per query = seed_mult * k (default 2)               */
     int32_t use_estimator;  /* 1: order seeds by the trained estimator (needs rkr_train) */
     int32_t approx_refine;  /* approximate mode: max refine rounds (default 4)           */
-    int32_t prune_mult;     /* estimator pruning for the approximate mode: keep          */
-                            /* prune_mult * k users per query by predicted rank (0: off) */
+    int32_t prune_mult;     /* approximate mode only: answer from the prune_mult * k     */
+                            /* users per query of best predicted rank (estimator) or     */
+                            /* best u.q/|u| (no estimator), without the verifying screen */
+                            /* (0: off; Def. 3 is then not guaranteed)                   */
     int32_t screen_step;    /* reserved */
     int32_t reserved[3];
 } rkr_query_opts;
@@ -105,6 +107,7 @@ typedef struct {
     double ms_exact_kernel; /* summed duration of the exact count kernels (HIP events)     */
     double ms_recheck_kernel; /* summed duration of the FP64 recheck kernels (HIP events)  */
     int64_t screen_ctas;    /* workgroups of the screening launch                           */
+    int64_t screen_variant; /* tile variant the autotuner chose for the screening launch    */
 } rkr_query_stats;
 
 /*

@@ -22,8 +22,13 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -54,10 +59,68 @@ static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Online autotuner of the screening kernel's tile variant.  For each shape
+// key the first calls run the variants in turn and record their HIP-event
+// times; later calls use the fastest.  Decisions persist in a text cache
+// (RKR_AUTOTUNE_CACHE, default $HOME/.cache/rkr/autotune.txt), one
+// "key variant" line each, read at index build.
+struct Tuner {
+    std::map<std::string, int> best;
+    std::map<std::string, std::vector<double>> trials;
+    std::string path;
+    void load() {
+        const char *env = getenv("RKR_AUTOTUNE_CACHE");
+        const char *home = getenv("HOME");
+        if (env && *env) path = env;
+        else if (home && *home) path = std::string(home) + "/.cache/rkr/autotune.txt";
+        if (path.empty() || path == "off") return;
+        FILE *f = fopen(path.c_str(), "r");
+        if (!f) return;
+        char k[512];
+        int v;
+        while (fscanf(f, "%511s %d", k, &v) == 2) best[k] = v;
+        fclose(f);
+    }
+    void save(const std::string &key, int v) {
+        if (path.empty() || path == "off") return;
+        std::string dir = path.substr(0, path.find_last_of('/'));
+        if (!dir.empty()) {
+            std::string cur;
+            for (size_t i = 0; i < dir.size(); ++i) {
+                cur += dir[i];
+                if (dir[i] == '/' && i > 0) mkdir(cur.c_str(), 0755);
+            }
+            mkdir(dir.c_str(), 0755);
+        }
+        FILE *f = fopen(path.c_str(), "a");
+        if (!f) return;
+        fprintf(f, "%s %d\n", key.c_str(), v);
+        fclose(f);
+    }
+    int pick(const std::string &key, int nvar) {
+        if (nvar <= 1) return 0;
+        auto it = best.find(key);
+        if (it != best.end() && it->second < nvar) return it->second;
+        const auto &t = trials[key];
+        return (int)t.size() < nvar ? (int)t.size() : 0;
+    }
+    void record(const std::string &key, int variant, double ms, int nvar) {
+        if (nvar <= 1 || best.count(key)) return;
+        auto &t = trials[key];
+        if ((int)t.size() != variant) return;
+        t.push_back(ms);
+        if ((int)t.size() == nvar) {
+            int b = (int)(std::min_element(t.begin(), t.end()) - t.begin());
+            best[key] = b;
+            save(key, b);
+        }
+    }
+};
+
 struct rkr_index {
     int64_t n = 0, m = 0;
-    int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1, nib = 2, nub = 2;
-    int64_t nsteps = 0, nblk = 0;
+    int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1;
+    int64_t nblk32 = 0, nblk = 0;     // item blocks of 32 (real, allocated: a multiple of 4)
     hipStream_t st = nullptr;
     // index data
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
@@ -71,6 +134,7 @@ struct rkr_index {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     rkr_query_opts qo{};
     rkr_query_stats stats{};
+    Tuner tuner;
     // estimator
     Estimator est;
 };
@@ -109,15 +173,14 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     if (!x) return fail(RKR_E_NOMEM, "host allocation failed");
     x->n = n; x->m = m; x->d = d; x->dpad = dpad; x->nks = nks; x->sk = sk; x->recheck = recheck;
     x->mk = dt == RKR_BF16 ? MK_BF16 : MK_F32;
-    x->nib = nib_of(sk); x->nub = nub_of(sk, nks);
     x->st = st;
     x->qo.seed_mult = 2;
     x->qo.approx_refine = 4;
+    x->tuner.load();
     const int mes = dt == RKR_BF16 ? 2 : 4;
     const int es = elem_size(sk);
-    const int64_t step_items = 32 * x->nib;
-    x->nsteps = (m + step_items - 1) / step_items;
-    x->nblk = x->nsteps * x->nib;
+    x->nblk32 = (m + 31) / 32;
+    x->nblk = (x->nblk32 + 3) / 4 * 4;
     rkr_status rs = RKR_OK;
     auto body = [&]() -> rkr_status {
         HIPCK(x->Um.ensure((size_t)n * d * mes));
@@ -234,8 +297,16 @@ static double event_ms(hipEvent_t a, hipEvent_t b) {
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
     return (double)ms;
 }
-static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts) {
+static std::string tune_key(const rkr_index *x, int nq, int64_t npairs) {
+    char b[256];
+    snprintf(b, sizeof b, "gfx950/screen/sk%d/nks%d/n%lld/m%lld/nq%d/pairs%lld", x->sk, x->nks, (long long)x->n,
+             (long long)x->m, nq, (long long)npairs);
+    return b;
+}
+
+static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int variant) {
     CountArgs a{};
+    const int nib = nib_of(x->sk, x->nks, variant);
     a.plp = x->plp.as<uint8_t>();
     a.m = x->m;
     a.nks = x->nks;
@@ -258,8 +329,8 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts) {
     a.cap_total = ts.cap_total;
     a.bound = x->bound.as<int32_t>();
     a.nq = ps.nq;
-    a.nsteps = x->nsteps;
-    a.steps_per_split = x->nsteps;
+    a.nsteps = (x->nblk32 + nib - 1) / nib;
+    a.steps_per_split = a.nsteps;
     a.cnt_out = x->cnt.as<uint32_t>();
     a.emit = x->emit.as<int2>();
     a.emit_count = x->ctr.as<unsigned long long>();
@@ -276,16 +347,18 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
     hipStream_t st = x->st;
     HIPCK(ensure_events(x));
     TaskSet &ts = x->ts_exact;
-    hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, ts, x->sc, st);
+    hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, nullptr, ts, x->sc, st);
     if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
-    const int tpw = WAVES_PER_WG * x->nub * USER_BLOCK;
+    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, 0) * USER_BLOCK;
     const int64_t gx = (ts.ntask + tpw - 1) / tpw;
+    CountArgs a = count_args(x, ps, ts, 0);
+    const int64_t nsteps = a.nsteps;
     int64_t nsplit = (512 + gx - 1) / std::max<int64_t>(gx, 1);
-    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(x->nsteps, 1))));
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(nsteps, 1))));
     HIPCK(ts.reserve_entries(ts.cap_total, (int)nsplit));
-    CountArgs a = count_args(x, ps, ts);
-    a.steps_per_split = (x->nsteps + nsplit - 1) / nsplit;
-    nsplit = std::max<int64_t>(1, (x->nsteps + a.steps_per_split - 1) / std::max<int64_t>(a.steps_per_split, 1));
+    a.ent_cnt = ts.ent_cnt;
+    a.steps_per_split = (nsteps + nsplit - 1) / nsplit;
+    nsplit = std::max<int64_t>(1, (nsteps + a.steps_per_split - 1) / std::max<int64_t>(a.steps_per_split, 1));
     if (x->emit_cap == 0) {
         x->emit_cap = 1 << 22;
         HIPCK(x->emit.ensure((size_t)x->emit_cap * 8));
@@ -296,7 +369,7 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
         HIPCK(q_zero_at(pids, N, x->cnt.as<uint32_t>(), st));
         HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));   // emit counter (64-bit)
         HIPCK(hipEventRecord(x->ev[0], st));
-        HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, st));
+        HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, 0, st));
         HIPCK(hipEventRecord(x->ev[1], st));
         unsigned long long ne = 0;
         HIPCK(hipMemcpyAsync(&ne, x->ctr.p, 8, hipMemcpyDeviceToHost, st));
@@ -410,9 +483,10 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     std::vector<int32_t> Sv(nq);
     const bool use_est = x->qo.use_estimator != 0;
     if (use_est && !x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
-    // approximate mode with estimator pruning: the candidates are the
-    // prune_mult * k users of best predicted rank, counted exactly; no screen
-    const bool pruned = c && use_est && x->qo.prune_mult > 0;
+    // approximate mode with pruning: the candidates are the prune_mult * k
+    // users of best predicted rank (estimator) or best t/|u| (heuristic),
+    // counted exactly; no screen, so Def. 3 is not guaranteed
+    const bool pruned = c && x->qo.prune_mult > 0;
     const float *pred = nullptr;
     if (use_est) {
         HIPCK(x->est.pred.ensure(npairs * 4));
@@ -483,16 +557,21 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     if (need_screen) {
         HIPCK(x->allpid.ensure(npairs * 4));
         HIPCK(launch_iota(x->allpid.as<int32_t>(), npairs, st));
-        hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->ts_screen, x->sc, st);
+        hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
+                                   x->ts_screen, x->sc, st);
         if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
-        CountArgs a = count_args(x, ps, x->ts_screen);
+        const std::string key = tune_key(x, nq, npairs);
+        const int variant = x->tuner.pick(key, num_variants(x->sk, x->nks));
+        CountArgs a = count_args(x, ps, x->ts_screen, variant);
         HIPCK(ensure_events(x));
         HIPCK(hipEventRecord(x->ev[0], st));
-        HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, st));
+        HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, variant, st));
         HIPCK(hipEventRecord(x->ev[1], st));
         HIPCK(hipStreamSynchronize(st));
         x->stats.ms_screen_kernel = event_ms(x->ev[0], x->ev[1]);
-        const int tpw = WAVES_PER_WG * x->nub * USER_BLOCK;
+        x->tuner.record(key, variant, x->stats.ms_screen_kernel, num_variants(x->sk, x->nks));
+        x->stats.screen_variant = variant;
+        const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
         x->stats.screen_ctas = (x->ts_screen.ntask + tpw - 1) / tpw;
         TView tv{x->ts_screen.ntask, x->ts_screen.len, x->ts_screen.blk_base, x->ts_screen.ent_pid};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));

@@ -23,7 +23,9 @@
 // 1 + count exceeds the query's bound B[q] (a proven upper bound on the k-th
 // smallest rank): its rank is then > B >= R_k, so it cannot be in the answer
 // (Def. 2), the counts only grow.  This is the paper's Lemma 1 (2) filter
-// applied to exact partial counts.
+// applied to exact partial counts.  A screen entry holds (pid, th, rem) with
+// rem = B[q] - 1 - count: the pair dies when rem turns negative, and an entry
+// that keeps its slot only rewrites rem.
 #include "rkr_internal.h"
 
 namespace rkr {
@@ -221,40 +223,51 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
             const float eps = f32_round_up(E * (1.0 + 1e-9));
             int w = 0;
             const int mylen = len[ub];
+            // software pipeline: the fields of entry i + 1 load while entry i is counted
+            int pid_n = 0, rem_n = 0;
+            float th_n = 0.0f, tl_n = 0.0f, tm_n = 0.0f;
+            uint32_t cnt_n = 0;
+            auto fetch = [&](int i) {
+                const int64_t e = ebase[ub] + (int64_t)i * 32;
+                pid_n = a.ent_pid[e];
+                th_n = a.ent_th[e];
+                if constexpr (MODE == CM_SCREEN) {
+                    rem_n = (int)a.ent_cnt[e];
+                } else {
+                    tl_n = a.ent_tl[e];
+                    tm_n = a.ent_tm[e];
+                    cnt_n = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
+                }
+            };
+            if (mylen > 0) fetch(0);
             for (int i = 0; __ballot(i < mylen) != 0ull; ++i) {
                 const bool act = i < mylen;
                 const int64_t e = ebase[ub] + (int64_t)i * 32;
-                int pid = 0, q = 0;
-                uint32_t cnt = 0;
-                float th = 0.0f, tl = 0.0f, tmv = 0.0f;
-                if (act) {
-                    pid = a.ent_pid[e];
-                    th = a.ent_th[e];
-                    if constexpr (MODE == CM_SCREEN) {
-                        q = a.ent_q[e];
-                        cnt = a.ent_cnt[e];
-                    } else {
-                        tl = a.ent_tl[e];
-                        tmv = a.ent_tm[e];
-                        cnt = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
-                    }
-                }
+                // take every field of entry i before the prefetch overwrites them
+                const int pid = pid_n;
+                const float th = th_n;
+                const int rem_in = rem_n;
+                const float tl = tl_n, tmv = tm_n;
+                uint32_t cnt = cnt_n;
+                if (i + 1 < mylen) fetch(i + 1);
                 const float hi = a.plain ? th : f32_next_up(th + eps);
                 uint32_t c = 0;
                 if constexpr (MODE == CM_SCREEN) {
+                    // remaining budget: the pair dies when more than bound - 1 items are certainly above
 #pragma unroll
                     for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
                         for (int r = 0; r < 16; ++r) c += (acc[ib][ub][r] > hi) ? 1u : 0u;
                     c = pair_sum(c);
-                    cnt += c;
-                    const bool alive = act && (1u + cnt <= (uint32_t)a.bound[q]);
+                    const int rem = rem_in - (int)c;
+                    const bool alive = act && rem >= 0;
                     if (alive && half == 0) {
                         const int64_t ew = ebase[ub] + (int64_t)w * 32;
-                        a.ent_pid[ew] = pid;
-                        a.ent_q[ew] = q;
-                        a.ent_cnt[ew] = cnt;
-                        a.ent_th[ew] = th;
+                        a.ent_cnt[ew] = (uint32_t)rem;
+                        if (w != i) {
+                            a.ent_pid[ew] = pid;
+                            a.ent_th[ew] = th;
+                        }
                     }
                     w += alive ? 1 : 0;
                 } else {
@@ -342,13 +355,16 @@ static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Tile variants of the count kernel: v0 = (2 user blocks, 2 item blocks) per
+// wave, v1 = (1 user block, 4 item blocks): v1 halves the entry iterations
+// per compared score at the cost of no B-fragment reuse of the LDS A tile.
 template <int SK, int MODE>
-static hipError_t dispatch_nks(const CountArgs &a, int nsplit, hipStream_t st) {
+static hipError_t dispatch_nks(const CountArgs &a, int nsplit, int variant, hipStream_t st) {
     const int nks = a.nks;
     if constexpr (SK == SK_BF16) {
-        if (nks <= 4) return launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
-        if (nks <= 8) return launch_one<SK, MODE, 8, 2, 2>(a, nsplit, st);
-        if (nks <= 13) return launch_one<SK, MODE, 13, 2, 2>(a, nsplit, st);
+        if (nks <= 4) return variant ? launch_one<SK, MODE, 4, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
+        if (nks <= 8) return variant ? launch_one<SK, MODE, 8, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 8, 2, 2>(a, nsplit, st);
+        if (nks <= 13) return variant ? launch_one<SK, MODE, 13, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 13, 2, 2>(a, nsplit, st);
         if (nks <= 20) return launch_one<SK, MODE, 20, 1, 2>(a, nsplit, st);
     } else if constexpr (SK == SK_F32) {
         if (nks <= 32) return launch_one<SK, MODE, 32, 1, 1>(a, nsplit, st);
@@ -356,34 +372,43 @@ static hipError_t dispatch_nks(const CountArgs &a, int nsplit, hipStream_t st) {
         if (nks <= 100) return launch_one<SK, MODE, 100, 1, 1>(a, nsplit, st);
         if (nks <= 160) return launch_one<SK, MODE, 160, 1, 1>(a, nsplit, st);
     } else {
-        if (nks <= 2) return launch_one<SK, MODE, 2, 2, 2>(a, nsplit, st);
-        if (nks <= 4) return launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
+        if (nks <= 2) return variant ? launch_one<SK, MODE, 2, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 2, 2, 2>(a, nsplit, st);
+        if (nks <= 4) return variant ? launch_one<SK, MODE, 4, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
         if (nks <= 8) return launch_one<SK, MODE, 8, 1, 2>(a, nsplit, st);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, hipStream_t st) {
+hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int variant, hipStream_t st) {
     if (mode != CM_SCREEN && mode != CM_EXACT) return hipErrorInvalidValue;
     if (sk == SK_BF16)
-        return mode == CM_SCREEN ? dispatch_nks<SK_BF16, CM_SCREEN>(a, nsplit, st)
-                                 : dispatch_nks<SK_BF16, CM_EXACT>(a, nsplit, st);
+        return mode == CM_SCREEN ? dispatch_nks<SK_BF16, CM_SCREEN>(a, nsplit, variant, st)
+                                 : dispatch_nks<SK_BF16, CM_EXACT>(a, nsplit, variant, st);
     if (sk == SK_F32)
-        return mode == CM_SCREEN ? dispatch_nks<SK_F32, CM_SCREEN>(a, nsplit, st)
-                                 : dispatch_nks<SK_F32, CM_EXACT>(a, nsplit, st);
+        return mode == CM_SCREEN ? dispatch_nks<SK_F32, CM_SCREEN>(a, nsplit, variant, st)
+                                 : dispatch_nks<SK_F32, CM_EXACT>(a, nsplit, variant, st);
     if (sk == SK_FP8)
-        return mode == CM_SCREEN ? dispatch_nks<SK_FP8, CM_SCREEN>(a, nsplit, st)
-                                 : dispatch_nks<SK_FP8, CM_EXACT>(a, nsplit, st);
+        return mode == CM_SCREEN ? dispatch_nks<SK_FP8, CM_SCREEN>(a, nsplit, variant, st)
+                                 : dispatch_nks<SK_FP8, CM_EXACT>(a, nsplit, variant, st);
     return hipErrorInvalidValue;
 }
 
 // Largest supported k-step count per score kind (d <= KS * max).
 int max_nks(int sk) { return sk == SK_BF16 ? 20 : (sk == SK_F32 ? 160 : 8); }
-int nub_of(int sk, int nks) {
+int nub_of(int sk, int nks, int variant) {
     if (sk == SK_F32) return 1;
-    if (sk == SK_BF16) return nks <= 13 ? 2 : 1;
-    return nks <= 4 ? 2 : 1;
+    if (sk == SK_BF16) return (nks <= 13 && !variant) ? 2 : 1;
+    return (nks <= 4 && !variant) ? 2 : 1;
 }
-int nib_of(int sk) { return sk == SK_F32 ? 1 : 2; }
+int nib_of(int sk, int nks, int variant) {
+    if (sk == SK_F32) return 1;
+    if (sk == SK_BF16) return (nks <= 13 && variant) ? 4 : 2;
+    return (nks <= 4 && variant) ? 4 : 2;
+}
+int num_variants(int sk, int nks) {
+    if (sk == SK_BF16) return nks <= 13 ? 2 : 1;
+    if (sk == SK_FP8) return nks <= 4 ? 2 : 1;
+    return 1;
+}
 
 }  // namespace rkr

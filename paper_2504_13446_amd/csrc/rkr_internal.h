@@ -82,7 +82,7 @@ struct CountArgs {
     int32_t *ent_len;             // [ntask_pad]
     int32_t *ent_pid;
     int32_t *ent_q;
-    uint32_t *ent_cnt;            // [nsplit][cap_total]
+    uint32_t *ent_cnt;            // exact: [nsplit][cap_total] counts; screen: remaining budget
     float *ent_th;                // FP32 value >= the FP64 threshold
     float *ent_tl;                // FP32 value <= the FP64 threshold
     const float *ent_tm;          // fl32 of the FP64 threshold (plain verdict of near ties)
@@ -107,6 +107,6 @@ enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_INTERVAL = 2 };
 struct DeviceIndex;
 
 // launchers (count.hip)
-hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, hipStream_t st);
+hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int variant, hipStream_t st);
 
 }  // namespace rkr

@@ -257,8 +257,8 @@ __global__ void k_block_cap(const int32_t *len, int64_t nblk, int64_t *cap32) {
 __global__ void k_fill_entries(const int32_t *pids, int64_t N, const int32_t *flag, const int64_t *excl,
                                const int64_t *task_start, const int64_t *blk_base, const int32_t *pair_q,
                                const float *th, const float *tl, const float *tm, int plain,
-                               int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt, float *ent_th,
-                               float *ent_tl, float *ent_tm) {
+                               const int32_t *bound, int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt,
+                               float *ent_th, float *ent_tl, float *ent_tm) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     int64_t t = excl[i] + flag[i] - 1;
@@ -266,16 +266,18 @@ __global__ void k_fill_entries(const int32_t *pids, int64_t N, const int32_t *fl
     int64_t e = blk_base[t >> 5] + j * 32 + (t & 31);
     int32_t pid = pids[i];
     ent_pid[e] = pid;
-    ent_q[e] = pair_q[pid];
-    ent_cnt[e] = 0;
+    const int32_t q = pair_q[pid];
+    ent_q[e] = q;
+    // screen entries start with the remaining budget B[q] - 1, exact ones with count 0
+    ent_cnt[e] = bound ? (uint32_t)(bound[q] - 1) : 0u;
     // plain mode compares the score with fl32(t) itself: both edges = fl32(t)
     ent_th[e] = plain ? tm[pid] : th[pid];
     ent_tl[e] = plain ? tm[pid] : tl[pid];
     ent_tm[e] = tm[pid];
 }
 
-hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, TaskSet &ts,
-                       Scratch &sc, hipStream_t st) {
+hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, const int32_t *bound,
+                       TaskSet &ts, Scratch &sc, hipStream_t st) {
     ts.ntask = 0;
     ts.ntask_pad = 0;
     ts.cap_total = 0;
@@ -307,8 +309,8 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     if ((e = ts.reserve_entries(cap_total)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_entries, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, flag, excl, task_start,
-                       ts.blk_base, ps.pair_q, ps.th, ps.tl, ps.tm, plain, ts.ent_pid, ts.ent_q, ts.ent_cnt,
-                       ts.ent_th, ts.ent_tl, ts.ent_tm);
+                       ts.blk_base, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound, ts.ent_pid, ts.ent_q,
+                       ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     ts.ntask = ntask;
     ts.ntask_pad = ntask_pad;
     ts.cap_total = cap_total;
