@@ -137,7 +137,8 @@ def main() -> int:
                                                       "ms_select", "ms_total", "ms_screen_kernel",
                                                       "ms_exact_kernel", "ms_recheck_kernel")},
         "counters": {k: int(st[k]) for k in ("pairs", "seed_pairs", "survivors", "refined_pairs",
-                                             "uncertain", "flips", "compares", "screen_ctas")},
+                                             "uncertain", "flips", "compares", "compare_slots", "screen_ctas",
+                                             "screen_variant")},
         "roofline": {"kernel": "k_count<screen>", "bound": "mfma", "achieved": round(achieved, 2),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None, "flop_per_launch": flop,
@@ -185,7 +186,7 @@ def cpu_baseline(w, ids, rk, off, users: int) -> dict:
     from oracle import oracle as O
     threads = O.num_threads()
     if users <= 0:
-        users = max(8, 2 * threads)
+        users = max(64, 24 * threads)
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(w.n, size=min(users, w.n), replace=False))
     log("cpu baseline: %d users x %d queries x %d items on %d threads" % (sample.size, w.nq, w.m, threads))

@@ -108,6 +108,8 @@ typedef struct {
     double ms_recheck_kernel; /* summed duration of the FP64 recheck kernels (HIP events)  */
     int64_t screen_ctas;    /* workgroups of the screening launch                           */
     int64_t screen_variant; /* tile variant the autotuner chose for the screening launch    */
+    int64_t compare_slots;  /* lane slots of the compare loops (active or idle): compares / */
+                            /* compare_slots is the SIMD efficiency of the entry loops      */
 } rkr_query_stats;
 
 /*

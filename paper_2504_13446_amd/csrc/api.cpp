@@ -467,7 +467,10 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     ps.th = x->th.as<float>();
     ps.tl = x->tl.as<float>();
     ps.tm = x->tm.as<float>();
-    HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    if (dense)
+        HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    else
+        HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
     {
         int flags = 0;
         HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
@@ -614,6 +617,12 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(hipStreamSynchronize(st));
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
+    {
+        unsigned long long slots = 0;
+        HIPCK(hipMemcpyAsync(&slots, x->ctr.as<unsigned long long>() + 3, 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        x->stats.compare_slots = (int64_t)slots;
+    }
     const double t5 = now_ms();
     x->stats.ms_select = t5 - t4;
     x->stats.ms_total = t5 - t0;
@@ -743,7 +752,7 @@ extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(Qm, (int64_t)nq * d, x->mk, x->flags.as<int>(), st));
     HIPCK(launch_dense_pairs(n, nq, ps.pair_u, ps.pair_q, st));
-    HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
     // best users by t/|u| (select) + stratified users, marked in a pair flag array
     const int top = (int)std::min<int64_t>(std::min<int64_t>(pairs_per_query / 2, 4096), n);
     const int strat = (int)std::min<int64_t>(pairs_per_query - pairs_per_query / 2, n);
@@ -838,8 +847,8 @@ extern "C" rkr_status rkr_predict(rkr_index *x, int32_t nq, const void *Qm, floa
     HIPCK(x->tl.ensure(npairs * 4));
     HIPCK(x->tm.ensure(npairs * 4));
     HIPCK(launch_dense_pairs(n, nq, x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), st));
-    HIPCK(launch_thresh(x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), npairs, x->Um.p, Qm, x->d, x->mk,
-                        x->t64.as<double>(), x->th.as<float>(), x->tl.as<float>(), x->tm.as<float>(), st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), x->th.as<float>(),
+                              x->tl.as<float>(), x->tm.as<float>(), st));
     HIPCK(est_infer(x->est, nullptr, nullptr, npairs, x->pair_u.as<int32_t>(), x->t64.as<double>(),
                     x->unorm3.as<double>(), out, nq, n, st));
     HIPCK(hipStreamSynchronize(st));

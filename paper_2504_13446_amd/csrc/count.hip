@@ -147,7 +147,7 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
     for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
     if (!__syncthreads_or(any_live) || s_begin >= s_end) return;
 
-    uint64_t ncmp = 0;
+    uint64_t ncmp = 0, nslot = 0;
 
     // ---- prologue: stage the first step (direct global -> LDS, 16 bytes per lane)
     stage_step<LOADS_MAX>(a.plp + s_begin * (int64_t)step_bytes, lds, step_bytes, tid);
@@ -307,6 +307,7 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
                     if (act && half == 0) a.ent_cnt[(int64_t)split * a.cap_total + e] = cnt;
                 }
                 ncmp += act ? (uint64_t)(NIB * 16) : 0ull;
+                nslot += (uint64_t)(NIB * 16);
             }
             if constexpr (MODE == CM_SCREEN) len[ub] = w;
         }
@@ -334,10 +335,16 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
         }
     }
     // executed compares (both lanes of a pair count their own items)
-    uint64_t tot = ncmp;
+    uint64_t tot = ncmp, tslot = nslot;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
-    if (lane == 0 && a.stat) atomicAdd(a.stat, (unsigned long long)tot);
+    for (int o = 32; o >= 1; o >>= 1) {
+        tot += __shfl_xor(tot, o, 64);
+        tslot += __shfl_xor(tslot, o, 64);
+    }
+    if (lane == 0 && a.stat) {
+        atomicAdd(a.stat, (unsigned long long)tot);
+        atomicAdd(a.stat + 2, (unsigned long long)tslot);   // lane slots, active or not
+    }
 }
 
 template <int SK, int MODE, int NKS, int NUB, int NIB>

@@ -114,6 +114,8 @@ hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
                          const void *Qm, int d, int mk, double *t64, float *th, float *tl, float *tm,
                          hipStream_t st);
+hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
+                               float *th, float *tl, float *tm, hipStream_t st);
 hipError_t launch_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, const double *t64, const void *Um,
                           const void *Pm, int d, int mk, uint32_t *cnt, unsigned long long *flips,
                           hipStream_t st);

@@ -245,6 +245,54 @@ __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
     tm[i] = (float)acc;
 }
 
+// Dense thresholds, register-tiled: a block computes 64 users x 64 queries
+// (4 x 4 per thread) with both operands staged in LDS as doubles, 32
+// dimensions at a time; every dot still runs its fma chain in dimension
+// order, so the values equal the per-pair kernel's.  pid = u * nq + q.
+__global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk,
+                                                      double *t64, float *th, float *tl, float *tm) {
+    __shared__ double su[32][65];
+    __shared__ double sq[32][65];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t ub = (int64_t)blockIdx.y * 64;
+    const int qb = blockIdx.x * 64;
+    double acc[4][4];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = 0; k0 < d; k0 += 32) {
+        for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+            const int r = e >> 5, kk = e & 31;
+            const int64_t u = ub + r;
+            const int q = qb + r;
+            su[kk][r] = (k0 + kk < d && u < n) ? master_elem(Um, mk, u * d + k0 + kk) : 0.0;
+            sq[kk][r] = (k0 + kk < d && q < nq) ? master_elem(Qm, mk, (int64_t)q * d + k0 + kk) : 0.0;
+        }
+        __syncthreads();
+        const int kmax = min(32, d - k0);
+        for (int kk = 0; kk < kmax; ++kk) {
+            double a[4], b[4];
+            for (int t = 0; t < 4; ++t) { a[t] = su[kk][ty * 4 + t]; b[t] = sq[kk][tx * 4 + t]; }
+            for (int x = 0; x < 4; ++x)
+                for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+        }
+        __syncthreads();
+    }
+    for (int x = 0; x < 4; ++x) {
+        const int64_t u = ub + ty * 4 + x;
+        if (u >= n) continue;
+        for (int y = 0; y < 4; ++y) {
+            const int q = qb + tx * 4 + y;
+            if (q >= nq) continue;
+            const int64_t i = u * nq + q;
+            const double v = acc[x][y];
+            t64[i] = v;
+            th[i] = f32_round_up(v);
+            tl[i] = f32_round_down(v);
+            tm[i] = (float)v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP64 recheck of near ties: one thread per emitted (pair, item) record.
 // The item id is in sorted order; its master row sits in Pm_sorted.
@@ -348,6 +396,14 @@ hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_thresh, dim3(nblocks(npairs, 256)), dim3(256), 0, st, pair_u, pair_q, npairs,
                        Um, Qm, d, mk, t64, th, tl, tm);
+    return hipGetLastError();
+}
+
+hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
+                               float *th, float *tl, float *tm, hipStream_t st) {
+    if (n <= 0 || nq <= 0) return hipSuccess;
+    dim3 g((unsigned)((nq + 63) / 64), (unsigned)((n + 63) / 64));
+    hipLaunchKernelGGL(k_thresh_dense, g, dim3(256), 0, st, Um, n, Qm, nq, d, mk, t64, th, tl, tm);
     return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ class QueryStats(ctypes.Structure):
         [(n, ctypes.c_double) for n in ("ms_thresh", "ms_seed", "ms_screen", "ms_refine", "ms_select",
                                         "ms_total", "mlp_loss", "ms_screen_kernel", "ms_exact_kernel",
                                         "ms_recheck_kernel")] + [("screen_ctas", ctypes.c_int64),
-                                                             ("screen_variant", ctypes.c_int64)]
+                                                             ("screen_variant", ctypes.c_int64),
+                                                             ("compare_slots", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
