@@ -13,12 +13,15 @@
 //                 1 + certain count > X_q (the paper's Lemma 1 (2))
 //   7. refine     exact count of the pairs still live after the screen
 //   8. answer     per query the k best (rank, id) among seeds and survivors
-// Exactness: a dropped pair has rank > X_q >= ... (see DESIGN notes in the
-// header of count.hip); every user that can be in the answer is counted
-// exactly.  Approximate mode: a dropped pair has rank > B_q / c >= a_i / c for
-// every i <= k, where a_i is the i-th rank of the returned set, so the i-th
-// smallest rank over all users is >= a_i / c unless it is a counted user, in
-// which case it is <= a_i; either way Def. 3 holds.
+// Exactness: a dropped pair has rank > X_q = B_q >= the k-th rank of the
+// returned set (the count kernel only drops a pair once its certain count,
+// a lower bound of the exact one, shows it), so it is strictly worse than
+// every returned user; every user that can be in the answer is counted
+// exactly.  Approximate mode: a dropped pair has rank > floor(B_q / c), so
+// c * rank > B_q >= a_i for every i <= k (a_i: the i-th rank of the returned
+// set); the i-th smallest rank over all users either belongs to a counted user,
+// and then a_i is at most it, or to a dropped one, and then a_i < c times it:
+// Def. 3 holds either way.
 #include <math.h>
 #include <string.h>
 
@@ -349,9 +352,10 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
     TaskSet &ts = x->ts_exact;
     hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, nullptr, ts, x->sc, st);
     if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
-    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, 0) * USER_BLOCK;
+    const int xv = x->sk == SK_F32 ? 0 : 2;     // exact passes: low-register tile
+    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
     const int64_t gx = (ts.ntask + tpw - 1) / tpw;
-    CountArgs a = count_args(x, ps, ts, 0);
+    CountArgs a = count_args(x, ps, ts, xv);
     const int64_t nsteps = a.nsteps;
     int64_t nsplit = (512 + gx - 1) / std::max<int64_t>(gx, 1);
     nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(nsteps, 1))));
@@ -369,7 +373,7 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
         HIPCK(q_zero_at(pids, N, x->cnt.as<uint32_t>(), st));
         HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));   // emit counter (64-bit)
         HIPCK(hipEventRecord(x->ev[0], st));
-        HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, 0, st));
+        HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, xv, st));
         HIPCK(hipEventRecord(x->ev[1], st));
         unsigned long long ne = 0;
         HIPCK(hipMemcpyAsync(&ne, x->ctr.p, 8, hipMemcpyDeviceToHost, st));

@@ -272,18 +272,25 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
                     w += alive ? 1 : 0;
                 } else {
                     const float lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
-                    uint32_t umask = 0, pmask = 0;
+                    uint32_t umask = 0;
 #pragma unroll
                     for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
                             const float s = acc[ib][ub][r];
-                            c += (s > hi) ? 1u : 0u;
-                            umask |= ((s >= lo) && (s <= hi)) ? (1u << (ib * 16 + r)) : 0u;
-                            pmask |= (s > tmv) ? (1u << (ib * 16 + r)) : 0u;
+                            const bool gt = s > hi;
+                            c += gt ? 1u : 0u;
+                            umask |= (!gt && s >= lo) ? (1u << (ib * 16 + r)) : 0u;
                         }
                     if (!act) umask = 0;
                     if (__ballot(umask != 0) != 0ull) {
+                        // rare: the plain FP32 verdicts (score > fl32(t)) of this entry's scores
+                        uint32_t pmask = 0;
+#pragma unroll
+                        for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                            for (int r = 0; r < 16; ++r)
+                                pmask |= (acc[ib][ub][r] > tmv) ? (1u << (ib * 16 + r)) : 0u;
                         const uint32_t nu = __popc(umask);
                         const uint32_t incl = wave_incl_scan(nu, lane);
                         const uint32_t total = __shfl(incl, 63, 64);
@@ -362,26 +369,43 @@ static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Tile variants of the count kernel: v0 = (2 user blocks, 2 item blocks) per
-// wave, v1 = (1 user block, 4 item blocks): v1 halves the entry iterations
-// per compared score at the cost of no B-fragment reuse of the LDS A tile.
+// Tile variants of the count kernel (user blocks x item blocks per wave):
+// v0 = 2 x 2, v1 = 1 x 4, v2 = 1 x 2.  v1 halves the entry iterations per
+// compared score at the cost of no reuse of an LDS A fragment across user
+// blocks; v2 is the low-register tile of the exact passes (their near-tie
+// masks hold 64 items per step).
 template <int SK, int MODE>
 static hipError_t dispatch_nks(const CountArgs &a, int nsplit, int variant, hipStream_t st) {
     const int nks = a.nks;
     if constexpr (SK == SK_BF16) {
-        if (nks <= 4) return variant ? launch_one<SK, MODE, 4, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
-        if (nks <= 8) return variant ? launch_one<SK, MODE, 8, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 8, 2, 2>(a, nsplit, st);
-        if (nks <= 13) return variant ? launch_one<SK, MODE, 13, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 13, 2, 2>(a, nsplit, st);
-        if (nks <= 20) return launch_one<SK, MODE, 20, 1, 2>(a, nsplit, st);
+        if (variant == 2) {
+            if (nks <= 4) return launch_one<SK, MODE, 4, 1, 2>(a, nsplit, st);
+            if (nks <= 8) return launch_one<SK, MODE, 8, 1, 2>(a, nsplit, st);
+            if (nks <= 13) return launch_one<SK, MODE, 13, 1, 2>(a, nsplit, st);
+            if (nks <= 20) return launch_one<SK, MODE, 20, 1, 2>(a, nsplit, st);
+        }
+        if constexpr (MODE == CM_SCREEN) {
+            if (nks <= 4) return variant ? launch_one<SK, MODE, 4, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
+            if (nks <= 8) return variant ? launch_one<SK, MODE, 8, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 8, 2, 2>(a, nsplit, st);
+            if (nks <= 13) return variant ? launch_one<SK, MODE, 13, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 13, 2, 2>(a, nsplit, st);
+            if (nks <= 20) return launch_one<SK, MODE, 20, 1, 2>(a, nsplit, st);
+        }
     } else if constexpr (SK == SK_F32) {
         if (nks <= 32) return launch_one<SK, MODE, 32, 1, 1>(a, nsplit, st);
         if (nks <= 64) return launch_one<SK, MODE, 64, 1, 1>(a, nsplit, st);
         if (nks <= 100) return launch_one<SK, MODE, 100, 1, 1>(a, nsplit, st);
         if (nks <= 160) return launch_one<SK, MODE, 160, 1, 1>(a, nsplit, st);
     } else {
-        if (nks <= 2) return variant ? launch_one<SK, MODE, 2, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 2, 2, 2>(a, nsplit, st);
-        if (nks <= 4) return variant ? launch_one<SK, MODE, 4, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
-        if (nks <= 8) return launch_one<SK, MODE, 8, 1, 2>(a, nsplit, st);
+        if (variant == 2) {
+            if (nks <= 2) return launch_one<SK, MODE, 2, 1, 2>(a, nsplit, st);
+            if (nks <= 4) return launch_one<SK, MODE, 4, 1, 2>(a, nsplit, st);
+            if (nks <= 8) return launch_one<SK, MODE, 8, 1, 2>(a, nsplit, st);
+        }
+        if constexpr (MODE == CM_SCREEN) {
+            if (nks <= 2) return variant ? launch_one<SK, MODE, 2, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 2, 2, 2>(a, nsplit, st);
+            if (nks <= 4) return variant ? launch_one<SK, MODE, 4, 1, 4>(a, nsplit, st) : launch_one<SK, MODE, 4, 2, 2>(a, nsplit, st);
+            if (nks <= 8) return launch_one<SK, MODE, 8, 1, 2>(a, nsplit, st);
+        }
     }
     return hipErrorInvalidValue;
 }
@@ -403,14 +427,15 @@ hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int va
 // Largest supported k-step count per score kind (d <= KS * max).
 int max_nks(int sk) { return sk == SK_BF16 ? 20 : (sk == SK_F32 ? 160 : 8); }
 int nub_of(int sk, int nks, int variant) {
-    if (sk == SK_F32) return 1;
-    if (sk == SK_BF16) return (nks <= 13 && !variant) ? 2 : 1;
-    return (nks <= 4 && !variant) ? 2 : 1;
+    if (sk == SK_F32 || variant != 0) return 1;
+    if (sk == SK_BF16) return nks <= 13 ? 2 : 1;
+    return nks <= 4 ? 2 : 1;
 }
 int nib_of(int sk, int nks, int variant) {
     if (sk == SK_F32) return 1;
-    if (sk == SK_BF16) return (nks <= 13 && variant) ? 4 : 2;
-    return (nks <= 4 && variant) ? 4 : 2;
+    if (variant != 1) return 2;
+    if (sk == SK_BF16) return nks <= 13 ? 4 : 2;
+    return nks <= 4 ? 4 : 2;
 }
 int num_variants(int sk, int nks) {
     if (sk == SK_BF16) return nks <= 13 ? 2 : 1;
