@@ -48,7 +48,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)

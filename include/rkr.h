@@ -107,7 +107,9 @@ typedef struct {
     double ms_exact_kernel; /* summed duration of the exact count kernels (HIP events)     */
     double ms_recheck_kernel; /* summed duration of the FP64 recheck kernels (HIP events)  */
     int64_t screen_ctas;    /* workgroups of the screening launch                           */
-    int64_t screen_variant; /* tile variant the autotuner chose for the screening launch    */
+    int64_t screen_variant; /* launch candidate the autotuner chose for the screening pass: */
+                            /* tile variant (v % n), persistent grid if v >= n (n = tile    */
+                            /* variants of the score kind)                                  */
     int64_t compare_slots;  /* lane slots of the compare loops (active or idle): compares / */
                             /* compare_slots is the SIMD efficiency of the entry loops      */
 } rkr_query_stats;

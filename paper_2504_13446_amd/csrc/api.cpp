@@ -124,6 +124,7 @@ struct rkr_index {
     int64_t n = 0, m = 0;
     int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1;
     int64_t nblk32 = 0, nblk = 0;     // item blocks of 32 (real, allocated: a multiple of 4)
+    int num_cus = 256;
     hipStream_t st = nullptr;
     // index data
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
@@ -180,6 +181,12 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     x->qo.seed_mult = 2;
     x->qo.approx_refine = 4;
     x->tuner.load();
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            x->num_cus = cus;
+    }
     const int mes = dt == RKR_BF16 ? 2 : 4;
     const int es = elem_size(sk);
     x->nblk32 = (m + 31) / 32;
@@ -302,7 +309,7 @@ static double event_ms(hipEvent_t a, hipEvent_t b) {
 }
 static std::string tune_key(const rkr_index *x, int nq, int64_t npairs) {
     char b[256];
-    snprintf(b, sizeof b, "gfx950/screen/sk%d/nks%d/n%lld/m%lld/nq%d/pairs%lld", x->sk, x->nks, (long long)x->n,
+    snprintf(b, sizeof b, "gfx950/screen2/sk%d/nks%d/n%lld/m%lld/nq%d/pairs%lld", x->sk, x->nks, (long long)x->n,
              (long long)x->m, nq, (long long)npairs);
     return b;
 }
@@ -567,19 +574,29 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
                                    x->ts_screen, x->sc, st);
         if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
+        // candidates: each tile variant, launched as a grid or as a persistent grid
         const std::string key = tune_key(x, nq, npairs);
-        const int variant = x->tuner.pick(key, num_variants(x->sk, x->nks));
+        const int ntv = num_variants(x->sk, x->nks);
+        const int cand = x->tuner.pick(key, 2 * ntv);
+        const int variant = cand % ntv;
+        const bool persistent = cand >= ntv;
         CountArgs a = count_args(x, ps, x->ts_screen, variant);
+        if (persistent) {
+            HIPCK(launch_fill_u32(x->ctr.as<uint32_t>() + 8, 0, 2, st));
+            a.tile_counter = x->ctr.as<unsigned long long>() + 4;
+            a.persistent_ctas = x->num_cus;
+        }
         HIPCK(ensure_events(x));
         HIPCK(hipEventRecord(x->ev[0], st));
         HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, variant, st));
         HIPCK(hipEventRecord(x->ev[1], st));
         HIPCK(hipStreamSynchronize(st));
         x->stats.ms_screen_kernel = event_ms(x->ev[0], x->ev[1]);
-        x->tuner.record(key, variant, x->stats.ms_screen_kernel, num_variants(x->sk, x->nks));
-        x->stats.screen_variant = variant;
+        x->tuner.record(key, cand, x->stats.ms_screen_kernel, 2 * ntv);
+        x->stats.screen_variant = cand;
         const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
-        x->stats.screen_ctas = (x->ts_screen.ntask + tpw - 1) / tpw;
+        x->stats.screen_ctas = persistent ? std::min<int64_t>(x->num_cus, (x->ts_screen.ntask + tpw - 1) / tpw)
+                                          : (x->ts_screen.ntask + tpw - 1) / tpw;
         TView tv{x->ts_screen.ntask, x->ts_screen.len, x->ts_screen.blk_base, x->ts_screen.ent_pid};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
     }

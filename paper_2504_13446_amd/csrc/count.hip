@@ -28,6 +28,8 @@
 // that keeps its slot only rewrites rem.
 #include "rkr_internal.h"
 
+#include <algorithm>
+
 namespace rkr {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -86,7 +88,8 @@ __device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_byt
 }
 
 template <int SK, int MODE, int NKS, int NUB, int NIB>
-__global__ __launch_bounds__(512) void k_count(CountArgs a) {
+__device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, uint64_t &ncmp,
+                                  uint64_t &nslot) {
     using FT = typename FragT<SK>::T;
     constexpr int FB = frag_fb(SK);
     constexpr int KS = frag_ks(SK);
@@ -95,7 +98,6 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * FB;
     constexpr int LOADS_MAX = (STEP_BYTES_MAX + 512 * 16 - 1) / (512 * 16);
 
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int nks = a.nks;
     const int step_bytes = NIB * nks * 64 * FB;
     const int tid = threadIdx.x;
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
     FT bfrag[NUB][NKS];
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) {
-        int64_t t = (int64_t)blockIdx.x * TASKS_PER_WG + (wave * NUB + ub) * USER_BLOCK + l32;
+        int64_t t = tile * TASKS_PER_WG + (wave * NUB + ub) * USER_BLOCK + l32;
         tix[ub] = t;
         int u = (t < a.ntask) ? a.task_user[t] : -1;
         uid[ub] = u;
@@ -146,8 +148,6 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
     if (!__syncthreads_or(any_live) || s_begin >= s_end) return;
-
-    uint64_t ncmp = 0, nslot = 0;
 
     // ---- prologue: stage the first step (direct global -> LDS, 16 bytes per lane)
     stage_step<LOADS_MAX>(a.plp + s_begin * (int64_t)step_bytes, lds, step_bytes, tid);
@@ -341,6 +341,30 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
             }
         }
     }
+}
+
+// One workgroup per tile of users (grid launch), or, with a tile counter, a
+// persistent grid whose workgroups take tiles from the counter until none is
+// left (every workgroup exits once the counter passes the last tile).
+template <int SK, int MODE, int NKS, int NUB, int NIB, bool PERSIST>
+__global__ __launch_bounds__(512) void k_count(CountArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const int lane = threadIdx.x & 63;
+    uint64_t ncmp = 0, nslot = 0;
+    if constexpr (!PERSIST) {
+        count_tile<SK, MODE, NKS, NUB, NIB>(a, (int64_t)blockIdx.x, lds, ncmp, nslot);
+    } else {
+        __shared__ int64_t sh_tile;
+        for (;;) {
+            if (threadIdx.x == 0) sh_tile = (int64_t)atomicAdd(a.tile_counter, 1ull);
+            __syncthreads();
+            const int64_t t = sh_tile;
+            __syncthreads();
+            if (t >= a.ntiles) break;
+            count_tile<SK, MODE, NKS, NUB, NIB>(a, t, lds, ncmp, nslot);
+            __syncthreads();   // the next tile reuses the LDS buffers
+        }
+    }
     // executed compares (both lanes of a pair count their own items)
     uint64_t tot = ncmp, tslot = nslot;
 #pragma unroll
@@ -359,13 +383,27 @@ static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
     const size_t lds = 2 * STEP_BYTES_MAX;
-    auto kern = k_count<SK, MODE, NKS, NUB, NIB>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
+    if (ntiles == 0) return hipSuccess;
+    CountArgs b = a;
+    b.ntiles = ntiles;
+    if constexpr (MODE == CM_SCREEN) {
+        if (b.tile_counter) {
+            auto kern = k_count<SK, MODE, NKS, NUB, NIB, true>;
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+            dim3 grid((unsigned)std::min<int64_t>(ntiles, std::max(1, b.persistent_ctas)), 1);
+            hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, b);
+            return hipGetLastError();
+        }
+    }
+    b.tile_counter = nullptr;
+    auto kern = k_count<SK, MODE, NKS, NUB, NIB, false>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)((a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG), (unsigned)nsplit);
-    if (grid.x == 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, a);
+    dim3 grid((unsigned)ntiles, (unsigned)nsplit);
+    hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, b);
     return hipGetLastError();
 }
 
@@ -438,8 +476,8 @@ int nib_of(int sk, int nks, int variant) {
     return nks <= 4 ? 4 : 2;
 }
 int num_variants(int sk, int nks) {
-    if (sk == SK_BF16) return nks <= 13 ? 2 : 1;
-    if (sk == SK_FP8) return nks <= 4 ? 2 : 1;
+    if (sk == SK_BF16) return nks <= 13 ? 3 : 1;
+    if (sk == SK_FP8) return nks <= 4 ? 3 : 1;
     return 1;
 }
 

@@ -100,6 +100,11 @@ struct CountArgs {
     unsigned long long emit_cap;
     unsigned long long *stat;     // [0]: executed compares
     int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
+    // persistent launch: workgroups take tiles from *tile_counter (zeroed before
+    // the launch) until it passes ntiles; null = one workgroup per tile
+    unsigned long long *tile_counter;
+    int64_t ntiles;
+    int persistent_ctas;
 };
 
 enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_INTERVAL = 2 };
