@@ -84,7 +84,9 @@ typedef struct {
                             /* users per query of best predicted rank (estimator) or     */
                             /* best u.q/|u| (no estimator), without the verifying screen */
                             /* (0: off; Def. 3 is then not guaranteed)                   */
-    int32_t screen_step;    /* reserved */
+    int32_t graph;          /* 1: rkr_ranks runs as a captured hipGraph (captured on the */
+                            /*    first call, replayed after; falls back to the eager    */
+                            /*    path when the near-tie buffer would overflow)          */
     int32_t reserved[3];
 } rkr_query_opts;
 
@@ -112,6 +114,7 @@ typedef struct {
                             /* variants of the score kind)                                  */
     int64_t compare_slots;  /* lane slots of the compare loops (active or idle): compares / */
                             /* compare_slots is the SIMD efficiency of the entry loops      */
+    int64_t graph_replays;  /* 1 if the call replayed a captured graph                      */
 } rkr_query_stats;
 
 /*

@@ -62,11 +62,12 @@ static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Online autotuner of the screening kernel's tile variant.  For each shape
-// key the first calls run the variants in turn and record their HIP-event
-// times; later calls use the fastest.  Decisions persist in a text cache
-// (RKR_AUTOTUNE_CACHE, default $HOME/.cache/rkr/autotune.txt), one
-// "key variant" line each, read at index build.
+// Online autotuner of the screening kernel's launch (tile variant x grid or
+// persistent).  For each shape key the first calls run the candidates in turn
+// and record their HIP-event times; later calls use the fastest.  Decisions
+// persist in a text cache (RKR_AUTOTUNE_CACHE, default
+// $HOME/.cache/rkr/autotune.txt, "off" to disable), one "key candidate" line
+// each, read at index build.  RKR_SCREEN_CANDIDATE forces a candidate.
 struct Tuner {
     std::map<std::string, int> best;
     std::map<std::string, std::vector<double>> trials;
@@ -102,6 +103,11 @@ struct Tuner {
     }
     int pick(const std::string &key, int nvar) {
         if (nvar <= 1) return 0;
+        const char *force = getenv("RKR_SCREEN_CANDIDATE");   // fixed choice, e.g. for profiling
+        if (force && *force) {
+            int v = atoi(force);
+            if (v >= 0 && v < nvar) return v;
+        }
         auto it = best.find(key);
         if (it != best.end() && it->second < nvar) return it->second;
         const auto &t = trials[key];
@@ -117,6 +123,36 @@ struct Tuner {
             best[key] = b;
             save(key, b);
         }
+    }
+};
+
+// The single-query all-ranks pipeline captured in a hipGraph: every size is
+// fixed by n, so thresholds -> one-entry-per-user tasks -> exact count ->
+// FP64 recheck (record count read on the device) -> ranks replay as one
+// graph launch.  The graph owns its buffers, so eager calls that grow the
+// index's buffers never touch memory the graph refers to.
+struct RanksGraph {
+    bool valid = false;
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    DBuf qbuf, rbuf, pair_u, pair_q, t64, th, tl, tm, cnt, ctr, emit;
+    TaskSet ts;
+    int64_t emit_cap = 0;
+    void destroy() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        ge = nullptr;
+        g = nullptr;
+        valid = false;
+    }
+    void release() {
+        destroy();
+        if (cs) (void)hipStreamDestroy(cs);
+        cs = nullptr;
+        DBuf *b[] = {&qbuf, &rbuf, &pair_u, &pair_q, &t64, &th, &tl, &tm, &cnt, &ctr, &emit};
+        for (DBuf *x : b) x->release();
+        ts.release();
     }
 };
 
@@ -139,6 +175,7 @@ struct rkr_index {
     rkr_query_opts qo{};
     rkr_query_stats stats{};
     Tuner tuner;
+    RanksGraph rg;
     // estimator
     Estimator est;
 };
@@ -262,6 +299,7 @@ extern "C" void rkr_destroy(rkr_index *x) {
     for (DBuf *b : bufs) b->release();
     x->ts_screen.release();
     x->ts_exact.release();
+    x->rg.release();
     for (auto &e : x->ev)
         if (e) (void)hipEventDestroy(e);
     x->sc.release();
@@ -671,9 +709,7 @@ extern "C" rkr_status rkr_query_approx(rkr_index *x, const void *q, int32_t k, d
     return rkr_query_batch(x, 1, q, &k, &c, nullptr, nullptr, ids_out, rank_ub_out);
 }
 
-extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out) {
-    g_err.clear();
-    if (!x || !q || !ranks_out) return fail(RKR_E_INVALID, "NULL argument");
+static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     hipStream_t st = x->st;
     const int64_t n = x->n;
     const double t0 = now_ms();
@@ -703,7 +739,7 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
     HIPCK(launch_dense_pairs(n, 1, ps.pair_u, ps.pair_q, st));
-    HIPCK(launch_thresh(ps.pair_u, ps.pair_q, n, x->Um.p, q, x->d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
     int flags = 0;
     HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
@@ -720,6 +756,124 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     x->stats.flips = (int64_t)ctr[2];
     x->stats.refined_pairs = n;
     x->stats.ms_total = now_ms() - t0;
+    return RKR_OK;
+}
+
+static rkr_status capture_ranks_graph(rkr_index *x) {
+    RanksGraph &g = x->rg;
+    const int64_t n = x->n;
+    const int mes = x->mk == MK_BF16 ? 2 : 4;
+    const int xv = x->sk == SK_F32 ? 0 : 2;
+    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+    const int64_t ntask_pad = (n + 511) / 512 * 512;
+    g.emit_cap = std::max<int64_t>(1 << 20, 2 * x->stats.uncertain + 65536);
+    if (!g.cs) HIPCK(hipStreamCreateWithFlags(&g.cs, hipStreamNonBlocking));
+    HIPCK(g.qbuf.ensure((size_t)x->d * mes));
+    HIPCK(g.rbuf.ensure(n * 4));
+    HIPCK(g.pair_u.ensure(n * 4));
+    HIPCK(g.pair_q.ensure(n * 4));
+    HIPCK(g.t64.ensure(n * 8));
+    HIPCK(g.th.ensure(n * 4));
+    HIPCK(g.tl.ensure(n * 4));
+    HIPCK(g.tm.ensure(n * 4));
+    HIPCK(g.cnt.ensure(n * 4));
+    HIPCK(g.ctr.ensure(64));
+    HIPCK(g.emit.ensure((size_t)g.emit_cap * 8));
+    HIPCK(g.ts.reserve(ntask_pad, ntask_pad / 32));
+    PairSet ps;
+    ps.nq = 1;
+    ps.dense = 1;
+    ps.npairs = n;
+    ps.pair_u = g.pair_u.as<int32_t>();
+    ps.pair_q = g.pair_q.as<int32_t>();
+    ps.t64 = g.t64.as<double>();
+    ps.th = g.th.as<float>();
+    ps.tl = g.tl.as<float>();
+    ps.tm = g.tm.as<float>();
+    g.ts.ntask = n;
+    g.ts.ntask_pad = ntask_pad;
+    g.ts.cap_total = ntask_pad;
+    CountArgs a = count_args(x, ps, g.ts, xv);
+    const int64_t nsteps = a.nsteps;
+    const int64_t gx = (n + tpw - 1) / tpw;
+    int64_t nsplit = (512 + gx - 1) / std::max<int64_t>(gx, 1);
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(nsteps, 1))));
+    HIPCK(g.ts.reserve_entries(ntask_pad, (int)nsplit));
+    a = count_args(x, ps, g.ts, xv);
+    a.steps_per_split = (nsteps + nsplit - 1) / nsplit;
+    nsplit = std::max<int64_t>(1, (nsteps + a.steps_per_split - 1) / std::max<int64_t>(a.steps_per_split, 1));
+    a.cnt_out = g.cnt.as<uint32_t>();
+    a.emit = g.emit.as<int2>();
+    a.emit_count = g.ctr.as<unsigned long long>();
+    a.emit_cap = (unsigned long long)g.emit_cap;
+    a.stat = g.ctr.as<unsigned long long>() + 1;
+    hipStream_t cs = g.cs;
+    HIPCK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    // kernels only (fills instead of memsets), so every replay starts clean
+    hipError_t e = launch_fill_u32(g.ctr.as<uint32_t>(), 0, 16, cs);
+    if (e == hipSuccess) e = launch_dense_pairs(n, 1, ps.pair_u, ps.pair_q, cs);
+    if (e == hipSuccess)
+        e = launch_thresh_dense(x->Um.p, n, g.qbuf.p, 1, x->d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, cs);
+    if (e == hipSuccess) e = q_tasks_one_per_user(n, ntask_pad, ps, x->recheck ? 0 : 1, g.ts, cs);
+    if (e == hipSuccess) e = launch_fill_u32(g.cnt.as<uint32_t>(), 0, n, cs);
+    if (e == hipSuccess) e = launch_count(x->sk, CM_EXACT, a, (int)nsplit, xv, cs);
+    if (e == hipSuccess)
+        e = launch_recheck_dev(g.emit.as<int2>(), g.ctr.as<unsigned long long>(), g.emit_cap, ps.pair_u, ps.t64,
+                               x->Um.p, x->Pm.p, x->d, x->mk, g.cnt.as<uint32_t>(),
+                               g.ctr.as<unsigned long long>() + 2, cs);
+    if (e == hipSuccess) e = q_ranks_out(g.cnt.as<uint32_t>(), n, g.rbuf.as<int32_t>(), cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail_hip(e != hipSuccess ? e : e2, "graph capture of the ranks pipeline");
+    }
+    g.g = graph;
+    HIPCK(hipGraphInstantiate(&g.ge, g.g, nullptr, nullptr, 0));
+    g.valid = true;
+    return RKR_OK;
+}
+
+extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out) {
+    g_err.clear();
+    if (!x || !q || !ranks_out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->qo.graph) return ranks_eager(x, q, ranks_out);
+    RanksGraph &g = x->rg;
+    if (!g.valid) {
+        // first call: run eagerly (sizes the near-tie buffer), then capture
+        rkr_status rs = ranks_eager(x, q, ranks_out);
+        if (rs != RKR_OK) return rs;
+        return capture_ranks_graph(x);
+    }
+    hipStream_t st = x->st;
+    const double t0 = now_ms();
+    const int mes = x->mk == MK_BF16 ? 2 : 4;
+    HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+    HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
+    HIPCK(q_copy(q, g.qbuf.p, (int64_t)x->d * mes, st));
+    HIPCK(hipGraphLaunch(g.ge, st));
+    unsigned long long ctr[3] = {0, 0, 0};
+    int flags = 0;
+    HIPCK(hipMemcpyAsync(ctr, g.ctr.p, 24, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
+    if (ctr[0] > (unsigned long long)g.emit_cap) {
+        // more near ties than the captured buffer holds: answer eagerly, recapture next time
+        g.destroy();
+        return ranks_eager(x, q, ranks_out);
+    }
+    HIPCK(q_copy(g.rbuf.p, ranks_out, x->n * 4, st));
+    HIPCK(hipStreamSynchronize(st));
+    x->stats = rkr_query_stats{};
+    x->stats.queries = 1;
+    x->stats.pairs = x->n;
+    x->stats.refined_pairs = x->n;
+    x->stats.uncertain = (int64_t)ctr[0];
+    x->stats.compares = (int64_t)ctr[1];
+    x->stats.flips = (int64_t)ctr[2];
+    x->stats.ms_total = now_ms() - t0;
+    x->stats.graph_replays = 1;
     return RKR_OK;
 }
 

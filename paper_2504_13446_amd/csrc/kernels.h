@@ -116,6 +116,9 @@ hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
                          hipStream_t st);
 hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
                                float *th, float *tl, float *tm, hipStream_t st);
+hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
+                              const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
+                              unsigned long long *flips, hipStream_t st);
 hipError_t launch_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, const double *t64, const void *Um,
                           const void *Pm, int d, int mk, uint32_t *cnt, unsigned long long *flips,
                           hipStream_t st);

@@ -320,6 +320,30 @@ __global__ void k_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, 
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(flips, (unsigned long long)__popcll(b));
 }
 
+// The same with the record count read from device memory (graph replays):
+// a fixed grid strides over min(*count, cap) records.
+__global__ void k_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
+                              const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
+                              unsigned long long *flips) {
+    const int64_t nrec = (int64_t)min((unsigned long long)cap, *count);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t nflip = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += stride) {
+        const int2 r = rec[i];
+        const int pid = r.x;
+        const int64_t item = r.y & 0x7FFFFFFF;
+        const bool plain = (r.y >> 31) & 1;
+        const int64_t u = pair_u[pid];
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k)
+            acc = fma(master_elem(Um, mk, u * d + k), master_elem(Pm, mk, item * d + k), acc);
+        const bool above = acc > t64[pid];
+        if (above) atomicAdd(&cnt[pid], 1u);
+        nflip += (above != plain) ? 1u : 0u;
+    }
+    if (nflip) atomicAdd(flips, (unsigned long long)nflip);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -404,6 +428,14 @@ hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq
     if (n <= 0 || nq <= 0) return hipSuccess;
     dim3 g((unsigned)((nq + 63) / 64), (unsigned)((n + 63) / 64));
     hipLaunchKernelGGL(k_thresh_dense, g, dim3(256), 0, st, Um, n, Qm, nq, d, mk, t64, th, tl, tm);
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
+                              const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
+                              unsigned long long *flips, hipStream_t st) {
+    hipLaunchKernelGGL(k_recheck_dev, dim3(2048), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk, cnt,
+                       flips);
     return hipGetLastError();
 }
 

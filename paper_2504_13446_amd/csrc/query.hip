@@ -166,6 +166,37 @@ __global__ void k_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks) {
     if (i < n) ranks[i] = (int32_t)(1u + cnt[i]);
 }
 
+// One entry per user (single query, every user): task t = user t, block b's
+// entries at 32 b + lane.  Built without host round trips so the whole
+// single-query pipeline can be captured in a graph.
+__global__ void k_tasks_one_per_user(int64_t n, int64_t ntask_pad, const float *th, const float *tl,
+                                     const float *tm, int plain, int32_t *task_user, int32_t *len,
+                                     int64_t *blk_base, int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt,
+                                     float *ent_th, float *ent_tl, float *ent_tm) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask_pad) return;
+    const bool real = t < n;
+    task_user[t] = real ? (int32_t)t : -1;
+    len[t] = real ? 1 : 0;
+    if ((t & 31) == 0) blk_base[t >> 5] = t;
+    ent_pid[t] = real ? (int32_t)t : 0;
+    ent_q[t] = 0;
+    ent_cnt[t] = 0;
+    const float h = real ? (plain ? tm[t] : th[t]) : 0.0f;
+    const float l = real ? (plain ? tm[t] : tl[t]) : 0.0f;
+    ent_th[t] = h;
+    ent_tl[t] = l;
+    ent_tm[t] = real ? tm[t] : 0.0f;
+}
+__global__ void k_copy_words(const uint32_t *src, uint32_t *dst, int64_t nw) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) dst[i] = src[i];
+}
+__global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t nb) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 #define LAUNCH1D(kern, N, ...)                                                              \
     do {                                                                                   \
@@ -238,6 +269,20 @@ hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_o
 }
 hipError_t q_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int32_t *ranks, hipStream_t st) {
     LAUNCH1D(k_write_answer, total, keys, total, ids, ranks);
+    return hipGetLastError();
+}
+hipError_t q_tasks_one_per_user(int64_t n, int64_t ntask_pad, const PairSet &ps, int plain, TaskSet &ts,
+                                hipStream_t st) {
+    LAUNCH1D(k_tasks_one_per_user, ntask_pad, n, ntask_pad, ps.th, ps.tl, ps.tm, plain, ts.task_user, ts.len,
+             ts.blk_base, ts.ent_pid, ts.ent_q, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+    return hipGetLastError();
+}
+hipError_t q_copy(const void *src, void *dst, int64_t bytes, hipStream_t st) {
+    if (bytes % 4 == 0 && ((uintptr_t)src % 4) == 0 && ((uintptr_t)dst % 4) == 0) {
+        LAUNCH1D(k_copy_words, bytes / 4, (const uint32_t *)src, (uint32_t *)dst, bytes / 4);
+    } else {
+        LAUNCH1D(k_copy_bytes, bytes, (const uint8_t *)src, (uint8_t *)dst, bytes);
+    }
     return hipGetLastError();
 }
 hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream_t st) {

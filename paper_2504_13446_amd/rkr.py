@@ -45,7 +45,7 @@ class BuildOpts(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("seed_mult", ctypes.c_int32), ("use_estimator", ctypes.c_int32),
                 ("approx_refine", ctypes.c_int32), ("prune_mult", ctypes.c_int32),
-                ("screen_step", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class QueryStats(ctypes.Structure):
@@ -56,7 +56,8 @@ class QueryStats(ctypes.Structure):
                                         "ms_total", "mlp_loss", "ms_screen_kernel", "ms_exact_kernel",
                                         "ms_recheck_kernel")] + [("screen_ctas", ctypes.c_int64),
                                                              ("screen_variant", ctypes.c_int64),
-                                                             ("compare_slots", ctypes.c_int64)]
+                                                             ("compare_slots", ctypes.c_int64),
+                                                             ("graph_replays", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -154,8 +155,9 @@ def rkr_destroy(h: int) -> None:
 
 
 def rkr_configure(h: int, seed_mult: int = 0, use_estimator: bool = False, approx_refine: int = 0,
-                  prune_mult: int = 0) -> None:
-    o = QueryOpts(int(seed_mult), 1 if use_estimator else 0, int(approx_refine), int(prune_mult), 0)
+                  prune_mult: int = 0, graph: bool = False) -> None:
+    o = QueryOpts(int(seed_mult), 1 if use_estimator else 0, int(approx_refine), int(prune_mult),
+                  1 if graph else 0)
     _check(load().rkr_configure(h, ctypes.byref(o)))
 
 
