@@ -37,6 +37,10 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
+// Screening compares scores as 7-bit codes once some lane of the wave holds
+// this many live entries (below it, quantising costs more than it saves).
+constexpr int SWAR_MIN_ENTRIES = 4;
+
 template <int SK> struct FragT;
 template <> struct FragT<SK_BF16> { using T = i32x4; };
 template <> struct FragT<SK_F32> { using T = float; };
@@ -144,6 +148,71 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
     }
 
+    // Screening pass over the live entries of user block ub for the current
+    // step: count(hi) returns the lane's number of scores certainly above hi
+    // (a lower bound of the exact count); entries whose remaining budget turns
+    // negative are dropped, the others are compacted to the front.
+    auto screen_entries = [&](int ub, float eps, auto count) {
+        int w = 0;
+        const int mylen = len[ub];
+        // the fields of a group of ED entries load while the previous group is
+        // counted (one group of latency hidden instead of one entry)
+        constexpr int ED = 4;
+        int pid_n[ED], rem_n[ED];
+        float th_n[ED];
+        auto fetch_group = [&](int i0) {
+#pragma unroll
+            for (int k = 0; k < ED; ++k) {
+                const int i = i0 + k;
+                if (i < mylen) {
+                    const int64_t e = ebase[ub] + (int64_t)i * 32;
+                    pid_n[k] = a.ent_pid[e];
+                    th_n[k] = a.ent_th[e];
+                    rem_n[k] = (int)a.ent_cnt[e];
+                }
+            }
+        };
+        fetch_group(0);
+        uint32_t it_act = 0, it_all = 0;
+        for (int i0 = 0; __ballot(i0 < mylen) != 0ull; i0 += ED) {
+            // take the group's fields before the next group's loads overwrite them
+            int pid_c[ED], rem_c[ED];
+            float th_c[ED];
+#pragma unroll
+            for (int k = 0; k < ED; ++k) {
+                pid_c[k] = pid_n[k];
+                rem_c[k] = rem_n[k];
+                th_c[k] = th_n[k];
+            }
+            fetch_group(i0 + ED);
+#pragma unroll
+            for (int k = 0; k < ED; ++k) {
+                const int i = i0 + k;
+                if (__ballot(i < mylen) == 0ull) break;
+                const bool act = i < mylen;
+                const float hi = a.plain ? th_c[k] : f32_next_up(th_c[k] + eps);
+                const uint32_t c = pair_sum(count(hi));
+                // remaining budget: the pair dies when more than bound - 1 items are certainly above
+                const int rem = rem_c[k] - (int)c;
+                const bool alive = act && rem >= 0;
+                if (alive && half == 0) {
+                    const int64_t ew = ebase[ub] + (int64_t)w * 32;
+                    a.ent_cnt[ew] = (uint32_t)rem;
+                    if (w != i) {
+                        a.ent_pid[ew] = pid_c[k];
+                        a.ent_th[ew] = th_c[k];
+                    }
+                }
+                w += alive ? 1 : 0;
+                it_act += act ? 1u : 0u;
+                it_all += 1u;
+            }
+        }
+        len[ub] = w;
+        ncmp += (uint64_t)it_act * (NIB * 16);
+        nslot += (uint64_t)it_all * (NIB * 16);
+    };
+
     int any_live = 0;
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
@@ -221,102 +290,140 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         for (int ub = 0; ub < NUB; ++ub) {
             double E = un_hat[ub] * ca + un_del[ub] * cb + un_full[ub] * cc + cabs;
             const float eps = f32_round_up(E * (1.0 + 1e-9));
+            if constexpr (MODE == CM_SCREEN) {
+                // Screening only needs a lower bound of each pair's count.  With
+                // enough live entries, the lane's scores are first mapped to
+                // 7-bit codes by a monotone function F, and an entry counts the
+                // codes above F(hi): code(s) > F(hi) implies s > hi.  Four codes
+                // share a dword, so one subtract, mask and bit count compare
+                // four scores with an entry.
+                const bool full = item0 + NIB * 32 <= a.m;
+                if (full && __ballot(len[ub] >= SWAR_MIN_ENTRIES) != 0ull) {
+                    constexpr int QW = NIB * 4;
+                    uint32_t qd[QW];
+                    float mn = acc[0][ub][0], mx = acc[0][ub][0];
+#pragma unroll
+                    for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            mn = fminf(mn, acc[ib][ub][r]);
+                            mx = fmaxf(mx, acc[ib][ub][r]);
+                        }
+                    // F(x) = cvt_u8(med3(fma(x - mn, sc, 128), 128, 255)).  For a score
+                    // x in [mn, mx], (x - mn) * sc <= 126 (1 + 2^-22), so the fma lies
+                    // in [128, 254.01] (med3 is the identity there): every code byte
+                    // keeps its top bit.  A flat or tiny range gives sc = 0: all codes
+                    // 128, nothing counted (still a lower bound).
+                    const float rg = mx - mn;
+                    const float sc = rg > 1e-30f ? 126.0f * __builtin_amdgcn_rcpf(rg) : 0.0f;
+#pragma unroll
+                    for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            uint32_t wd = 0;
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                wd = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(acc[ib][ub][4 * j + b] - mn, sc, 128.0f), b,
+                                                                   wd);
+                            qd[ib * 4 + j] = wd;
+                        }
+                    screen_entries(ub, eps, [&](float hi) -> uint32_t {
+                        const float v = __builtin_amdgcn_fmed3f(fmaf(hi - mn, sc, 128.0f), 128.0f, 255.0f);
+                        // g = F(hi) in [128, 255]; byte (code - (g - 127)) has its top bit
+                        // set iff code > g, and never borrows (code >= 128 >= g - 127)
+                        const uint32_t g = __builtin_amdgcn_cvt_pk_u8_f32(v, 0, 0u) & 0xFFu;
+                        const uint32_t H = (g - 127u) * 0x01010101u;
+                        uint32_t c = 0;
+#pragma unroll
+                        for (int j = 0; j < QW; ++j) c = __builtin_popcount((qd[j] - H) & 0x80808080u) + c;
+                        return c;
+                    });
+                } else {
+                    screen_entries(ub, eps, [&](float hi) -> uint32_t {
+                        uint32_t c = 0;
+#pragma unroll
+                        for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) c += (acc[ib][ub][r] > hi) ? 1u : 0u;
+                        return c;
+                    });
+                }
+                continue;
+            }
             int w = 0;
             const int mylen = len[ub];
             // software pipeline: the fields of entry i + 1 load while entry i is counted
-            int pid_n = 0, rem_n = 0;
+            int pid_n = 0;
             float th_n = 0.0f, tl_n = 0.0f, tm_n = 0.0f;
             uint32_t cnt_n = 0;
             auto fetch = [&](int i) {
                 const int64_t e = ebase[ub] + (int64_t)i * 32;
                 pid_n = a.ent_pid[e];
                 th_n = a.ent_th[e];
-                if constexpr (MODE == CM_SCREEN) {
-                    rem_n = (int)a.ent_cnt[e];
-                } else {
-                    tl_n = a.ent_tl[e];
-                    tm_n = a.ent_tm[e];
-                    cnt_n = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
-                }
+                tl_n = a.ent_tl[e];
+                tm_n = a.ent_tm[e];
+                cnt_n = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
             };
             if (mylen > 0) fetch(0);
+            uint32_t it_act = 0, it_all = 0;
             for (int i = 0; __ballot(i < mylen) != 0ull; ++i) {
                 const bool act = i < mylen;
                 const int64_t e = ebase[ub] + (int64_t)i * 32;
                 // take every field of entry i before the prefetch overwrites them
                 const int pid = pid_n;
                 const float th = th_n;
-                const int rem_in = rem_n;
                 const float tl = tl_n, tmv = tm_n;
                 uint32_t cnt = cnt_n;
                 if (i + 1 < mylen) fetch(i + 1);
                 const float hi = a.plain ? th : f32_next_up(th + eps);
                 uint32_t c = 0;
-                if constexpr (MODE == CM_SCREEN) {
-                    // remaining budget: the pair dies when more than bound - 1 items are certainly above
+                const float lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
+                uint32_t umask = 0;
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float s = acc[ib][ub][r];
+                        const bool gt = s > hi;
+                        c += gt ? 1u : 0u;
+                        umask |= (!gt && s >= lo) ? (1u << (ib * 16 + r)) : 0u;
+                    }
+                if (!act) umask = 0;
+                if (__ballot(umask != 0) != 0ull) {
+                    // rare: the plain FP32 verdicts (score > fl32(t)) of this entry's scores
+                    uint32_t pmask = 0;
 #pragma unroll
                     for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) c += (acc[ib][ub][r] > hi) ? 1u : 0u;
-                    c = pair_sum(c);
-                    const int rem = rem_in - (int)c;
-                    const bool alive = act && rem >= 0;
-                    if (alive && half == 0) {
-                        const int64_t ew = ebase[ub] + (int64_t)w * 32;
-                        a.ent_cnt[ew] = (uint32_t)rem;
-                        if (w != i) {
-                            a.ent_pid[ew] = pid;
-                            a.ent_th[ew] = th;
-                        }
+                        for (int r = 0; r < 16; ++r)
+                            pmask |= (acc[ib][ub][r] > tmv) ? (1u << (ib * 16 + r)) : 0u;
+                    const uint32_t nu = __popc(umask);
+                    const uint32_t incl = wave_incl_scan(nu, lane);
+                    const uint32_t total = __shfl(incl, 63, 64);
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
+                    base = __shfl(base, 0, 64);
+                    unsigned long long pos = base + (incl - nu);
+                    uint32_t mm = umask;
+                    while (mm) {
+                        const int bit = __ffs(mm) - 1;
+                        mm &= mm - 1;
+                        const int ib = bit >> 4, r = bit & 15;
+                        const int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                        const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
+                        if (pos < a.emit_cap) a.emit[pos] = make_int2(pid, (int)item | plainbit);
+                        ++pos;
                     }
-                    w += alive ? 1 : 0;
-                } else {
-                    const float lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
-                    uint32_t umask = 0;
-#pragma unroll
-                    for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const float s = acc[ib][ub][r];
-                            const bool gt = s > hi;
-                            c += gt ? 1u : 0u;
-                            umask |= (!gt && s >= lo) ? (1u << (ib * 16 + r)) : 0u;
-                        }
-                    if (!act) umask = 0;
-                    if (__ballot(umask != 0) != 0ull) {
-                        // rare: the plain FP32 verdicts (score > fl32(t)) of this entry's scores
-                        uint32_t pmask = 0;
-#pragma unroll
-                        for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-                            for (int r = 0; r < 16; ++r)
-                                pmask |= (acc[ib][ub][r] > tmv) ? (1u << (ib * 16 + r)) : 0u;
-                        const uint32_t nu = __popc(umask);
-                        const uint32_t incl = wave_incl_scan(nu, lane);
-                        const uint32_t total = __shfl(incl, 63, 64);
-                        unsigned long long base = 0;
-                        if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
-                        base = __shfl(base, 0, 64);
-                        unsigned long long pos = base + (incl - nu);
-                        uint32_t mm = umask;
-                        while (mm) {
-                            const int bit = __ffs(mm) - 1;
-                            mm &= mm - 1;
-                            const int ib = bit >> 4, r = bit & 15;
-                            const int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                            const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
-                            if (pos < a.emit_cap) a.emit[pos] = make_int2(pid, (int)item | plainbit);
-                            ++pos;
-                        }
-                    }
-                    c = pair_sum(c);
-                    cnt += c;
-                    if (act && half == 0) a.ent_cnt[(int64_t)split * a.cap_total + e] = cnt;
                 }
-                ncmp += act ? (uint64_t)(NIB * 16) : 0ull;
-                nslot += (uint64_t)(NIB * 16);
+                c = pair_sum(c);
+                cnt += c;
+                if (act && half == 0) a.ent_cnt[(int64_t)split * a.cap_total + e] = cnt;
+                it_act += act ? 1u : 0u;
+                it_all += 1u;
             }
-            if constexpr (MODE == CM_SCREEN) len[ub] = w;
+            (void)w;
+            ncmp += (uint64_t)it_act * (NIB * 16);
+            nslot += (uint64_t)it_all * (NIB * 16);
         }
 
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
