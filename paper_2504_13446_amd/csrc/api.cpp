@@ -205,10 +205,11 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     if (sk != SK_F32 && sk != SK_BF16 && sk != SK_FP8) return fail(RKR_E_INVALID, "unknown score kind");
     if (sketch < 0) return fail(RKR_E_INVALID, "sketch_samples must be >= 0");
     const int KS = frag_ks(sk);
-    const int dpad = (d + KS - 1) / KS * KS;
-    const int nks = dpad / KS;
-    if (nks > max_nks(sk))
+    // pad d to a k-step count the count kernels are instantiated for (zero padding)
+    const int nks = nks_bucket(sk, (d + KS - 1) / KS);
+    if (nks == 0)
         return fail(RKR_E_UNSUPPORTED, "d too large for this score kind (max " + std::to_string(max_nks(sk) * KS) + ")");
+    const int dpad = nks * KS;
 
     rkr_index *x = new (std::nothrow) rkr_index();
     if (!x) return fail(RKR_E_NOMEM, "host allocation failed");
@@ -612,6 +613,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
                                    x->ts_screen, x->sc, st);
         if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
+        // the screening kernel addresses entries with 32-bit byte offsets
+        if (x->ts_screen.cap_total >= ((int64_t)1 << 30))
+            return fail(RKR_E_UNSUPPORTED, "more than 2^30 screening entries: split the batch");
         // candidates: each tile variant, launched as a grid or as a persistent grid
         const std::string key = tune_key(x, nq, npairs);
         const int ntv = num_variants(x->sk, x->nks);

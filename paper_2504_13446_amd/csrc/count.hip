@@ -102,8 +102,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * FB;
     constexpr int LOADS_MAX = (STEP_BYTES_MAX + 512 * 16 - 1) / (512 * 16);
 
-    const int nks = a.nks;
-    const int step_bytes = NIB * nks * 64 * FB;
+    constexpr int step_bytes = STEP_BYTES_MAX;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -143,7 +142,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             FT v{};
-            if (s < nks && u >= 0) v = *(const FT *)(urow + (int64_t)s * KS * ES);
+            if (u >= 0) v = *(const FT *)(urow + (int64_t)s * KS * ES);
             bfrag[ub][s] = v;
         }
     }
@@ -152,29 +151,70 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     // step: count(hi) returns the lane's number of scores certainly above hi
     // (a lower bound of the exact count); entries whose remaining budget turns
     // negative are dropped, the others are compacted to the front.
+    // Entry fields are addressed by 32-bit byte offsets from the array bases
+    // (the host keeps every entry array below 4 GiB).
+    uint32_t ebyte[NUB];
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub) ebyte[ub] = (uint32_t)ebase[ub] * 4u;
+    auto ld_i32 = [](const void *base, uint32_t off) { return *(const int32_t *)((const uint8_t *)base + off); };
+    auto ld_f32 = [](const void *base, uint32_t off) { return *(const float *)((const uint8_t *)base + off); };
+    auto st_u32 = [](void *base, uint32_t off, uint32_t v) { *(uint32_t *)((uint8_t *)base + off) = v; };
+
+    // The fields of a group of ED entries load while the previous group is
+    // counted; a step's first group is requested before its scores are
+    // computed, so the matrix-core work hides that latency.
+    //
+    // The loop over entries is branch-free per lane: it runs nit (the wave's
+    // longest list, uniform) iterations; every lane loads slot i and stores to
+    // slot (alive ? w : i).  Slots below nit exist for every lane of the
+    // block (a block's lists were laid out for its longest initial list), a
+    // lane past its own list or whose pair just died only rewrites its own
+    // slot i >= w, which later compaction overwrites in program order, and the
+    // two lanes of a pair write identical values.
+    constexpr int ED = 4;
+    int g0_pid[NUB][ED], g0_rem[NUB][ED];
+    float g0_th[NUB][ED];
+    int nit[NUB];
+    auto wave_max = [](int v) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+        return __builtin_amdgcn_readfirstlane(v);
+    };
+    auto fetch_into = [&](int ub, int i0, int *pid, int *rem, float *th) {
+#pragma unroll
+        for (int k = 0; k < ED; ++k) {
+            const int i = i0 + k;
+            if (i < nit[ub]) {
+                const uint32_t o = ebyte[ub] + (uint32_t)i * 128u;
+                pid[k] = ld_i32(a.ent_pid, o);
+                th[k] = ld_f32(a.ent_th, o);
+                rem[k] = ld_i32(a.ent_cnt, o);
+            }
+        }
+    };
+    // first group of the current lists (sets nit)
+    auto fetch_first = [&](int ub) {
+        nit[ub] = wave_max(len[ub]);
+        fetch_into(ub, 0, g0_pid[ub], g0_rem[ub], g0_th[ub]);
+    };
+
+    // Screening pass over the live entries of user block ub for the current
+    // step: count(hi) returns the lane's number of scores certainly above hi
+    // (a lower bound of the exact count); entries whose remaining budget turns
+    // negative are dropped, the others are compacted to the front.
     auto screen_entries = [&](int ub, float eps, auto count) {
         int w = 0;
         const int mylen = len[ub];
-        // the fields of a group of ED entries load while the previous group is
-        // counted (one group of latency hidden instead of one entry)
-        constexpr int ED = 4;
+        const int lim = nit[ub];
         int pid_n[ED], rem_n[ED];
         float th_n[ED];
-        auto fetch_group = [&](int i0) {
 #pragma unroll
-            for (int k = 0; k < ED; ++k) {
-                const int i = i0 + k;
-                if (i < mylen) {
-                    const int64_t e = ebase[ub] + (int64_t)i * 32;
-                    pid_n[k] = a.ent_pid[e];
-                    th_n[k] = a.ent_th[e];
-                    rem_n[k] = (int)a.ent_cnt[e];
-                }
-            }
-        };
-        fetch_group(0);
-        uint32_t it_act = 0, it_all = 0;
-        for (int i0 = 0; __ballot(i0 < mylen) != 0ull; i0 += ED) {
+        for (int k = 0; k < ED; ++k) {
+            pid_n[k] = g0_pid[ub][k];
+            rem_n[k] = g0_rem[ub][k];
+            th_n[k] = g0_th[ub][k];
+        }
+        for (int i0 = 0; i0 < lim; i0 += ED) {
             // take the group's fields before the next group's loads overwrite them
             int pid_c[ED], rem_c[ED];
             float th_c[ED];
@@ -184,33 +224,29 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 rem_c[k] = rem_n[k];
                 th_c[k] = th_n[k];
             }
-            fetch_group(i0 + ED);
+            fetch_into(ub, i0 + ED, pid_n, rem_n, th_n);
 #pragma unroll
             for (int k = 0; k < ED; ++k) {
                 const int i = i0 + k;
-                if (__ballot(i < mylen) == 0ull) break;
-                const bool act = i < mylen;
-                const float hi = a.plain ? th_c[k] : f32_next_up(th_c[k] + eps);
-                const uint32_t c = pair_sum(count(hi));
-                // remaining budget: the pair dies when more than bound - 1 items are certainly above
-                const int rem = rem_c[k] - (int)c;
-                const bool alive = act && rem >= 0;
-                if (alive && half == 0) {
-                    const int64_t ew = ebase[ub] + (int64_t)w * 32;
-                    a.ent_cnt[ew] = (uint32_t)rem;
-                    if (w != i) {
-                        a.ent_pid[ew] = pid_c[k];
-                        a.ent_th[ew] = th_c[k];
-                    }
+                if (i < lim) {
+                    const bool act = i < mylen;
+                    const float hb = f32_next_up(th_c[k] + eps);
+                    const float hi = a.plain ? th_c[k] : hb;
+                    const uint32_t c = pair_sum(count(hi));
+                    // remaining budget: the pair dies when more than bound - 1 items are certainly above
+                    const int rem = rem_c[k] - (int)c;
+                    const bool alive = act && rem >= 0;
+                    const uint32_t ow = ebyte[ub] + (uint32_t)(alive ? w : i) * 128u;
+                    st_u32(a.ent_cnt, ow, (uint32_t)rem);
+                    st_u32(a.ent_pid, ow, (uint32_t)pid_c[k]);
+                    st_u32(a.ent_th, ow, __float_as_uint(th_c[k]));
+                    w += alive ? 1 : 0;
                 }
-                w += alive ? 1 : 0;
-                it_act += act ? 1u : 0u;
-                it_all += 1u;
             }
         }
         len[ub] = w;
-        ncmp += (uint64_t)it_act * (NIB * 16);
-        nslot += (uint64_t)it_all * (NIB * 16);
+        ncmp += (uint64_t)mylen * (NIB * 16);
+        nslot += (uint64_t)lim * (NIB * 16);
     };
 
     int any_live = 0;
@@ -223,15 +259,47 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
+    // Screening, second half of the workgroup: its waves count a step's codes
+    // at the start of the next step, before their matrix-core work, so that on
+    // a SIMD one wave's MFMA overlaps the other wave's compare loop.
+    constexpr int QW = NIB * 4;
+    uint32_t qd_p[NUB][QW];
+    float mn_p[NUB], sc_p[NUB], eps_p[NUB];
+    bool have_prev = false;
+    const bool late = MODE == CM_SCREEN && wave >= WAVES_PER_WG / 2;
+    // the code compare against threshold hi (see the compare section)
+    auto code_count = [](const uint32_t *qd, float mn, float sc, float hi) -> uint32_t {
+        const float v = __builtin_amdgcn_fmed3f(fmaf(hi - mn, sc, 128.0f), 128.0f, 255.0f);
+        // g = F(hi) in [128, 255]; byte (code - (g - 127)) has its top bit
+        // set iff code > g, and never borrows (code >= 128 >= g - 127)
+        const uint32_t g = __builtin_amdgcn_cvt_pk_u8_f32(v, 0, 0u);
+        const uint32_t H = __builtin_amdgcn_perm(0u, g, 0u) - 0x7F7F7F7Fu;
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < QW; ++j) c = __builtin_popcount((qd[j] - H) & 0x80808080u) + c;
+        return c;
+    };
+
     for (int64_t st = s_begin; st < s_end; ++st) {
         const int buf = (int)((st - s_begin) & 1);
         const uint8_t *tile = lds + buf * STEP_BYTES_MAX;
         // prefetch the next step straight into the other LDS buffer; it was last
         // read in the previous step, before the barrier that ended it
+        if constexpr (MODE == CM_SCREEN) {
+#pragma unroll
+            for (int ub = 0; ub < NUB; ++ub) fetch_first(ub);
+        }
         const bool has_next = (st + 1 < s_end);
         if (has_next)
             stage_step<LOADS_MAX>(a.plp + (st + 1) * (int64_t)step_bytes, lds + (buf ^ 1) * STEP_BYTES_MAX,
                                   step_bytes, tid);
+        if constexpr (MODE == CM_SCREEN) {
+            if (late && have_prev) {
+#pragma unroll
+                for (int ub = 0; ub < NUB; ++ub)
+                    screen_entries(ub, eps_p[ub], [&](float hi) { return code_count(qd_p[ub], mn_p[ub], sc_p[ub], hi); });
+            }
+        }
 
         // ---- scores of NIB x 32 items against NUB x 32 users
         f32x16 acc[NIB][NUB];
@@ -250,16 +318,16 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 pscale[ib] = 127 + (item < a.m ? (int)a.pexp[item] : 0);
             }
         }
+        // every k-step is real (the layouts are padded to NKS), so this is one
+        // straight-line block the scheduler can pipeline LDS reads through
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
-            if (s < nks) {
 #pragma unroll
-                for (int ib = 0; ib < NIB; ++ib) {
-                    FT af = *(const FT *)(tile + ((ib * nks + s) * 64 + lane) * FB);
+            for (int ib = 0; ib < NIB; ++ib) {
+                FT af = *(const FT *)(tile + ((ib * NKS + s) * 64 + lane) * FB);
 #pragma unroll
-                    for (int ub = 0; ub < NUB; ++ub)
-                        acc[ib][ub] = mfma_step<SK>(acc[ib][ub], af, bfrag[ub][s], pscale[ib], uscale[ub]);
-                }
+                for (int ub = 0; ub < NUB; ++ub)
+                    acc[ib][ub] = mfma_step<SK>(acc[ib][ub], af, bfrag[ub][s], pscale[ib], uscale[ub]);
             }
         }
         // items past the end never count: make their scores -inf
@@ -286,58 +354,78 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
 
         // ---- compare and count
+        // Screening only needs a lower bound of each pair's count.  With enough
+        // live entries, the lane's scores are first mapped to 7-bit codes by a
+        // monotone function F, and an entry counts the codes above F(hi):
+        // code(s) > F(hi) implies s > hi.  Four codes share a dword, so one
+        // subtract, mask and bit count compare four scores with an entry.
+        //   F(x) = cvt_u8(med3(fma(x - mn, sc, 128), 128, 255)),  sc = 126 / (mx - mn)
+        // For a score x in [mn, mx], (x - mn) * sc <= 126 (1 + 2^-22), so the fma
+        // lies in [128, 254.01] (med3 is the identity there): every code byte keeps
+        // its top bit.  A flat or tiny range gives sc = 0: all codes 128, nothing
+        // counted (still a lower bound).  Past-the-end items (a partial last step)
+        // take the code of mn, 128, which is never counted either.
+        auto quantize = [&](int ub, bool full, uint32_t *qd, float &mn_o, float &sc_o) {
+            float mn, mx;
+            if (full) {
+                mn = acc[0][ub][0];
+                mx = mn;
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        mn = fminf(mn, acc[ib][ub][r]);
+                        mx = fmaxf(mx, acc[ib][ub][r]);
+                    }
+            } else {
+                mn = __builtin_inff();
+                mx = -__builtin_inff();
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float v = acc[ib][ub][r];
+                        if (v != -__builtin_inff()) {
+                            mn = fminf(mn, v);
+                            mx = fmaxf(mx, v);
+                        }
+                    }
+                if (!(mn <= mx)) mn = mx = 0.0f;
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (acc[ib][ub][r] == -__builtin_inff()) acc[ib][ub][r] = mn;
+            }
+            const float rg = mx - mn;
+            const float sc = rg > 1e-30f ? 126.0f * __builtin_amdgcn_rcpf(rg) : 0.0f;
+#pragma unroll
+            for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t wd = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        wd = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(acc[ib][ub][4 * j + b] - mn, sc, 128.0f), b, wd);
+                    qd[ib * 4 + j] = wd;
+                }
+            mn_o = mn;
+            sc_o = sc;
+        };
 #pragma unroll
         for (int ub = 0; ub < NUB; ++ub) {
             double E = un_hat[ub] * ca + un_del[ub] * cb + un_full[ub] * cc + cabs;
             const float eps = f32_round_up(E * (1.0 + 1e-9));
             if constexpr (MODE == CM_SCREEN) {
-                // Screening only needs a lower bound of each pair's count.  With
-                // enough live entries, the lane's scores are first mapped to
-                // 7-bit codes by a monotone function F, and an entry counts the
-                // codes above F(hi): code(s) > F(hi) implies s > hi.  Four codes
-                // share a dword, so one subtract, mask and bit count compare
-                // four scores with an entry.
                 const bool full = item0 + NIB * 32 <= a.m;
-                if (full && __ballot(len[ub] >= SWAR_MIN_ENTRIES) != 0ull) {
-                    constexpr int QW = NIB * 4;
+                if (late) {
+                    quantize(ub, full, qd_p[ub], mn_p[ub], sc_p[ub]);
+                    eps_p[ub] = eps;
+                } else if (full && __ballot(len[ub] >= SWAR_MIN_ENTRIES) != 0ull) {
                     uint32_t qd[QW];
-                    float mn = acc[0][ub][0], mx = acc[0][ub][0];
-#pragma unroll
-                    for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            mn = fminf(mn, acc[ib][ub][r]);
-                            mx = fmaxf(mx, acc[ib][ub][r]);
-                        }
-                    // F(x) = cvt_u8(med3(fma(x - mn, sc, 128), 128, 255)).  For a score
-                    // x in [mn, mx], (x - mn) * sc <= 126 (1 + 2^-22), so the fma lies
-                    // in [128, 254.01] (med3 is the identity there): every code byte
-                    // keeps its top bit.  A flat or tiny range gives sc = 0: all codes
-                    // 128, nothing counted (still a lower bound).
-                    const float rg = mx - mn;
-                    const float sc = rg > 1e-30f ? 126.0f * __builtin_amdgcn_rcpf(rg) : 0.0f;
-#pragma unroll
-                    for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            uint32_t wd = 0;
-#pragma unroll
-                            for (int b = 0; b < 4; ++b)
-                                wd = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(acc[ib][ub][4 * j + b] - mn, sc, 128.0f), b,
-                                                                   wd);
-                            qd[ib * 4 + j] = wd;
-                        }
-                    screen_entries(ub, eps, [&](float hi) -> uint32_t {
-                        const float v = __builtin_amdgcn_fmed3f(fmaf(hi - mn, sc, 128.0f), 128.0f, 255.0f);
-                        // g = F(hi) in [128, 255]; byte (code - (g - 127)) has its top bit
-                        // set iff code > g, and never borrows (code >= 128 >= g - 127)
-                        const uint32_t g = __builtin_amdgcn_cvt_pk_u8_f32(v, 0, 0u) & 0xFFu;
-                        const uint32_t H = (g - 127u) * 0x01010101u;
-                        uint32_t c = 0;
-#pragma unroll
-                        for (int j = 0; j < QW; ++j) c = __builtin_popcount((qd[j] - H) & 0x80808080u) + c;
-                        return c;
-                    });
+                    float mn, sc;
+                    quantize(ub, true, qd, mn, sc);
+                    screen_entries(ub, eps, [&](float hi) { return code_count(qd, mn, sc, hi); });
                 } else {
                     screen_entries(ub, eps, [&](float hi) -> uint32_t {
                         uint32_t c = 0;
@@ -426,11 +514,22 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             nslot += (uint64_t)it_all * (NIB * 16);
         }
 
+        have_prev = late;
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         int live = 0;
 #pragma unroll
         for (int ub = 0; ub < NUB; ++ub) live |= (len[ub] > 0);
         if (!__syncthreads_or(live)) break;
+    }
+
+    if constexpr (MODE == CM_SCREEN) {
+        if (late && have_prev) {
+#pragma unroll
+            for (int ub = 0; ub < NUB; ++ub) {
+                fetch_first(ub);
+                screen_entries(ub, eps_p[ub], [&](float hi) { return code_count(qd_p[ub], mn_p[ub], sc_p[ub], hi); });
+            }
+        }
     }
 
     // ---- write back
@@ -490,6 +589,7 @@ static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
     const size_t lds = 2 * STEP_BYTES_MAX;
+    if (a.nks != NKS) return hipErrorInvalidValue;   // layouts are padded to a supported k-step count
     const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
     if (ntiles == 0) return hipSuccess;
     CountArgs b = a;
@@ -567,6 +667,17 @@ hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int va
         return mode == CM_SCREEN ? dispatch_nks<SK_FP8, CM_SCREEN>(a, nsplit, variant, st)
                                  : dispatch_nks<SK_FP8, CM_EXACT>(a, nsplit, variant, st);
     return hipErrorInvalidValue;
+}
+
+// The k-step count an index pads its low-precision layouts to: the smallest
+// count a kernel is instantiated for that holds nks k-steps (0 if none).
+int nks_bucket(int sk, int nks) {
+    static const int bf16[] = {4, 8, 13, 20}, f32[] = {32, 64, 100, 160}, fp8[] = {2, 4, 8};
+    const int *b = sk == SK_BF16 ? bf16 : (sk == SK_F32 ? f32 : fp8);
+    const int nb = sk == SK_FP8 ? 3 : 4;
+    for (int i = 0; i < nb; ++i)
+        if (nks <= b[i]) return b[i];
+    return 0;
 }
 
 // Largest supported k-step count per score kind (d <= KS * max).

@@ -141,6 +141,7 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t st);
 
 // count.hip
 int max_nks(int sk);
+int nks_bucket(int sk, int nks);
 int nub_of(int sk, int nks, int variant);
 int nib_of(int sk, int nks, int variant);
 int num_variants(int sk, int nks);

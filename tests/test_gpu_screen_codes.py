@@ -1,0 +1,77 @@
+"""GPU: the screening pass's 7-bit code compare on inputs built to break it.
+
+The screen drops a pair once its lower-bound count exceeds the query's bound;
+an overcount would drop a pair of the exact answer, so exact top-k answers
+against the oracle are the check.  Every case uses at least eight queries so
+that lanes hold enough live entries for the code compare to run."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2504_13446_amd import rkr
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, dtype):
+    return rkr.to_device(x, dtype)
+
+
+def _check(idx, U, P, Qv, ks):
+    R = O.ranks(U, P, Qv)
+    ids, rk, off = idx.query_batch(_dev(Qv, "f32"), ks)
+    ids = ids.cpu().numpy(); rk = rk.cpu().numpy()
+    for i in range(Qv.shape[0]):
+        wi, wr = O.topk(R[i], int(ks[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], wi), i
+        assert np.array_equal(rk[off[i]:off[i + 1]], wr), i
+    return idx.stats()
+
+
+@pytest.mark.parametrize("score", ["bf16", "fp8", "f32"])
+def test_flat_steps(score):
+    """Five distinct item vectors, each repeated 160 times: after the norm sort
+    whole steps hold one item, every lane sees a flat score range (scale 0,
+    nothing counted by codes)."""
+    rng = np.random.default_rng(71)
+    d = 24
+    base = rng.standard_normal((5, d)).astype(np.float32)
+    P = np.repeat(base, 160, axis=0)
+    U = rng.standard_normal((400, d)).astype(np.float32)
+    Qv = np.concatenate([base, rng.standard_normal((5, d)).astype(np.float32)])
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score=score)
+    _check(idx, U, P, Qv, np.array([1, 3, 10, 25, 50, 7, 7, 90, 2, 13], np.int32))
+    idx.close()
+
+
+@pytest.mark.parametrize("score", ["bf16", "f32"])
+def test_offset_scores(score):
+    """Scores = 1000 + a small spread: the codes' range is tiny against the
+    scores' magnitude (x - mn loses no bits that matter, the codes must still
+    only undercount)."""
+    rng = np.random.default_rng(72)
+    n, m, d = 900, 1500, 16
+    U = rng.standard_normal((n, d)).astype(np.float32) * 1e-3
+    U[:, 0] = 1.0
+    P = rng.standard_normal((m, d)).astype(np.float32)
+    P[:, 0] = 1000.0
+    Qv = np.concatenate([P[rng.choice(m, 8, replace=False)], rng.standard_normal((4, d)).astype(np.float32)])
+    Qv[8:, 0] = 1000.0
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score=score)
+    _check(idx, U, P, Qv, np.full(12, 20, np.int32))
+    idx.close()
+
+
+@pytest.mark.parametrize("score", ["bf16", "fp8"])
+def test_integer_ties_many_queries(score):
+    """Entries in {-1, 0, 1}: scores are small integers, so most codes sit on
+    the thresholds' own code; 24 queries keep the code compare on."""
+    rng = np.random.default_rng(73)
+    n, m, d = 700, 2100, 6
+    U = rng.integers(-1, 2, size=(n, d)).astype(np.float32)
+    P = rng.integers(-1, 2, size=(m, d)).astype(np.float32)
+    Qv = P[rng.choice(m, 24, replace=False)]
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score=score)
+    ks = np.array([1, 2, 5, 9, 17, 33, 60, 100] * 3, np.int32)
+    _check(idx, U, P, Qv, ks)
+    idx.close()
