@@ -91,6 +91,31 @@ __device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_byt
     }
 }
 
+// LDS stages of P: the exact passes (little work per step) keep up to four
+// steps in flight, screening (long steps) double-buffers.  150 KB of LDS at most.
+template <int MODE>
+constexpr int stage_buffers(int step_bytes) {
+    if (MODE != CM_EXACT) return 2;
+    const int nb = 153600 / step_bytes;
+    return nb < 2 ? 2 : (nb > 4 ? 4 : nb);
+}
+// Staging loads the last wave of a workgroup issues per step (the fewest of
+// any wave): a lower bound on the vector-memory operations a step's staging
+// adds to every wave's counter.
+constexpr int stage_loads_min(int step_bytes) {
+    int c = 0;
+    for (int j = 0; j < 64; ++j)
+        if ((j * 512 + (WAVES_PER_WG - 1) * 64) * 16 < step_bytes) ++c;
+    return c;
+}
+// s_waitcnt for at most N outstanding vector-memory operations (the other
+// counters left free).
+template <int N>
+__device__ inline void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 template <int SK, int MODE, int NKS, int NUB, int NIB>
 __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, uint64_t &ncmp,
                                   uint64_t &nslot) {
@@ -103,6 +128,10 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     constexpr int LOADS_MAX = (STEP_BYTES_MAX + 512 * 16 - 1) / (512 * 16);
 
     constexpr int step_bytes = STEP_BYTES_MAX;
+    constexpr int NBUF = stage_buffers<MODE>(STEP_BYTES_MAX);
+    // when step st + 1 must have landed, the staging of at most NBUF - 2 later
+    // steps (each >= LOADS_MIN operations) may still be in flight
+    constexpr int WAIT_N = (NBUF - 2) * stage_loads_min(STEP_BYTES_MAX);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -249,15 +278,53 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         nslot += (uint64_t)lim * (NIB * 16);
     };
 
+    // Exact passes: the first EC entries of each lane's list stay in registers
+    // (fields and running count) for the whole scan; most lists of the seed,
+    // refine and all-ranks passes hold one or two pairs.
+    constexpr int EC = MODE == CM_EXACT ? 2 : 0;
+    int rpid[NUB][EC > 0 ? EC : 1];
+    float rth[NUB][EC > 0 ? EC : 1], rtl[NUB][EC > 0 ? EC : 1], rtm[NUB][EC > 0 ? EC : 1];
+    uint32_t rcnt[NUB][EC > 0 ? EC : 1];
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub)
+#pragma unroll
+        for (int k = 0; k < EC; ++k) {
+            rcnt[ub][k] = 0;
+            rpid[ub][k] = 0;
+            rth[ub][k] = rtl[ub][k] = rtm[ub][k] = 0.0f;
+            if (k < len[ub]) {
+                const int64_t e = ebase[ub] + (int64_t)k * 32;
+                rpid[ub][k] = a.ent_pid[e];
+                rth[ub][k] = a.ent_th[e];
+                rtl[ub][k] = a.ent_tl[e];
+                rtm[ub][k] = a.ent_tm[e];
+            }
+        }
+
     int any_live = 0;
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
     if (!__syncthreads_or(any_live) || s_begin >= s_end) return;
 
-    // ---- prologue: stage the first step (direct global -> LDS, 16 bytes per lane)
-    stage_step<LOADS_MAX>(a.plp + s_begin * (int64_t)step_bytes, lds, step_bytes, tid);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // ---- prologue: stage the first NBUF - 1 steps (direct global -> LDS, 16
+    // bytes per lane); wait for the first
+    const int64_t npro = std::min<int64_t>(NBUF - 1, s_end - s_begin);
+    for (int64_t k = 0; k < npro; ++k)
+        stage_step<LOADS_MAX>(a.plp + (s_begin + k) * (int64_t)step_bytes, lds + k * STEP_BYTES_MAX, step_bytes,
+                              tid);
+    if (s_begin + NBUF - 2 < s_end)
+        wait_vm<WAIT_N>();
+    else
+        wait_vm<0>();
+    // "any list still live" flags of the step-end barrier: one slot per step,
+    // three in rotation; the slot of step k - 1 is cleared after the barrier
+    // of step k (every read of it precedes that barrier) and reused at step
+    // k + 2 (whose writes follow the barrier of step k + 1)
+    __shared__ int wg_live[3];
+    if (tid < 3) wg_live[tid] = 0;
+    int lslot = 0;
     __syncthreads();
+    int cbuf = 0;   // LDS stage holding step st
 
     // Screening, second half of the workgroup: its waves count a step's codes
     // at the start of the next step, before their matrix-core work, so that on
@@ -281,18 +348,18 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     };
 
     for (int64_t st = s_begin; st < s_end; ++st) {
-        const int buf = (int)((st - s_begin) & 1);
-        const uint8_t *tile = lds + buf * STEP_BYTES_MAX;
-        // prefetch the next step straight into the other LDS buffer; it was last
-        // read in the previous step, before the barrier that ended it
+        const uint8_t *tile = lds + cbuf * STEP_BYTES_MAX;
+        // prefetch step st + NBUF - 1 straight into its LDS stage; that stage was
+        // last read in the previous step, before the barrier that ended it
         if constexpr (MODE == CM_SCREEN) {
 #pragma unroll
             for (int ub = 0; ub < NUB; ++ub) fetch_first(ub);
         }
-        const bool has_next = (st + 1 < s_end);
-        if (has_next)
-            stage_step<LOADS_MAX>(a.plp + (st + 1) * (int64_t)step_bytes, lds + (buf ^ 1) * STEP_BYTES_MAX,
+        if (st + NBUF - 1 < s_end) {
+            const int pb = cbuf + NBUF - 1 >= NBUF ? cbuf - 1 : cbuf + NBUF - 1;
+            stage_step<LOADS_MAX>(a.plp + (st + NBUF - 1) * (int64_t)step_bytes, lds + pb * STEP_BYTES_MAX,
                                   step_bytes, tid);
+        }
         if constexpr (MODE == CM_SCREEN) {
             if (late && have_prev) {
 #pragma unroll
@@ -438,31 +505,10 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 }
                 continue;
             }
-            int w = 0;
             const int mylen = len[ub];
-            // software pipeline: the fields of entry i + 1 load while entry i is counted
-            int pid_n = 0;
-            float th_n = 0.0f, tl_n = 0.0f, tm_n = 0.0f;
-            uint32_t cnt_n = 0;
-            auto fetch = [&](int i) {
-                const int64_t e = ebase[ub] + (int64_t)i * 32;
-                pid_n = a.ent_pid[e];
-                th_n = a.ent_th[e];
-                tl_n = a.ent_tl[e];
-                tm_n = a.ent_tm[e];
-                cnt_n = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
-            };
-            if (mylen > 0) fetch(0);
-            uint32_t it_act = 0, it_all = 0;
-            for (int i = 0; __ballot(i < mylen) != 0ull; ++i) {
-                const bool act = i < mylen;
-                const int64_t e = ebase[ub] + (int64_t)i * 32;
-                // take every field of entry i before the prefetch overwrites them
-                const int pid = pid_n;
-                const float th = th_n;
-                const float tl = tl_n, tmv = tm_n;
-                uint32_t cnt = cnt_n;
-                if (i + 1 < mylen) fetch(i + 1);
+            // band count of one entry against the step's scores: certainly-above
+            // scores add to cnt, near ties are emitted for the FP64 recheck
+            auto exact_entry = [&](bool act, int pid, float th, float tl, float tmv, uint32_t &cnt) {
                 const float hi = a.plain ? th : f32_next_up(th + eps);
                 uint32_t c = 0;
                 const float lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
@@ -471,10 +517,10 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const float s = acc[ib][ub][r];
-                        const bool gt = s > hi;
+                        const float sv = acc[ib][ub][r];
+                        const bool gt = sv > hi;
                         c += gt ? 1u : 0u;
-                        umask |= (!gt && s >= lo) ? (1u << (ib * 16 + r)) : 0u;
+                        umask |= (!gt && sv >= lo) ? (1u << (ib * 16 + r)) : 0u;
                     }
                 if (!act) umask = 0;
                 if (__ballot(umask != 0) != 0ull) {
@@ -503,23 +549,61 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                         ++pos;
                     }
                 }
-                c = pair_sum(c);
-                cnt += c;
+                cnt += pair_sum(c);
+            };
+            // the first EC entries live in registers for the whole scan
+#pragma unroll
+            for (int k = 0; k < EC; ++k)
+                if (__ballot(k < mylen) != 0ull)
+                    exact_entry(k < mylen, rpid[ub][k], rth[ub][k], rtl[ub][k], rtm[ub][k], rcnt[ub][k]);
+            // the rest: fields from memory (the fields of entry i + 1 load while
+            // entry i is counted), the partial count kept per split
+            int pid_n = 0;
+            float th_n = 0.0f, tl_n = 0.0f, tm_n = 0.0f;
+            uint32_t cnt_n = 0;
+            auto fetch = [&](int i) {
+                const int64_t e = ebase[ub] + (int64_t)i * 32;
+                pid_n = a.ent_pid[e];
+                th_n = a.ent_th[e];
+                tl_n = a.ent_tl[e];
+                tm_n = a.ent_tm[e];
+                cnt_n = (st == s_begin) ? 0u : a.ent_cnt[(int64_t)split * a.cap_total + e];
+            };
+            if (mylen > EC) fetch(EC);
+            for (int i = EC; __ballot(i < mylen) != 0ull; ++i) {
+                const bool act = i < mylen;
+                const int64_t e = ebase[ub] + (int64_t)i * 32;
+                // take every field of entry i before the prefetch overwrites them
+                const int pid = pid_n;
+                const float th = th_n;
+                const float tl = tl_n, tmv = tm_n;
+                uint32_t cnt = cnt_n;
+                if (i + 1 < mylen) fetch(i + 1);
+                exact_entry(act, pid, th, tl, tmv, cnt);
                 if (act && half == 0) a.ent_cnt[(int64_t)split * a.cap_total + e] = cnt;
-                it_act += act ? 1u : 0u;
-                it_all += 1u;
             }
-            (void)w;
-            ncmp += (uint64_t)it_act * (NIB * 16);
-            nslot += (uint64_t)it_all * (NIB * 16);
+            ncmp += (uint64_t)mylen * (NIB * 16);
+            nslot += (uint64_t)wave_max(mylen) * (NIB * 16);
         }
 
         have_prev = late;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // step st + 1 has landed (same-wave entry stores stay ordered before
+        // the next step's loads of the same slots)
+        if (st + NBUF - 1 < s_end)
+            wait_vm<WAIT_N>();
+        else
+            wait_vm<0>();
+        cbuf = cbuf + 1 == NBUF ? 0 : cbuf + 1;
         int live = 0;
 #pragma unroll
         for (int ub = 0; ub < NUB; ++ub) live |= (len[ub] > 0);
-        if (!__syncthreads_or(live)) break;
+        const bool wave_live = __ballot(live) != 0ull;    // every lane takes part
+        if (lane == 0 && wave_live) atomicOr(&wg_live[lslot], 1);
+        __syncthreads();
+        const int any = wg_live[lslot];
+        if (tid == 0) wg_live[lslot == 0 ? 2 : lslot - 1] = 0;
+        lslot = lslot == 2 ? 0 : lslot + 1;
+        if (!any) break;
     }
 
     if constexpr (MODE == CM_SCREEN) {
@@ -540,7 +624,10 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             if (half == 0) a.ent_len[tix[ub]] = len[ub];
         } else {
             if (half == 0) {
-                for (int i = 0; i < len[ub]; ++i) {
+#pragma unroll
+                for (int k = 0; k < EC; ++k)
+                    if (k < len[ub]) atomicAdd(&a.cnt_out[rpid[ub][k]], rcnt[ub][k]);
+                for (int i = EC; i < len[ub]; ++i) {
                     const int64_t e = ebase[ub] + (int64_t)i * 32;
                     atomicAdd(&a.cnt_out[a.ent_pid[e]], a.ent_cnt[(int64_t)split * a.cap_total + e]);
                 }
@@ -588,7 +675,7 @@ template <int SK, int MODE, int NKS, int NUB, int NIB>
 static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
-    const size_t lds = 2 * STEP_BYTES_MAX;
+    const size_t lds = (size_t)stage_buffers<MODE>(STEP_BYTES_MAX) * STEP_BYTES_MAX;
     if (a.nks != NKS) return hipErrorInvalidValue;   // layouts are padded to a supported k-step count
     const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
     if (ntiles == 0) return hipSuccess;

@@ -75,3 +75,33 @@ def test_integer_ties_many_queries(score):
     ks = np.array([1, 2, 5, 9, 17, 33, 60, 100] * 3, np.int32)
     _check(idx, U, P, Qv, ks)
     idx.close()
+
+
+def test_screen_kills_what_it_should():
+    """The screen's pruning power, pinned.  Seeds follow the default rule (the
+    2k users of smallest -t/|u|, ties to the smaller id), the bound B_q is the
+    k-th smallest seed rank, and the screen drops a pair once its certain
+    count reaches B_q.  So every non-seed pair of rank <= B_q must survive,
+    and a pair of rank well above B_q must not (only items inside the error
+    band or sharing a threshold's 7-bit code go uncounted)."""
+    from paper_2504_13446_amd import workloads as W
+    w = W.make("small", n=3000, m=4000, nq=12)
+    k = 20
+    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16")
+    idx.configure(seed_mult=2)
+    R = O.ranks(w.U, w.P, w.Qv).astype(np.int64)
+    T = O.dots(w.U, w.Qv)                                     # [n, nq]
+    nu = O.norms(w.U)
+    lo = hi = 0
+    for q in range(w.Qv.shape[0]):
+        h = (-T[:, q] / nu).astype(np.float32)
+        seeds = np.lexsort((np.arange(w.n), h))[:2 * k]
+        _, wr = O.topk(R[q][seeds], k, uids=seeds)
+        B = int(wr[-1])
+        nonseed = np.ones(w.n, bool); nonseed[seeds] = False
+        lo += int(np.sum(nonseed & (R[q] <= B)))
+        hi += int(np.sum(nonseed & (R[q] <= 1.3 * B + 10)))
+    ids, rk, off = idx.query_batch(_dev(w.Qv, "f32"), np.full(w.Qv.shape[0], k, np.int32))
+    st = idx.stats()
+    idx.close()
+    assert lo <= st["survivors"] <= hi, (lo, st["survivors"], hi)
