@@ -24,8 +24,10 @@
 // smallest rank): its rank is then > B >= R_k, so it cannot be in the answer
 // (Def. 2), the counts only grow.  This is the paper's Lemma 1 (2) filter
 // applied to exact partial counts.  A screen entry holds (pid, th, rem) with
-// rem = B[q] - 1 - count: the pair dies when rem turns negative, and an entry
-// that keeps its slot only rewrites rem.
+// rem = B[q] - 1 - count: the pair dies when rem turns negative; survivors are
+// compacted to the front of the user's list every step.  With enough live
+// entries the screen compares 7-bit monotone codes of the scores instead of
+// the scores (a lower bound of the certain count, four compares per dword).
 #include "rkr_internal.h"
 
 #include <algorithm>
