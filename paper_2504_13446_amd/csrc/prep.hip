@@ -298,6 +298,47 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
 // The item id is in sorted order; its master row sits in Pm_sorted.
 // Bit 31 of the item field carries the plain FP32 verdict (score > fl32(t)).
 // ---------------------------------------------------------------------------
+// The spec inner product of master rows a and b: one FP64 fma chain in
+// dimension order.  Rows are read 16 bytes at a time when both are 16-byte
+// aligned; the chain (and so the result) is the same either way.
+__device__ inline double spec_dot_rows(const void *A, int64_t ra, const void *B, int64_t rb, int d, int mk) {
+    double acc = 0.0;
+    if (mk == MK_BF16) {
+        const uint16_t *a = (const uint16_t *)A + ra * d, *b = (const uint16_t *)B + rb * d;
+        int k = 0;
+        if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0) {
+            for (; k + 8 <= d; k += 8) {
+                const uint4 va = *(const uint4 *)(a + k), vb = *(const uint4 *)(b + k);
+                const uint32_t wa[4] = {va.x, va.y, va.z, va.w}, wb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // element 2j is the low half of word j, element 2j + 1 the high half
+                    acc = fma((double)__uint_as_float(wa[j] << 16), (double)__uint_as_float(wb[j] << 16), acc);
+                    acc = fma((double)__uint_as_float(wa[j] & 0xFFFF0000u),
+                              (double)__uint_as_float(wb[j] & 0xFFFF0000u), acc);
+                }
+            }
+        }
+        for (; k < d; ++k)
+            acc = fma((double)__uint_as_float((uint32_t)a[k] << 16), (double)__uint_as_float((uint32_t)b[k] << 16),
+                      acc);
+        return acc;
+    }
+    const float *a = (const float *)A + ra * d, *b = (const float *)B + rb * d;
+    int k = 0;
+    if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0) {
+        for (; k + 4 <= d; k += 4) {
+            const float4 va = *(const float4 *)(a + k), vb = *(const float4 *)(b + k);
+            acc = fma((double)va.x, (double)vb.x, acc);
+            acc = fma((double)va.y, (double)vb.y, acc);
+            acc = fma((double)va.z, (double)vb.z, acc);
+            acc = fma((double)va.w, (double)vb.w, acc);
+        }
+    }
+    for (; k < d; ++k) acc = fma((double)a[k], (double)b[k], acc);
+    return acc;
+}
+
 __global__ void k_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, const double *t64,
                           const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                           unsigned long long *flips) {
@@ -309,9 +350,7 @@ __global__ void k_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, 
         const int64_t item = r.y & 0x7FFFFFFF;
         const bool plain = (r.y >> 31) & 1;
         const int64_t u = pair_u[pid];
-        double acc = 0.0;
-        for (int k = 0; k < d; ++k)
-            acc = fma(master_elem(Um, mk, u * d + k), master_elem(Pm, mk, item * d + k), acc);
+        const double acc = spec_dot_rows(Um, u, Pm, item, d, mk);
         const bool above = acc > t64[pid];
         if (above) atomicAdd(&cnt[pid], 1u);
         flip = above != plain;
@@ -334,9 +373,7 @@ __global__ void k_recheck_dev(const int2 *rec, const unsigned long long *count, 
         const int64_t item = r.y & 0x7FFFFFFF;
         const bool plain = (r.y >> 31) & 1;
         const int64_t u = pair_u[pid];
-        double acc = 0.0;
-        for (int k = 0; k < d; ++k)
-            acc = fma(master_elem(Um, mk, u * d + k), master_elem(Pm, mk, item * d + k), acc);
+        const double acc = spec_dot_rows(Um, u, Pm, item, d, mk);
         const bool above = acc > t64[pid];
         if (above) atomicAdd(&cnt[pid], 1u);
         nflip += (above != plain) ? 1u : 0u;

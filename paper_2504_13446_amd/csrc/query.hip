@@ -66,6 +66,43 @@ __global__ void k_seed_keys(QView v, const int32_t *pair_u, const double *t64, c
     keys[j] = ((uint64_t)f32_order_key(h) << 32) | (uint32_t)i;
 }
 
+// Dense domains: the same keys, one workgroup per tile of 64 users x 32
+// queries through LDS, so the reads of the user-major pair arrays and the
+// writes of the query-major keys are both coalesced.
+__global__ __launch_bounds__(256) void k_seed_keys_dense(int64_t n, int nq, const double *t64,
+                                                         const double *unorm3, const float *pred,
+                                                         uint64_t *keys) {
+    __shared__ float s_h[32][65];
+    const int64_t u0 = (int64_t)blockIdx.x * 64;
+    const int q0 = blockIdx.y * 32;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int uu = r * 8 + (tid >> 5), qq = tid & 31;
+        const int64_t u = u0 + uu;
+        const int q = q0 + qq;
+        if (u < n && q < nq) {
+            const int64_t pid = u * nq + q;
+            float h;
+            if (pred) {
+                h = pred[pid];
+            } else {
+                const double nu = unorm3[3 * u + 2];
+                h = nu > 0.0 ? (float)(-t64[pid] / nu) : 0.0f;
+            }
+            s_h[qq][uu] = h;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int qq = r * 4 + (tid >> 6), uu = tid & 63;
+        const int64_t u = u0 + uu;
+        const int q = q0 + qq;
+        if (u < n && q < nq) keys[(int64_t)q * n + u] = ((uint64_t)f32_order_key(s_h[qq][uu]) << 32) | (uint32_t)u;
+    }
+}
+
 __global__ void k_mark_selected(QView v, const uint64_t *sel, const int64_t *sel_off, int64_t total,
                                 uint8_t *flag) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,6 +242,12 @@ __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t nb) {
 
 hipError_t q_seed_keys(const QView &v, const int32_t *pair_u, const double *t64, const double *unorm3,
                        const float *pred, int64_t total, uint64_t *keys, hipStream_t st) {
+    if (v.dense) {
+        if (v.n > 0 && v.nq > 0)
+            hipLaunchKernelGGL(k_seed_keys_dense, dim3((unsigned)((v.n + 63) / 64), (unsigned)((v.nq + 31) / 32)),
+                               dim3(256), 0, st, v.n, v.nq, t64, unorm3, pred, keys);
+        return hipGetLastError();
+    }
     LAUNCH1D(k_seed_keys, total, v, pair_u, t64, unorm3, pred, total, keys);
     return hipGetLastError();
 }

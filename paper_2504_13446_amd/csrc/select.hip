@@ -254,26 +254,63 @@ __global__ void k_block_cap(const int32_t *len, int64_t nblk, int64_t *cap32) {
     cap32[b] = 32 * (int64_t)mx;
 }
 
-__global__ void k_fill_entries(const int32_t *pids, int64_t N, const int32_t *flag, const int64_t *excl,
-                               const int64_t *task_start, const int64_t *blk_base, const int32_t *pair_q,
-                               const float *th, const float *tl, const float *tm, int plain,
-                               const int32_t *bound, int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt,
-                               float *ent_th, float *ent_tl, float *ent_tm) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int64_t t = excl[i] + flag[i] - 1;
-    int64_t j = i - task_start[t];
-    int64_t e = blk_base[t >> 5] + j * 32 + (t & 31);
-    int32_t pid = pids[i];
-    ent_pid[e] = pid;
-    const int32_t q = pair_q[pid];
-    ent_q[e] = q;
-    // screen entries start with the remaining budget B[q] - 1, exact ones with count 0
-    ent_cnt[e] = bound ? (uint32_t)(bound[q] - 1) : 0u;
-    // plain mode compares the score with fl32(t) itself: both edges = fl32(t)
-    ent_th[e] = plain ? tm[pid] : th[pid];
-    ent_tl[e] = plain ? tm[pid] : tl[pid];
-    ent_tm[e] = tm[pid];
+// Entry fill, one workgroup per block of 32 tasks, 64 slots per pass through
+// an LDS tile: reads run along a task's pairs (consecutive), writes along the
+// 32 lanes of a slot (consecutive), so both sides coalesce.  Screening entries
+// get (pid, upper edge, remaining budget B[q] - 1); exact entries (pid, both
+// edges, fl32(t)) -- their counts start at 0 in the kernel itself.
+template <bool SCREEN>
+__global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const int64_t *task_start,
+                                                      const int32_t *len, int64_t ntask, const int64_t *blk_base,
+                                                      int64_t nblk, int64_t cap_total,
+                                                      const int32_t *pair_q, const float *th, const float *tl,
+                                                      const float *tm, int plain, const int32_t *bound,
+                                                      int32_t *ent_pid, uint32_t *ent_cnt, float *ent_th,
+                                                      float *ent_tl, float *ent_tm) {
+    constexpr int JT = 64;
+    __shared__ int32_t s_pid[32][JT + 1];
+    __shared__ float s_a[32][JT + 1], s_b[32][JT + 1], s_c[32][JT + 1];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t base = blk_base[b];
+    const int64_t cap = ((b + 1 < nblk ? blk_base[b + 1] : cap_total) - base) / 32;
+    for (int64_t j0 = 0; j0 < cap; j0 += JT) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int l = r * 4 + (tid >> 6), jj = tid & 63;
+            const int64_t t = b * 32 + l, j = j0 + jj;
+            if (t < ntask && j < len[t]) {
+                const int32_t pid = pids[task_start[t] + j];
+                s_pid[l][jj] = pid;
+                // plain mode compares the score with fl32(t) itself: both edges = fl32(t)
+                s_a[l][jj] = plain ? tm[pid] : th[pid];
+                if constexpr (SCREEN) {
+                    s_b[l][jj] = __int_as_float(bound[pair_q[pid]] - 1);
+                } else {
+                    s_b[l][jj] = plain ? tm[pid] : tl[pid];
+                    s_c[l][jj] = tm[pid];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int jj = r * 8 + (tid >> 5), l = tid & 31;
+            const int64_t t = b * 32 + l, j = j0 + jj;
+            if (t < ntask && j < len[t]) {
+                const int64_t e = base + j * 32 + l;
+                ent_pid[e] = s_pid[l][jj];
+                ent_th[e] = s_a[l][jj];
+                if constexpr (SCREEN) {
+                    ent_cnt[e] = (uint32_t)__float_as_int(s_b[l][jj]);
+                } else {
+                    ent_tl[e] = s_b[l][jj];
+                    ent_tm[e] = s_c[l][jj];
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, const int32_t *bound,
@@ -308,9 +345,16 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     if ((e = hipMemcpyAsync(&cap_total, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     if ((e = ts.reserve_entries(cap_total)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_entries, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, flag, excl, task_start,
-                       ts.blk_base, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound, ts.ent_pid, ts.ent_q,
-                       ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+    if (bound)
+        hipLaunchKernelGGL(k_fill_entries<true>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
+                           ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound,
+                           ts.ent_pid,
+                           ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+    else
+        hipLaunchKernelGGL(k_fill_entries<false>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
+                           ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound,
+                           ts.ent_pid,
+                           ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     ts.ntask = ntask;
     ts.ntask_pad = ntask_pad;
     ts.cap_total = cap_total;
