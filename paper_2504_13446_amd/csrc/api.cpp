@@ -579,8 +579,11 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(launch_fill_u8(x->seedflag.as<uint8_t>(), 0, npairs, st));
     HIPCK(q_mark_selected(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->seedflag.as<uint8_t>(), st));
     HIPCK(x->seedpid.ensure(nsel * 4));
+    HIPCK(x->allpid.ensure(npairs * 4));
     int64_t nseed = 0;
-    HIPCK(q_compact_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), &nseed, x->sc, st));
+    // seeds (counted exactly below) and the other pairs (the ones to screen)
+    HIPCK(q_split_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), &nseed,
+                        x->allpid.as<int32_t>(), st, x->sc));
     x->stats.seed_pairs = nseed;
     // ---- 4. exact count of the seeds
     HIPCK(x->cnt.ensure(npairs * 4));
@@ -607,10 +610,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     if (pruned) need_screen = false;
     int64_t nsurv = 0;
     HIPCK(x->surv.ensure(npairs * 4));
-    if (need_screen) {
-        HIPCK(x->allpid.ensure(npairs * 4));
-        HIPCK(launch_iota(x->allpid.as<int32_t>(), npairs, st));
-        hipError_t e = build_tasks(x->allpid.as<int32_t>(), npairs, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
+    const int64_t nscreen = npairs - nseed;   // the seeds' ranks are known: they are not screened
+    if (need_screen && nscreen > 0) {
+        hipError_t e = build_tasks(x->allpid.as<int32_t>(), nscreen, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
                                    x->ts_screen, x->sc, st);
         if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
         // the screening kernel addresses entries with 32-bit byte offsets

@@ -36,6 +36,9 @@ hipError_t q_rank_keys_sel(const QView &v, const uint64_t *sel, const int64_t *s
                            const uint32_t *cnt, uint64_t *keys, hipStream_t st);
 hipError_t q_bounds(const uint64_t *best, const int64_t *best_off, const int32_t *k, const double *c, int nq,
                     int32_t *bound, int32_t *seed_kth, hipStream_t st);
+// flagged indices to out1 (their number to *count1), the others to out0
+hipError_t q_split_flags(const uint8_t *flag, int64_t N, int32_t *out1, int64_t *count1, int32_t *out0,
+                         hipStream_t st, Scratch &sc);
 hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, int64_t *count, Scratch &sc,
                        hipStream_t st);
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,

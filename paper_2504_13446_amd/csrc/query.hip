@@ -117,6 +117,17 @@ __global__ void k_scatter_flagged(const uint8_t *flag, const int64_t *excl, int6
     if (i < N && flag[i]) out[excl[i]] = (int32_t)i;
 }
 
+// Both sides of a flag array: flagged indices to out1 (ascending), the others
+// to out0 (ascending), from one exclusive scan of the flags.
+__global__ void k_scatter_split(const uint8_t *flag, const int64_t *excl, int64_t N, int32_t *out1, int32_t *out0) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (flag[i])
+        out1[excl[i]] = (int32_t)i;
+    else
+        out0[i - excl[i]] = (int32_t)i;
+}
+
 __global__ void k_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) cnt[pids[i]] = 0;
@@ -265,6 +276,17 @@ hipError_t q_compact_flags(const uint8_t *flag, int64_t N, int32_t *out, int64_t
     if (e != hipSuccess) return e;
     LAUNCH1D(k_scatter_flagged, N, flag, excl, N, out);
     if ((e = hipMemcpyAsync(count, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+hipError_t q_split_flags(const uint8_t *flag, int64_t N, int32_t *out1, int64_t *count1, int32_t *out0,
+                         hipStream_t st, Scratch &sc) {
+    int64_t *excl = (int64_t *)sc.take(N * 8 + 8);
+    int64_t *dtot = (int64_t *)sc.take(16);
+    if (!excl || !dtot) return hipErrorOutOfMemory;
+    hipError_t e = scan_u8(flag, N, excl, dtot, sc, st);
+    if (e != hipSuccess) return e;
+    LAUNCH1D(k_scatter_split, N, flag, excl, N, out1, out0);
+    if ((e = hipMemcpyAsync(count1, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }
 hipError_t q_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt, hipStream_t st) {
