@@ -169,7 +169,7 @@ struct rkr_index {
     DBuf pair_u, pair_q, pair_off, qm_pid, t64, th, tl, tm, cnt, seedflag, keys, sel, selrank, best, cand,
         candkeys, ans, seedpid, surv, emit, ctr, bound, seedkth, kdev, sdev, cdev, segoff, seloff, bestoff,
         candoff, cursor, qcount, flags, allpid;
-    TaskSet ts_screen, ts_exact;
+    TaskSet ts_screen, ts_screen2, ts_exact;
     int64_t emit_cap = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     rkr_query_opts qo{};
@@ -299,6 +299,7 @@ extern "C" void rkr_destroy(rkr_index *x) {
                     &x->qcount, &x->flags, &x->allpid};
     for (DBuf *b : bufs) b->release();
     x->ts_screen.release();
+    x->ts_screen2.release();
     x->ts_exact.release();
     x->rg.release();
     for (auto &e : x->ev)
@@ -380,6 +381,8 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int va
     a.nq = ps.nq;
     a.nsteps = (x->nblk32 + nib - 1) / nib;
     a.steps_per_split = a.nsteps;
+    a.step0 = 0;
+    a.step_end = a.nsteps;
     a.cnt_out = x->cnt.as<uint32_t>();
     a.emit = x->emit.as<int2>();
     a.emit_count = x->ctr.as<unsigned long long>();
@@ -624,24 +627,59 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         const int cand = x->tuner.pick(key, 2 * ntv);
         const int variant = cand % ntv;
         const bool persistent = cand >= ntv;
-        CountArgs a = count_args(x, ps, x->ts_screen, variant);
-        if (persistent) {
-            HIPCK(launch_fill_u32(x->ctr.as<uint32_t>() + 8, 0, 2, st));
-            a.tile_counter = x->ctr.as<unsigned long long>() + 4;
-            a.persistent_ctas = x->num_cus;
-        }
+        // The scan runs in phases.  Every user stays live through the first
+        // quarter or so of P, then users die fast; after a phase whose end
+        // leaves fewer than half of the current tasks live, the live pairs are
+        // compacted, with their remaining budgets, into a new dense task set,
+        // so that later steps run only tiles of live users.
+        static const int kPhaseEnd32[] = {9, 10, 11, 12, 14, 16, 20, 32};   // in 32nds of the scan
         HIPCK(ensure_events(x));
-        HIPCK(hipEventRecord(x->ev[0], st));
-        HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, variant, st));
-        HIPCK(hipEventRecord(x->ev[1], st));
-        HIPCK(hipStreamSynchronize(st));
-        x->stats.ms_screen_kernel = event_ms(x->ev[0], x->ev[1]);
-        x->tuner.record(key, cand, x->stats.ms_screen_kernel, 2 * ntv);
-        x->stats.screen_variant = cand;
+        TaskSet *cur = &x->ts_screen, *nxt = &x->ts_screen2;
         const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
-        x->stats.screen_ctas = persistent ? std::min<int64_t>(x->num_cus, (x->ts_screen.ntask + tpw - 1) / tpw)
-                                          : (x->ts_screen.ntask + tpw - 1) / tpw;
-        TView tv{x->ts_screen.ntask, x->ts_screen.len, x->ts_screen.blk_base, x->ts_screen.ent_pid};
+        const int64_t nsteps = count_args(x, ps, *cur, variant).nsteps;
+        int64_t s0 = 0;
+        double ms_kernel = 0.0;
+        x->stats.screen_ctas = 0;
+        for (int ph = 0; ph < (int)(sizeof kPhaseEnd32 / sizeof kPhaseEnd32[0]) && s0 < nsteps; ++ph) {
+            const int64_t s1 = kPhaseEnd32[ph] == 32 ? nsteps : nsteps * kPhaseEnd32[ph] / 32;
+            if (s1 <= s0) continue;
+            CountArgs a = count_args(x, ps, *cur, variant);
+            a.step0 = s0;
+            a.step_end = s1;
+            a.steps_per_split = s1 - s0;
+            if (persistent) {
+                HIPCK(launch_fill_u32(x->ctr.as<uint32_t>() + 8, 0, 2, st));
+                a.tile_counter = x->ctr.as<unsigned long long>() + 4;
+                a.persistent_ctas = x->num_cus;
+            }
+            HIPCK(hipEventRecord(x->ev[0], st));
+            HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, variant, st));
+            HIPCK(hipEventRecord(x->ev[1], st));
+            HIPCK(hipStreamSynchronize(st));
+            ms_kernel += event_ms(x->ev[0], x->ev[1]);
+            const int64_t tiles = (cur->ntask + tpw - 1) / tpw;
+            x->stats.screen_ctas = std::max<int64_t>(x->stats.screen_ctas,
+                                                     persistent ? std::min<int64_t>(x->num_cus, tiles) : tiles);
+            s0 = s1;
+            if (s0 >= nsteps) break;
+            int64_t nlive = 0;
+            HIPCK(q_count_live(cur->len, cur->ntask, x->ctr.as<unsigned long long>() + 6, &nlive, st));
+            if (nlive == 0) break;                       // every screened pair is dead
+            if (2 * nlive >= cur->ntask) continue;       // still dense: keep the tiles
+            // compact: live pairs in task order (grouped by user), budgets at cnt[pid]
+            TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
+            int64_t npl = 0;
+            HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &npl, x->sc, st,
+                              x->cnt.as<uint32_t>()));
+            e = build_tasks(x->surv.as<int32_t>(), npl, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(), *nxt, x->sc,
+                            st, x->cnt.as<uint32_t>());
+            if (e != hipSuccess) return fail_hip(e, "build_tasks (screen compaction)");
+            std::swap(cur, nxt);
+        }
+        x->stats.ms_screen_kernel = ms_kernel;
+        x->tuner.record(key, cand, ms_kernel, 2 * ntv);
+        x->stats.screen_variant = cand;
+        TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
     }
     HIPCK(hipStreamSynchronize(st));

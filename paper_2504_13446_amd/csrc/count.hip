@@ -141,9 +141,9 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     const int half = lane >> 5;
     const int split = blockIdx.y;
 
-    int64_t s_begin = (int64_t)split * a.steps_per_split;
+    int64_t s_begin = a.step0 + (int64_t)split * a.steps_per_split;
     int64_t s_end = s_begin + a.steps_per_split;
-    if (s_end > a.nsteps) s_end = a.nsteps;
+    if (s_end > a.step_end) s_end = a.step_end;
 
     // ---- this lane's users, their register-stationary fragments and entries
     int uid[NUB];

@@ -21,6 +21,7 @@ struct TView {
     const int32_t *len;
     const int64_t *blk_base;
     const int32_t *ent_pid;
+    const uint32_t *ent_cnt;    // screening: remaining budgets
 };
 
 hipError_t scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st);
@@ -39,8 +40,12 @@ hipError_t q_bounds(const uint64_t *best, const int64_t *best_off, const int32_t
 // flagged indices to out1 (their number to *count1), the others to out0
 hipError_t q_split_flags(const uint8_t *flag, int64_t N, int32_t *out1, int64_t *count1, int32_t *out0,
                          hipStream_t st, Scratch &sc);
+// live pairs of a task set (seeds excluded), in task order; with rem_out,
+// also each pair's remaining budget at rem_out[pid]
 hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, int64_t *count, Scratch &sc,
-                       hipStream_t st);
+                       hipStream_t st, uint32_t *rem_out = nullptr);
+// number of tasks whose list is not empty
+hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, int64_t *count, hipStream_t st);
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
                             hipStream_t st);
 hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t nsel,

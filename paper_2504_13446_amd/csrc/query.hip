@@ -166,16 +166,33 @@ __global__ void k_surv_count(const TView t, const uint8_t *seedflag, int32_t *cn
     for (int i = 0; i < L; ++i) c += seedflag[t.ent_pid[base + (int64_t)i * 32]] ? 0 : 1;
     cnt_task[ti] = c;
 }
-__global__ void k_surv_write(const TView t, const uint8_t *seedflag, const int64_t *off, int32_t *out) {
+__global__ void k_surv_write(const TView t, const uint8_t *seedflag, const int64_t *off, int32_t *out,
+                             uint32_t *rem_out) {
     int64_t ti = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (ti >= t.ntask) return;
     int64_t o = off[ti];
     const int L = t.len[ti];
     const int64_t base = t.blk_base[ti >> 5] + (ti & 31);
     for (int i = 0; i < L; ++i) {
-        int32_t pid = t.ent_pid[base + (int64_t)i * 32];
-        if (!seedflag[pid]) out[o++] = pid;
+        const int64_t e = base + (int64_t)i * 32;
+        int32_t pid = t.ent_pid[e];
+        if (!seedflag[pid]) {
+            out[o++] = pid;
+            if (rem_out) rem_out[pid] = t.ent_cnt[e];
+        }
     }
+}
+
+// Number of tasks with a non-empty list (one 64-bit atomic per workgroup).
+__global__ void k_count_live(const int32_t *len, int64_t n, unsigned long long *out) {
+    __shared__ unsigned int s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long b = __ballot(i < n && len[i] > 0);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s, (unsigned int)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0 && s) atomicAdd(out, (unsigned long long)s);
 }
 
 // Answer candidates per query = its seeds + its survivors.
@@ -304,7 +321,7 @@ hipError_t q_bounds(const uint64_t *best, const int64_t *best_off, const int32_t
     return hipGetLastError();
 }
 hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, int64_t *count, Scratch &sc,
-                       hipStream_t st) {
+                       hipStream_t st, uint32_t *rem_out) {
     *count = 0;
     if (t.ntask <= 0) return hipSuccess;
     int32_t *ct = (int32_t *)sc.take(t.ntask * 4);
@@ -316,8 +333,19 @@ hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, in
     if (e != hipSuccess) return e;
     if ((e = hipMemcpyAsync(count, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    LAUNCH1D(k_surv_write, t.ntask, t, seedflag, off, out);
+    LAUNCH1D(k_surv_write, t.ntask, t, seedflag, off, out, rem_out);
     return hipGetLastError();
+}
+hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, int64_t *count, hipStream_t st) {
+    *count = 0;
+    hipError_t e = launch_fill_u32((uint32_t *)dev, 0, 2, st);
+    if (e != hipSuccess) return e;
+    LAUNCH1D(k_count_live, n, len, n, dev);
+    unsigned long long c = 0;
+    if ((e = hipMemcpyAsync(&c, dev, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    *count = (int64_t)c;
+    return hipSuccess;
 }
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
                             hipStream_t st) {

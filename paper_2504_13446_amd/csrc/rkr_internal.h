@@ -89,9 +89,11 @@ struct CountArgs {
     int64_t cap_total;
     const int32_t *bound;         // [nq] abandon bound (screen mode), INT32_MAX = none
     int nq;
-    // P range: steps [split * steps_per_split, ...) of nsteps
+    // P range: steps [step0 + split * steps_per_split, ...) of nsteps, cut at step_end
     int64_t nsteps;
     int64_t steps_per_split;
+    int64_t step0;
+    int64_t step_end;
     // exact mode outputs
     uint32_t *cnt_out;            // [npairs] += certain-above count
     uint32_t *cnt_lo_out;         // interval mode: [npairs] += count of scores >= lo

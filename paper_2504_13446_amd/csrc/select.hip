@@ -265,7 +265,8 @@ __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const
                                                       int64_t nblk, int64_t cap_total,
                                                       const int32_t *pair_q, const float *th, const float *tl,
                                                       const float *tm, int plain, const int32_t *bound,
-                                                      int32_t *ent_pid, uint32_t *ent_cnt, float *ent_th,
+                                                      const uint32_t *rem_init, int32_t *ent_pid,
+                                                      uint32_t *ent_cnt, float *ent_th,
                                                       float *ent_tl, float *ent_tm) {
     constexpr int JT = 64;
     __shared__ int32_t s_pid[32][JT + 1];
@@ -285,7 +286,8 @@ __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const
                 // plain mode compares the score with fl32(t) itself: both edges = fl32(t)
                 s_a[l][jj] = plain ? tm[pid] : th[pid];
                 if constexpr (SCREEN) {
-                    s_b[l][jj] = __int_as_float(bound[pair_q[pid]] - 1);
+                    // a fresh pair starts with B[q] - 1, a carried one with its remaining budget
+                    s_b[l][jj] = __uint_as_float(rem_init ? rem_init[pid] : (uint32_t)(bound[pair_q[pid]] - 1));
                 } else {
                     s_b[l][jj] = plain ? tm[pid] : tl[pid];
                     s_c[l][jj] = tm[pid];
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const
                 ent_pid[e] = s_pid[l][jj];
                 ent_th[e] = s_a[l][jj];
                 if constexpr (SCREEN) {
-                    ent_cnt[e] = (uint32_t)__float_as_int(s_b[l][jj]);
+                    ent_cnt[e] = __float_as_uint(s_b[l][jj]);
                 } else {
                     ent_tl[e] = s_b[l][jj];
                     ent_tm[e] = s_c[l][jj];
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const
 }
 
 hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, const int32_t *bound,
-                       TaskSet &ts, Scratch &sc, hipStream_t st) {
+                       TaskSet &ts, Scratch &sc, hipStream_t st, const uint32_t *rem_init) {
     ts.ntask = 0;
     ts.ntask_pad = 0;
     ts.cap_total = 0;
@@ -348,13 +350,11 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     if (bound)
         hipLaunchKernelGGL(k_fill_entries<true>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
                            ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound,
-                           ts.ent_pid,
-                           ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+                           rem_init, ts.ent_pid, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     else
         hipLaunchKernelGGL(k_fill_entries<false>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
                            ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound,
-                           ts.ent_pid,
-                           ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+                           rem_init, ts.ent_pid, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     ts.ntask = ntask;
     ts.ntask_pad = ntask_pad;
     ts.cap_total = cap_total;
