@@ -164,6 +164,7 @@ struct rkr_index {
     hipStream_t st = nullptr;
     // index data
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
+    DBuf coef_step[3];    // per-step coefficient maxima for steps of 1, 2, 4 blocks
     // per-call buffers
     Scratch sc;
     DBuf pair_u, pair_q, pair_off, qm_pid, t64, th, tl, tm, cnt, seedflag, keys, sel, selrank, best, cand,
@@ -266,6 +267,12 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
         const double g64 = d * u64 / (1.0 - d * u64) * 1.01;
         const double eabs = dpad * ldexp(1.0, -100);
         HIPCK(launch_block_coef(x->pnorm3.as<double>(), m, x->nblk, g32, g64, eabs, x->coef.as<double>(), st));
+        for (int k = 0; k < 3; ++k) {
+            const int nib = 1 << k;
+            const int64_t ns = (x->nblk32 + nib - 1) / nib;
+            HIPCK(x->coef_step[k].ensure((size_t)std::max<int64_t>(ns, 1) * 4 * 8));
+            HIPCK(launch_step_coef(x->coef.as<double>(), x->nblk, nib, ns, x->coef_step[k].as<double>(), st));
+        }
         int flags = 0;
         HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
         HIPCK(hipStreamSynchronize(st));
@@ -292,7 +299,7 @@ extern "C" void rkr_destroy(rkr_index *x) {
     if (!x) return;
     (void)hipStreamSynchronize(x->st);
     DBuf *bufs[] = {&x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
-                    &x->coef, &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64, &x->th, &x->tl,
+                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64, &x->th, &x->tl,
                     &x->tm, &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
                     &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
@@ -354,13 +361,31 @@ static std::string tune_key(const rkr_index *x, int nq, int64_t npairs) {
     return b;
 }
 
+// Splits of the item range for an exact pass over gx user tiles (one
+// workgroup per CU): the count in 1..16 that minimises rounds x split length,
+// ceil(gx * ns / cus) / ns (smallest such count on ties).
+static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus) {
+    const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(16, nsteps));
+    const int64_t c = std::max(1, cus);
+    int64_t best = 1;
+    double best_cost = 1e300;
+    for (int64_t ns = 1; ns <= maxs; ++ns) {
+        const double cost = (double)((gx * ns + c - 1) / c) / (double)ns;
+        if (cost < best_cost - 1e-12) {
+            best_cost = cost;
+            best = ns;
+        }
+    }
+    return best;
+}
+
 static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int variant) {
     CountArgs a{};
     const int nib = nib_of(x->sk, x->nks, variant);
     a.plp = x->plp.as<uint8_t>();
     a.m = x->m;
     a.nks = x->nks;
-    a.step_coef = x->coef.as<double>();
+    a.step_coef = x->coef_step[nib == 1 ? 0 : (nib == 2 ? 1 : 2)].as<double>();
     a.pexp = x->pexp.as<int8_t>();
     a.ulp = x->ulp.as<uint8_t>();
     a.dpad = x->dpad;
@@ -406,8 +431,7 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
     const int64_t gx = (ts.ntask + tpw - 1) / tpw;
     CountArgs a = count_args(x, ps, ts, xv);
     const int64_t nsteps = a.nsteps;
-    int64_t nsplit = (512 + gx - 1) / std::max<int64_t>(gx, 1);
-    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(nsteps, 1))));
+    int64_t nsplit = pick_nsplit(gx, nsteps, x->num_cus);
     HIPCK(ts.reserve_entries(ts.cap_total, (int)nsplit));
     a.ent_cnt = ts.ent_cnt;
     a.steps_per_split = (nsteps + nsplit - 1) / nsplit;
@@ -840,8 +864,7 @@ static rkr_status capture_ranks_graph(rkr_index *x) {
     CountArgs a = count_args(x, ps, g.ts, xv);
     const int64_t nsteps = a.nsteps;
     const int64_t gx = (n + tpw - 1) / tpw;
-    int64_t nsplit = (512 + gx - 1) / std::max<int64_t>(gx, 1);
-    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, std::min<int64_t>(16, std::max<int64_t>(nsteps, 1))));
+    int64_t nsplit = pick_nsplit(gx, nsteps, x->num_cus);
     HIPCK(g.ts.reserve_entries(ntask_pad, (int)nsplit));
     a = count_args(x, ps, g.ts, xv);
     a.steps_per_split = (nsteps + nsplit - 1) / nsplit;

@@ -80,8 +80,11 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v, int lane) {
 
 // Copy step_bytes from global memory to LDS with global_load_lds_dwordx4: the
 // 64 lanes of a wave fill 1 KB of LDS starting at the (wave-uniform) base.
+// The step's four error-bound coefficients (32 bytes) follow its P tile in
+// the same LDS stage: two lanes of wave 0 copy them, so they arrive with the
+// tile instead of costing a memory round trip when the step needs them.
 template <int LOADS>
-__device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_bytes, int tid) {
+__device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_bytes, int tid, const double *coef) {
     const int wave = tid >> 6;
 #pragma unroll
     for (int j = 0; j < LOADS; ++j) {
@@ -91,6 +94,9 @@ __device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_byt
             __builtin_amdgcn_global_load_lds((const void *)(src + off),
                                              (__attribute__((address_space(3))) void *)(dst + wbase), 16, 0, 0);
     }
+    if (wave == 0 && (tid & 63) < 2)
+        __builtin_amdgcn_global_load_lds((const void *)(coef + 2 * (tid & 63)),
+                                         (__attribute__((address_space(3))) void *)(dst + step_bytes), 16, 0, 0);
 }
 
 // LDS stages of P: the exact passes (little work per step) keep up to four
@@ -130,7 +136,8 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     constexpr int LOADS_MAX = (STEP_BYTES_MAX + 512 * 16 - 1) / (512 * 16);
 
     constexpr int step_bytes = STEP_BYTES_MAX;
-    constexpr int NBUF = stage_buffers<MODE>(STEP_BYTES_MAX);
+    constexpr int STAGE = STEP_BYTES_MAX + 32;     // P tile + the step's coefficients
+    constexpr int NBUF = stage_buffers<MODE>(STAGE);
     // when step st + 1 must have landed, the staging of at most NBUF - 2 later
     // steps (each >= LOADS_MIN operations) may still be in flight
     constexpr int WAIT_N = (NBUF - 2) * stage_loads_min(STEP_BYTES_MAX);
@@ -312,8 +319,8 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     // bytes per lane); wait for the first
     const int64_t npro = std::min<int64_t>(NBUF - 1, s_end - s_begin);
     for (int64_t k = 0; k < npro; ++k)
-        stage_step<LOADS_MAX>(a.plp + (s_begin + k) * (int64_t)step_bytes, lds + k * STEP_BYTES_MAX, step_bytes,
-                              tid);
+        stage_step<LOADS_MAX>(a.plp + (s_begin + k) * (int64_t)step_bytes, lds + k * STAGE, step_bytes, tid,
+                              a.step_coef + 4 * (s_begin + k));
     if (s_begin + NBUF - 2 < s_end)
         wait_vm<WAIT_N>();
     else
@@ -350,7 +357,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     };
 
     for (int64_t st = s_begin; st < s_end; ++st) {
-        const uint8_t *tile = lds + cbuf * STEP_BYTES_MAX;
+        const uint8_t *tile = lds + cbuf * STAGE;
         // prefetch step st + NBUF - 1 straight into its LDS stage; that stage was
         // last read in the previous step, before the barrier that ended it
         if constexpr (MODE == CM_SCREEN) {
@@ -359,8 +366,8 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
         if (st + NBUF - 1 < s_end) {
             const int pb = cbuf + NBUF - 1 >= NBUF ? cbuf - 1 : cbuf + NBUF - 1;
-            stage_step<LOADS_MAX>(a.plp + (st + NBUF - 1) * (int64_t)step_bytes, lds + pb * STEP_BYTES_MAX,
-                                  step_bytes, tid);
+            stage_step<LOADS_MAX>(a.plp + (st + NBUF - 1) * (int64_t)step_bytes, lds + pb * STAGE, step_bytes,
+                                  tid, a.step_coef + 4 * (st + NBUF - 1));
         }
         if constexpr (MODE == CM_SCREEN) {
             if (late && have_prev) {
@@ -415,12 +422,8 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
 
         // ---- error bound of this step for each of the lane's users
-        double ca = 0.0, cb = 0.0, cc = 0.0, cabs = 0.0;
-#pragma unroll
-        for (int ib = 0; ib < NIB; ++ib) {
-            const double *co = a.step_coef + 4 * (st * NIB + ib);
-            ca = fmax(ca, co[0]); cb = fmax(cb, co[1]); cc = fmax(cc, co[2]); cabs = fmax(cabs, co[3]);
-        }
+        const double *cs = (const double *)(tile + STEP_BYTES_MAX);   // staged with the tile
+        const double ca = cs[0], cb = cs[1], cc = cs[2], cabs = cs[3];
 
         // ---- compare and count
         // Screening only needs a lower bound of each pair's count.  With enough
@@ -584,8 +587,8 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 exact_entry(act, pid, th, tl, tmv, cnt);
                 if (act && half == 0) a.ent_cnt[(int64_t)split * a.cap_total + e] = cnt;
             }
-            ncmp += (uint64_t)mylen * (NIB * 16);
-            nslot += (uint64_t)wave_max(mylen) * (NIB * 16);
+            // exact lists never change during a pass: the statistics are
+            // added once per tile, after the scan
         }
 
         have_prev = late;
@@ -618,6 +621,14 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
     }
 
+    if constexpr (MODE == CM_EXACT) {
+        const uint64_t nsc = (uint64_t)(s_end - s_begin);
+#pragma unroll
+        for (int ub = 0; ub < NUB; ++ub) {
+            ncmp += nsc * (uint64_t)len[ub] * (NIB * 16);
+            nslot += nsc * (uint64_t)wave_max(len[ub]) * (NIB * 16);
+        }
+    }
     // ---- write back
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) {
@@ -677,7 +688,8 @@ template <int SK, int MODE, int NKS, int NUB, int NIB>
 static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
-    const size_t lds = (size_t)stage_buffers<MODE>(STEP_BYTES_MAX) * STEP_BYTES_MAX;
+    constexpr int STAGE = STEP_BYTES_MAX + 32;
+    const size_t lds = (size_t)stage_buffers<MODE>(STAGE) * STAGE;
     if (a.nks != NKS) return hipErrorInvalidValue;   // layouts are padded to a supported k-step count
     const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
     if (ntiles == 0) return hipSuccess;

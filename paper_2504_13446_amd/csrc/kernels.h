@@ -111,6 +111,8 @@ hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, in
                           double *norm3, int8_t *exps, hipStream_t st);
 hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64, double eabs,
                              double *coef, hipStream_t st);
+hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out,
+                            hipStream_t st);
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
                          const void *Qm, int d, int mk, double *t64, float *th, float *tl, float *tm,
                          hipStream_t st);

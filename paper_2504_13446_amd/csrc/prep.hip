@@ -227,6 +227,20 @@ __global__ void k_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
     coef[4 * b + 3] = eabs;
 }
 
+// Per step of nib consecutive blocks: the maxima of the blocks' coefficients
+// (a step's error bound covers all of its items).
+__global__ void k_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out) {
+    int64_t st = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (st >= nsteps) return;
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ib = 0; ib < nib; ++ib) {
+        const int64_t b = st * nib + ib;
+        if (b < nblk)
+            for (int k = 0; k < 4; ++k) c[k] = fmax(c[k], coef[4 * b + k]);
+    }
+    for (int k = 0; k < 4; ++k) out[4 * st + k] = c[k];
+}
+
 // ---------------------------------------------------------------------------
 // FP64 thresholds t(u,q) = spec dot, with the FP32 values bracketing it.
 // ---------------------------------------------------------------------------
@@ -448,6 +462,13 @@ hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
     if (nblk <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_coef, dim3(nblocks(nblk, 256)), dim3(256), 0, st, pnorm3, m, nblk, g32,
                        g64, eabs, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out,
+                            hipStream_t st) {
+    if (nsteps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step_coef, dim3(nblocks(nsteps, 256)), dim3(256), 0, st, coef, nblk, nib, nsteps, out);
     return hipGetLastError();
 }
 
