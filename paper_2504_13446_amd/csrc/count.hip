@@ -101,10 +101,17 @@ __device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_byt
 
 // LDS stages of P: the exact passes (little work per step) keep up to four
 // steps in flight, screening (long steps) double-buffers.  150 KB of LDS at most.
+// Exact passes also keep a near-tie record buffer per wave in LDS: records
+// are appended there and copied out with one global atomic per flush.
+constexpr int REC_PER_WAVE = 256;
+template <int MODE>
+constexpr int record_bytes() {
+    return MODE == CM_EXACT ? WAVES_PER_WG * REC_PER_WAVE * 8 : 0;
+}
 template <int MODE>
 constexpr int stage_buffers(int step_bytes) {
     if (MODE != CM_EXACT) return 2;
-    const int nb = 153600 / step_bytes;
+    const int nb = (153600 - record_bytes<MODE>()) / step_bytes;
     return nb < 2 ? 2 : (nb > 4 ? 4 : nb);
 }
 // Staging loads the last wave of a workgroup issues per step (the fewest of
@@ -285,6 +292,20 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         len[ub] = w;
         ncmp += (uint64_t)mylen * (NIB * 16);
         nslot += (uint64_t)lim * (NIB * 16);
+    };
+
+    // Exact passes: this wave's near-tie record buffer (LDS, after the P
+    // stages) and its fill count (uniform); flushed when full and at the end.
+    int2 *const recbuf = (int2 *)(lds + NBUF * STAGE) + wave * REC_PER_WAVE;
+    int rb_n = 0;
+    auto flush_records = [&]() {
+        if (rb_n == 0) return;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)rb_n);
+        base = __shfl(base, 0, 64);
+        for (int i = lane; i < rb_n; i += 64)
+            if (base + (unsigned long long)i < a.emit_cap) a.emit[base + i] = recbuf[i];
+        rb_n = 0;
     };
 
     // Exact passes: the first EC entries of each lane's list stay in registers
@@ -539,19 +560,32 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                     const uint32_t nu = __popc(umask);
                     const uint32_t incl = wave_incl_scan(nu, lane);
                     const uint32_t total = __shfl(incl, 63, 64);
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
-                    base = __shfl(base, 0, 64);
-                    unsigned long long pos = base + (incl - nu);
-                    uint32_t mm = umask;
-                    while (mm) {
-                        const int bit = __ffs(mm) - 1;
-                        mm &= mm - 1;
-                        const int ib = bit >> 4, r = bit & 15;
-                        const int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                        const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
-                        if (pos < a.emit_cap) a.emit[pos] = make_int2(pid, (int)item | plainbit);
-                        ++pos;
+                    if (rb_n + (int)total > REC_PER_WAVE) flush_records();
+                    auto put = [&](auto &&store) {
+                        uint32_t mm = umask;
+                        while (mm) {
+                            const int bit = __ffs(mm) - 1;
+                            mm &= mm - 1;
+                            const int ib = bit >> 4, r = bit & 15;
+                            const int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
+                            store(make_int2(pid, (int)item | plainbit));
+                        }
+                    };
+                    if ((int)total <= REC_PER_WAVE) {
+                        // into this wave's LDS buffer
+                        int pos = rb_n + (int)(incl - nu);
+                        put([&](int2 rec) { recbuf[pos++] = rec; });
+                        rb_n += (int)total;
+                    } else {
+                        // more than a buffer's worth at once: straight to the output
+                        unsigned long long base = 0;
+                        if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
+                        unsigned long long pos = __shfl(base, 0, 64) + (incl - nu);
+                        put([&](int2 rec) {
+                            if (pos < a.emit_cap) a.emit[pos] = rec;
+                            ++pos;
+                        });
                     }
                 }
                 cnt += pair_sum(c);
@@ -622,6 +656,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     }
 
     if constexpr (MODE == CM_EXACT) {
+        flush_records();
         const uint64_t nsc = (uint64_t)(s_end - s_begin);
 #pragma unroll
         for (int ub = 0; ub < NUB; ++ub) {
@@ -689,7 +724,7 @@ static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
     constexpr int STAGE = STEP_BYTES_MAX + 32;
-    const size_t lds = (size_t)stage_buffers<MODE>(STAGE) * STAGE;
+    const size_t lds = (size_t)stage_buffers<MODE>(STAGE) * STAGE + record_bytes<MODE>();
     if (a.nks != NKS) return hipErrorInvalidValue;   // layouts are padded to a supported k-step count
     const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
     if (ntiles == 0) return hipSuccess;
