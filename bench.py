@@ -20,6 +20,9 @@ Printed (one JSON line on stdout):
                 (2 n m d flop against the BF16 dense peak) beside it
   cpu_baseline  the CPU oracle on a bounded sample of users (all queries),
                 scaled to queries/s
+  single_all_ranks  secondary: exact ranks of all 100k users for one query on
+                the single-query workload (graph replays), BF16 + recheck and
+                plain FP32
 Progress goes to stderr.
 """
 from __future__ import annotations
@@ -89,6 +92,7 @@ def main() -> int:
     ap.add_argument("--score", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-query all-ranks line")
     ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM counters)")
@@ -167,6 +171,7 @@ def main() -> int:
                    "k": int(w.k[0]), "masters": w.dtype, "score": args.score, "mode": "exact",
                    "generator": "iid N(0,I) directions x LogNormal(0,0.5) norms, seeded"},
         "gcompare_per_s": round(gcmp, 1),
+        "gcompare_per_s_executed": round(float(st["compares"]) / (ms_step / 1e3) / 1e9, 1),
         "build_ms": round(build_ms, 1),
         "breakdown_ms": {k: round(st[k], 3) for k in ("ms_thresh", "ms_seed", "ms_screen", "ms_refine",
                                                       "ms_select", "ms_total", "ms_screen_kernel",
@@ -187,6 +192,9 @@ def main() -> int:
                      "mfma_view": {"achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                                    "frac": round(achieved / peak, 4), "flop_per_launch": flop}},
     }
+
+    if not args.no_single:
+        out["single_all_ranks"] = single_all_ranks(rkr, W)
 
     if not args.no_fp32:
         log("plain FP32 comparator: building")
@@ -212,6 +220,39 @@ def main() -> int:
     print(json.dumps(out))
     sys.stdout.flush()
     return 0
+
+
+def single_all_ranks(rkr, W) -> dict:
+    """Secondary line: exact ranks of every user for one query on the
+    single-query workload (100k x 100k, d = 100, low-rank, FP32 masters, BF16
+    scores + FP64 recheck), as replays of the captured all-ranks graph (median
+    of 10 after warm-up), plus the plain FP32 path for the same query."""
+    import torch
+    w = W.make("single")
+    U = rkr.to_device(w.U, w.dtype)
+    P = rkr.to_device(w.P, w.dtype)
+    q = rkr.to_device(w.Qv[0], w.dtype)
+    res = {"workload": "single", "n_users": w.n, "m_items": w.m, "d": w.d}
+    for name, kw in (("bf16_recheck", dict(score="bf16")), ("fp32_plain", dict(score="f32", recheck=False))):
+        idx = rkr.Index(U, P, **kw)
+        idx.configure(graph=True)
+        for _ in range(3):
+            idx.ranks(q)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(10):
+            t = time.perf_counter()
+            idx.ranks(q)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t) * 1e3)
+        st = idx.stats()
+        ms = float(np.median(times))
+        res[name] = {"ms_per_query": round(ms, 3), "gcompare_per_s": round(w.n * w.m / (ms / 1e3) / 1e9, 1),
+                     "near_ties_rechecked": int(st["uncertain"]), "graph_replays": int(st["graph_replays"])}
+        idx.close()
+    log("single all-ranks: bf16+recheck %.2f ms, fp32 plain %.2f ms per query" % (
+        res["bf16_recheck"]["ms_per_query"], res["fp32_plain"]["ms_per_query"]))
+    return res
 
 
 def _brief(s: dict) -> str:
