@@ -70,8 +70,10 @@ def lib():
         L.orc_norm_order.argtypes = [vp, i64, vp]
         L.orc_sketch.argtypes = [vp, i64, vp, vp, i64, ctypes.c_int, vp, ctypes.c_int, vp,
                                  ctypes.c_int]
+        L.orc_rank_table.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.c_int, vp, ctypes.c_int,
+                                     vp, vp, ctypes.c_int]
         for f in (L.orc_dots, L.orc_norms, L.orc_ranks, L.orc_certify, L.orc_norm_order,
-                  L.orc_sketch):
+                  L.orc_sketch, L.orc_rank_table):
             f.restype = None
         _lib = L
     return _lib
@@ -184,6 +186,21 @@ def sketch(U, P, sample, pos, threads: int = 0) -> np.ndarray:
     lib().orc_sketch(_p(U), U.shape[0], _p(P), _p(sample), sample.shape[0], U.shape[1], _p(pos),
                      pos.shape[0], _p(out), int(threads))
     return out
+
+
+def rank_table(U, P, sample, pos, threads: int = 0):
+    """Rank table with exact cells (Sec. 4.2 steps 2-3): thresholds t[u][j] =
+    the user's spec scores against the sample items, sorted descending, at the
+    1-based positions pos; cells cnt[u][j] = #{p in P : s(u,p) > t[u][j]}
+    (the paper's T_{i,j} minus its leading 1, counted over all of P)."""
+    U = widen(U); P = widen(P)
+    sample = np.ascontiguousarray(np.asarray(sample, np.int64))
+    pos = np.ascontiguousarray(np.asarray(pos, np.int32))
+    t = np.empty((U.shape[0], pos.shape[0]), np.float64)
+    cnt = np.empty((U.shape[0], pos.shape[0]), np.int64)
+    lib().orc_rank_table(_p(U), U.shape[0], _p(P), P.shape[0], _p(sample), sample.shape[0],
+                         U.shape[1], _p(pos), pos.shape[0], _p(t), _p(cnt), int(threads))
+    return t, cnt
 
 
 # --------------------------------------------------------------------------

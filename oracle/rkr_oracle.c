@@ -233,3 +233,44 @@ void orc_sketch(const double *U, int64_t n, const double *P,
         free(s);
     }
 }
+
+/*
+ * Rank table (paper Sec. 4.2, steps 2 and 3), with exact cells.
+ * Columns: for each user, its spec scores against the sample items (rows of
+ * P listed in sample[0..ns-1]), sorted in descending order and read at the
+ * 1-based positions pos[0..np-1] give the thresholds t_out[u*np + j].  Cells:
+ * cnt_out[u*np + j] = #{p in P : s(u,p) > t_out[u*np + j]}, the paper's cell
+ * T_{i,j} = 1 + sum_p I[u_i.p > t_{i,j}] without its leading 1, counted over
+ * all of P (the paper estimates it from samples instead).
+ */
+void orc_rank_table(const double *U, int64_t n, const double *P, int64_t m,
+                    const int64_t *sample, int64_t ns, int d, const int32_t *pos,
+                    int np, double *t_out, int64_t *cnt_out, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        double *s = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
+        double *all = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n; ++i) {
+            const double *u = U + i * d;
+            for (int64_t j = 0; j < ns; ++j)
+                s[j] = spec_dot(u, P + sample[j] * d, d);
+            qsort(s, (size_t)ns, sizeof(double), cmp_dbl_desc);
+            for (int64_t p = 0; p < m; ++p)
+                all[p] = spec_dot(u, P + p * d, d);
+            for (int j = 0; j < np; ++j) {
+                const double t = s[pos[j] - 1];
+                int64_t c = 0;
+                for (int64_t p = 0; p < m; ++p)
+                    if (all[p] > t)
+                        ++c;
+                t_out[i * np + j] = t;
+                cnt_out[i * np + j] = c;
+            }
+        }
+        free(all);
+        free(s);
+    }
+}

@@ -259,3 +259,52 @@ def test_sketch_closed_form():
 def test_widen_bf16():
     bits = np.array([0x3F80, 0xC000, 0x0000, 0x3E20], np.uint16)   # 1, -2, 0, 0.15625
     assert O.widen(bits, "bf16").tolist() == [1.0, -2.0, 0.0, 0.15625]
+
+
+def test_rank_table_integer_fixture():
+    """Rank table with exact cells (Sec. 4.2): on small integers every dot is
+    exact in int64, so thresholds and cells are checked against integer
+    arithmetic; the data holds many ties, so '>' versus '>=' and an
+    off-by-one position would both show."""
+    rng = np.random.default_rng(31)
+    n, m, d = 40, 300, 5
+    U = rng.integers(-3, 4, size=(n, d)).astype(np.float32)
+    P = rng.integers(-3, 4, size=(m, d)).astype(np.float32)
+    sample = np.array(sorted(rng.choice(m, 37, replace=False)), np.int64)
+    pos = np.array([1, 2, 5, 9, 20, 37], np.int32)
+    t, cnt = O.rank_table(U, P, sample, pos)
+    S = U.astype(np.int64) @ P.astype(np.int64).T                 # exact scores
+    srt = -np.sort(-S[:, sample], axis=1)                          # descending
+    want_t = srt[:, pos - 1]
+    want_c = (S[:, :, None] > want_t[:, None, :]).sum(axis=1)
+    assert np.array_equal(t, want_t.astype(np.float64))
+    assert np.array_equal(cnt, want_c)
+    assert np.all(np.diff(cnt, axis=1) >= 0)                       # lower thresholds, more above
+    # the top threshold from a sample holding the best item counts nothing above it
+    best = np.argmax(S, axis=1)
+    for u in range(n):
+        if best[u] in sample:
+            assert cnt[u, 0] == np.sum(S[u] > S[u, best[u]])
+
+
+def test_rank_table_brackets_ranks():
+    """The bracket the table gives (Sec. 4.2): a threshold at or above u.q
+    bounds the rank from below by 1 + its cell, one at or below u.q bounds it
+    from above."""
+    rng = np.random.default_rng(32)
+    U = rng.standard_normal((60, 8)).astype(np.float32)
+    P = rng.standard_normal((700, 8)).astype(np.float32)
+    sample = O.stratified_sample(P, 64)
+    pos = O.sketch_positions(64)
+    t, cnt = O.rank_table(U, P, sample, pos)
+    Qv = P[[3, 50, 400]]
+    R = O.ranks(U, P, Qv)
+    T = O.dots(U, Qv)
+    for qi in range(3):
+        for u in range(U.shape[0]):
+            above = t[u] >= T[u, qi]
+            below = t[u] <= T[u, qi]
+            if above.any():
+                assert R[qi, u] >= 1 + cnt[u][above].max()
+            if below.any():
+                assert R[qi, u] <= 1 + cnt[u][below].min()
