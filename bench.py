@@ -93,6 +93,10 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-single", action="store_true", help="skip the single-query all-ranks line")
+    ap.add_argument("--rank-table", type=int, default=4096,
+                    help="sample items for the index's rank table (0: no table)")
+    ap.add_argument("--no-table-compare", action="store_true",
+                    help="skip timing the same batch with the rank table switched off")
     ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM counters)")
@@ -124,7 +128,7 @@ def main() -> int:
     Q = rkr.to_device(w.Qv, w.dtype)
     torch.cuda.synchronize()
     t = time.time()
-    idx = rkr.Index(U, P, score=args.score)
+    idx = rkr.Index(U, P, score=args.score, rank_table=args.rank_table)
     torch.cuda.synchronize()
     build_ms = (time.time() - t) * 1e3
     log("index built in %.0f ms" % build_ms)
@@ -169,6 +173,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n_users": n, "m_items": m, "d": d, "queries": nq,
                    "k": int(w.k[0]), "masters": w.dtype, "score": args.score, "mode": "exact",
+                   "rank_table_samples": args.rank_table,
                    "generator": "iid N(0,I) directions x LogNormal(0,0.5) norms, seeded"},
         "gcompare_per_s": round(gcmp, 1),
         "gcompare_per_s_executed": round(float(st["compares"]) / (ms_step / 1e3) / 1e9, 1),
@@ -178,7 +183,7 @@ def main() -> int:
                                                       "ms_exact_kernel", "ms_recheck_kernel")},
         "counters": {k: int(st[k]) for k in ("pairs", "seed_pairs", "survivors", "refined_pairs",
                                              "uncertain", "flips", "compares", "compare_slots", "screen_ctas",
-                                             "screen_variant")},
+                                             "screen_variant", "table_pruned")},
         # The screening kernel is bound by its vector-ALU compare loop (VALU busy
         # ~60 %, matrix cores ~16 %, see profiles/): achieved = (user, query, item)
         # comparisons per launch / launch time, against one compare per lane-op
@@ -192,6 +197,27 @@ def main() -> int:
                      "mfma_view": {"achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                                    "frac": round(achieved / peak, 4), "flop_per_launch": flop}},
     }
+
+    if args.rank_table > 0 and not args.no_table_compare:
+        # the same batch with the table switched off (the screen then scans
+        # every non-seed pair); warm-up lets the tuner settle on its own key
+        idx.configure(no_table=True)
+        for _ in range(6):
+            idx.query_batch(Q, w.k)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(2):
+            ids_nt, rk_nt, _ = idx.query_batch(Q, w.k)
+        torch.cuda.synchronize()
+        ms_nt = (time.perf_counter() - t) * 1e3 / 2
+        same = bool(np.array_equal(ids_nt.cpu().numpy(), ids_np) and np.array_equal(rk_nt.cpu().numpy(), rk_np))
+        s_nt = idx.stats()
+        out["without_rank_table"] = {"ms_per_step": round(ms_nt, 2), "queries_per_s": round(nq / (ms_nt / 1e3), 3),
+                                     "screen_kernel_ms": round(s_nt["ms_screen_kernel"], 2),
+                                     "same_answers": same}
+        out["speedup_from_rank_table"] = round(ms_nt / ms_step, 3)
+        idx.configure(no_table=False)
+        log("without the rank table: %.1f ms/step (same answers: %s)" % (ms_nt, same))
 
     if not args.no_single:
         out["single_all_ranks"] = single_all_ranks(rkr, W)
@@ -257,9 +283,9 @@ def single_all_ranks(rkr, W) -> dict:
 
 def _brief(s: dict) -> str:
     return "total %.1f ms (thresh %.1f seed %.1f screen %.1f [kernel %.1f] refine %.1f select %.1f) " \
-           "survivors %d uncertain %d" % (s["ms_total"], s["ms_thresh"], s["ms_seed"], s["ms_screen"],
-                                          s["ms_screen_kernel"], s["ms_refine"], s["ms_select"],
-                                          s["survivors"], s["uncertain"])
+           "table-pruned %d survivors %d uncertain %d" % (
+               s["ms_total"], s["ms_thresh"], s["ms_seed"], s["ms_screen"], s["ms_screen_kernel"], s["ms_refine"],
+               s["ms_select"], s["table_pruned"], s["survivors"], s["uncertain"])
 
 
 def cpu_baseline(w, ids, rk, off, users: int) -> dict:

@@ -71,7 +71,10 @@ typedef struct {
                             /*    threshold rounded to FP32 (not exact; for comparison) */
     int32_t sketch_samples; /* >0: build the per-user score sketch for the estimator    */
                             /*     from this many norm-stratified items (e.g. 4096)     */
-    int32_t reserved;
+    int32_t rank_table;     /* >0: build the rank table (Sec. 4.2) from this many       */
+                            /*     norm-stratified items (at most 4096): 16 thresholds  */
+                            /*     per user with certain counts over all of P; batch    */
+                            /*     queries then skip the pairs it rules out (Lemma 1)   */
     void *stream;           /* hipStream_t for all work on this index; NULL = default   */
 } rkr_build_opts;
 
@@ -87,7 +90,8 @@ typedef struct {
     int32_t graph;          /* 1: rkr_ranks runs as a captured hipGraph (captured on the */
                             /*    first call, replayed after; falls back to the eager    */
                             /*    path when the near-tie buffer would overflow)          */
-    int32_t reserved[3];
+    int32_t no_table;       /* 1: do not prune with the rank table                       */
+    int32_t reserved[2];
 } rkr_query_opts;
 
 /* Counters of the last query call (rkr_stats). */
@@ -115,15 +119,18 @@ typedef struct {
     int64_t compare_slots;  /* lane slots of the compare loops (active or idle): compares / */
                             /* compare_slots is the SIMD efficiency of the entry loops      */
     int64_t graph_replays;  /* 1 if the call replayed a captured graph                      */
+    int64_t table_pruned;   /* pairs the rank table ruled out before the screen             */
 } rkr_query_stats;
 
 /*
  * Build an index over users U [device, n x d] and items P [device, m x d],
  * both in master dtype dt.  Sorts P by norm (descending; Sec. 4.2 step 1),
  * makes the low-precision copies, their exact residual norms, and the
- * per-segment error-bound coefficients.
+ * per-segment error-bound coefficients; with opts->rank_table > 0 also the
+ * rank table (one more pass over U.P^T; not built when m = 0).
  * Errors: RKR_E_INVALID if n <= 0, m < 0, d <= 0, d > 4096, a value is not
- * finite or |value| > 2^50; RKR_E_UNSUPPORTED for n or m >= 2^31.
+ * finite or |value| > 2^50, sketch_samples or rank_table < 0;
+ * RKR_E_UNSUPPORTED for n or m >= 2^31.
  * m = 0 is valid (every rank is 1).
  */
 rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t m, int32_t d,
@@ -168,6 +175,17 @@ rkr_status rkr_query_approx(rkr_index *idx, const void *q, int32_t k, double c,
 rkr_status rkr_query_batch(rkr_index *idx, int32_t nq, const void *Qm, const int32_t *k,
                            const double *c, const int64_t *cand_off, const int32_t *cand_ids,
                            int32_t *ids_out, int32_t *ranks_out);
+
+/*
+ * The rank table (Sec. 4.2) of an index built with rank_table > 0.  Column j
+ * of user u holds a threshold t_out[u * 16 + j] (FP64: the user's spec score
+ * against a sample item, columns in descending order) and cnt_out[u * 16 + j],
+ * a count of items p with s64(u,p) > t certainly (a lower bound of the exact
+ * count: items within the score error of t are left out).  The paper's cell
+ * is 1 + that count.  t_out [device, n x 16 double], cnt_out [device, n x 16
+ * uint32], caller-allocated.  RKR_E_STATE if the index has no table.
+ */
+rkr_status rkr_rank_table(const rkr_index *idx, double *t_out, uint32_t *cnt_out);
 
 /* Exact Def. 1 rank of q for every user: ranks_out [device, n int32]. */
 rkr_status rkr_ranks(rkr_index *idx, const void *q, int32_t *ranks_out);

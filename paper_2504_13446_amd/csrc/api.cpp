@@ -169,8 +169,12 @@ struct rkr_index {
     Scratch sc;
     DBuf pair_u, pair_q, pair_off, qm_pid, t64, th, tl, tm, cnt, seedflag, keys, sel, selrank, best, cand,
         candkeys, ans, seedpid, surv, emit, ctr, bound, seedkth, kdev, sdev, cdev, segoff, seloff, bestoff,
-        candoff, cursor, qcount, flags, allpid;
+        candoff, cursor, qcount, flags, allpid, keep;
     TaskSet ts_screen, ts_screen2, ts_exact;
+    // rank table (Sec. 4.2): [n][TABLE_COLS] FP64 thresholds, their FP32
+    // round-ups, and certain counts over all of P
+    DBuf tab_t, tab_th, tab_cnt;
+    bool has_table = false;
     int64_t emit_cap = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     rkr_query_opts qo{};
@@ -184,6 +188,8 @@ struct rkr_index {
 // ---------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------
+static rkr_status build_rank_table(rkr_index *x, int samples);
+
 extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t m, int32_t d, rkr_dtype dt,
                                 const rkr_build_opts *opts, rkr_index **out) {
     g_err.clear();
@@ -195,16 +201,18 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     if (dt != RKR_F32 && dt != RKR_BF16) return fail(RKR_E_INVALID, "unknown master dtype");
     if (!U || (m > 0 && !P)) return fail(RKR_E_INVALID, "U or P is NULL");
     if (n >= (1ll << 31) || m >= (1ll << 31)) return fail(RKR_E_UNSUPPORTED, "n and m must be below 2^31");
-    int sk = SK_BF16, recheck = 1, sketch = 0;
+    int sk = SK_BF16, recheck = 1, sketch = 0, table = 0;
     hipStream_t st = nullptr;
     if (opts) {
         sk = opts->score;
         recheck = opts->recheck ? 1 : 0;
         sketch = opts->sketch_samples;
+        table = opts->rank_table;
         st = (hipStream_t)opts->stream;
     }
     if (sk != SK_F32 && sk != SK_BF16 && sk != SK_FP8) return fail(RKR_E_INVALID, "unknown score kind");
     if (sketch < 0) return fail(RKR_E_INVALID, "sketch_samples must be >= 0");
+    if (table < 0) return fail(RKR_E_INVALID, "rank_table must be >= 0");
     const int KS = frag_ks(sk);
     // pad d to a k-step count the count kernels are instantiated for (zero padding)
     const int nks = nks_bucket(sk, (d + KS - 1) / KS);
@@ -284,6 +292,11 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
             if (s2 != RKR_OK) return s2;
         }
         x->sc.reset();
+        if (table > 0 && m > 0) {
+            rkr_status s3 = build_rank_table(x, table);
+            if (s3 != RKR_OK) return s3;
+        }
+        x->sc.reset();
         return RKR_OK;
     };
     rs = body();
@@ -298,7 +311,8 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
 extern "C" void rkr_destroy(rkr_index *x) {
     if (!x) return;
     (void)hipStreamSynchronize(x->st);
-    DBuf *bufs[] = {&x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
+    DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt,
+                    &x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
                     &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64, &x->th, &x->tl,
                     &x->tm, &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
@@ -328,6 +342,16 @@ extern "C" rkr_status rkr_configure(rkr_index *x, const rkr_query_opts *o) {
     return RKR_OK;
 }
 
+extern "C" rkr_status rkr_rank_table(const rkr_index *x, double *t_out, uint32_t *cnt_out) {
+    g_err.clear();
+    if (!x || !t_out || !cnt_out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->has_table) return fail(RKR_E_STATE, "index built without a rank table");
+    const int64_t cells = x->n * TABLE_COLS;
+    HIPCK(hipMemcpyAsync(t_out, x->tab_t.p, cells * 8, hipMemcpyDeviceToDevice, x->st));
+    HIPCK(hipMemcpyAsync(cnt_out, x->tab_cnt.p, cells * 4, hipMemcpyDeviceToDevice, x->st));
+    HIPCK(hipStreamSynchronize(x->st));
+    return RKR_OK;
+}
 extern "C" rkr_status rkr_stats(const rkr_index *x, rkr_query_stats *out) {
     g_err.clear();
     if (!x || !out) return fail(RKR_E_INVALID, "NULL argument");
@@ -467,6 +491,47 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
         HIPCK(x->emit.ensure((size_t)x->emit_cap * 8));
     }
     return fail(RKR_E_DEVICE, "near-tie buffer kept overflowing");
+}
+
+// The rank table (Sec. 4.2).  Thresholds (step 2): the user's spec scores
+// against S norm-stratified sample items, read at TABLE_COLS geometrically
+// spaced positions of their descending order (the paper spaces them
+// uniformly between the extreme scores).  Cells (step 3): counted over all of
+// P by the count kernel's table mode, as certain counts (lower bounds of the
+// exact counts) in place of the paper's sampled estimates, so that they can
+// rule pairs out without losing exactness.
+static rkr_status build_rank_table(rkr_index *x, int samples) {
+    const int64_t n = x->n, cells = n * TABLE_COLS;
+    hipStream_t st = x->st;
+    x->has_table = false;
+    HIPCK(x->tab_t.ensure(cells * 8));
+    HIPCK(x->tab_th.ensure(cells * 4));
+    HIPCK(x->tab_cnt.ensure(cells * 4));
+    rkr_status rs = sample_levels(x->Um.p, n, x->Pm.p, x->m, x->d, x->mk, samples, nullptr, x->tab_t.as<double>(),
+                                  x->sc, st);
+    if (rs != RKR_OK) return fail(rs, "rank table: sample scores");
+    HIPCK(q_round_up_f32(x->tab_t.as<double>(), cells, x->tab_th.as<float>(), st));
+    HIPCK(launch_fill_u32(x->tab_cnt.as<uint32_t>(), 0, cells, st));
+    PairSet ps;     // table mode reads neither pairs nor entry lists
+    TaskSet ts;
+    const int xv = x->sk == SK_F32 ? 0 : 2;
+    CountArgs a = count_args(x, ps, ts, xv);
+    a.ntask = n;
+    a.ent_th = x->tab_th.as<float>();
+    a.cnt_out = x->tab_cnt.as<uint32_t>();
+    a.stat = nullptr;
+    a.emit = nullptr;
+    a.emit_count = nullptr;
+    a.emit_cap = 0;
+    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+    const int64_t gx = (n + tpw - 1) / tpw;
+    int64_t nsplit = pick_nsplit(gx, a.nsteps, x->num_cus);
+    a.steps_per_split = (a.nsteps + nsplit - 1) / nsplit;
+    nsplit = (a.nsteps + a.steps_per_split - 1) / a.steps_per_split;
+    HIPCK(launch_count(x->sk, CM_TABLE, a, (int)nsplit, xv, st));
+    HIPCK(hipStreamSynchronize(st));
+    x->has_table = true;
+    return RKR_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -637,7 +702,18 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     if (pruned) need_screen = false;
     int64_t nsurv = 0;
     HIPCK(x->surv.ensure(npairs * 4));
-    const int64_t nscreen = npairs - nseed;   // the seeds' ranks are known: they are not screened
+    int64_t nscreen = npairs - nseed;   // the seeds' ranks are known: they are not screened
+    const bool table_used = need_screen && nscreen > 0 && x->has_table && !x->qo.no_table;
+    if (table_used) {
+        // the rank table rules out pairs the screen would drop (Lemma 1 (2))
+        HIPCK(x->keep.ensure(npairs));
+        HIPCK(q_table_keep(ps, x->seedflag.as<uint8_t>(), x->bound.as<int32_t>(), x->tab_t.as<double>(),
+                           x->tab_cnt.as<uint32_t>(), x->keep.as<uint8_t>(), st));
+        int64_t nk = 0;
+        HIPCK(q_compact_flags(x->keep.as<uint8_t>(), npairs, x->allpid.as<int32_t>(), &nk, x->sc, st));
+        x->stats.table_pruned = nscreen - nk;
+        nscreen = nk;
+    }
     if (need_screen && nscreen > 0) {
         hipError_t e = build_tasks(x->allpid.as<int32_t>(), nscreen, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
                                    x->ts_screen, x->sc, st);
@@ -646,7 +722,8 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         if (x->ts_screen.cap_total >= ((int64_t)1 << 30))
             return fail(RKR_E_UNSUPPORTED, "more than 2^30 screening entries: split the batch");
         // candidates: each tile variant, launched as a grid or as a persistent grid
-        const std::string key = tune_key(x, nq, npairs);
+        // a table-pruned screen sees far fewer pairs: tuned on its own
+        const std::string key = tune_key(x, nq, npairs) + (table_used ? "/table" : "");
         const int ntv = num_variants(x->sk, x->nks);
         const int cand = x->tuner.pick(key, 2 * ntv);
         const int variant = cand % ntv;

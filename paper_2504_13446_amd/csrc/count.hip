@@ -28,6 +28,10 @@
 // compacted to the front of the user's list every step.  With enough live
 // entries the screen compares 7-bit monotone codes of the scores instead of
 // the scores (a lower bound of the certain count, four compares per dword).
+// Table mode builds the rank table's cells (Sec. 4.2): every user carries its
+// TABLE_COLS thresholds in registers and counts, for each, the scores
+// certainly above it over all of P; near ties are left uncounted (the cells
+// are lower bounds of the exact counts) and nothing is emitted.
 #include "rkr_internal.h"
 
 #include <algorithm>
@@ -60,6 +64,15 @@ __device__ inline f32x16 mfma_step(f32x16 acc, typename FragT<SK>::T a, typename
         // A and B in FP8 e4m3 (format code 0); per-lane E8M0 scales (127 = 1.0)
         return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
     }
+}
+
+// acc += median(a, b, c) for unsigned integers: two VALU instructions (the
+// compiler only forms the median from min/max when it can order the bounds
+// itself, and left to itself it keeps every median of a step live before
+// summing them).
+__device__ inline void add_med3_u32(uint32_t &acc, uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t t;
+    asm("v_med3_u32 %1, %2, %3, %4\n\tv_add_u32 %0, %0, %1" : "+v"(acc), "=&v"(t) : "v"(a), "v"(b), "v"(c));
 }
 
 // Sum of a value over the lane pair (l, l + 32).
@@ -99,8 +112,8 @@ __device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_byt
                                          (__attribute__((address_space(3))) void *)(dst + step_bytes), 16, 0, 0);
 }
 
-// LDS stages of P: the exact passes (little work per step) keep up to four
-// steps in flight, screening (long steps) double-buffers.  150 KB of LDS at most.
+// LDS stages of P: the exact and table passes (little work per step) keep up
+// to four steps in flight, screening (long steps) double-buffers.  150 KB of LDS at most.
 // Exact passes also keep a near-tie record buffer per wave in LDS: records
 // are appended there and copied out with one global atomic per flush.
 constexpr int REC_PER_WAVE = 256;
@@ -110,7 +123,7 @@ constexpr int record_bytes() {
 }
 template <int MODE>
 constexpr int stage_buffers(int step_bytes) {
-    if (MODE != CM_EXACT) return 2;
+    if (MODE == CM_SCREEN) return 2;
     const int nb = (153600 - record_bytes<MODE>()) / step_bytes;
     return nb < 2 ? 2 : (nb > 4 ? 4 : nb);
 }
@@ -171,10 +184,17 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     for (int ub = 0; ub < NUB; ++ub) {
         int64_t t = tile * TASKS_PER_WG + (wave * NUB + ub) * USER_BLOCK + l32;
         tix[ub] = t;
-        int u = (t < a.ntask) ? a.task_user[t] : -1;
+        int u;
+        if constexpr (MODE == CM_TABLE) {
+            u = (t < a.ntask) ? (int)t : -1;
+            len[ub] = (u >= 0) ? TABLE_COLS : 0;
+            ebase[ub] = 0;
+        } else {
+            u = (t < a.ntask) ? a.task_user[t] : -1;
+            len[ub] = (u >= 0) ? a.ent_len[t] : 0;
+            ebase[ub] = a.blk_base[t >> 5] + l32;
+        }
         uid[ub] = u;
-        len[ub] = (u >= 0) ? a.ent_len[t] : 0;
-        ebase[ub] = a.blk_base[t >> 5] + l32;
         un_hat[ub] = un_del[ub] = un_full[ub] = 0.0;
         uscale[ub] = 127;
         if (u >= 0) {
@@ -329,6 +349,21 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 rtl[ub][k] = a.ent_tl[e];
                 rtm[ub][k] = a.ent_tm[e];
             }
+        }
+
+    // Table passes: the user's TABLE_COLS thresholds and running counts stay
+    // in registers for the whole scan.
+    constexpr int TC = MODE == CM_TABLE ? TABLE_COLS : 1;
+    float tth[NUB][TC];
+    uint32_t tcnt[NUB][TC];
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub)
+#pragma unroll
+        for (int j = 0; j < TC; ++j) {
+            tcnt[ub][j] = 0;
+            tth[ub][j] = 0.0f;
+            if constexpr (MODE == CM_TABLE)
+                if (uid[ub] >= 0) tth[ub][j] = a.ent_th[(int64_t)uid[ub] * TABLE_COLS + j];
         }
 
     int any_live = 0;
@@ -531,6 +566,28 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 }
                 continue;
             }
+            if constexpr (MODE == CM_TABLE) {
+                // s > hi as an integer median: with order keys (ks, kh) of the
+                // scores and of hi (zeros made +0, so the key order is the
+                // float order), med3(ks, kh, kh + 1) - kh is 1 iff ks > kh,
+                // else 0.  The kh terms are taken out once per step (exact
+                // modulo 2^32); no compare masks are kept live.
+                uint32_t ks[NIB * 16];
+#pragma unroll
+                for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) ks[ib * 16 + r] = f32_order_key(acc[ib][ub][r] + 0.0f);
+#pragma unroll
+                for (int j = 0; j < TC; ++j) {
+                    const uint32_t kh = f32_order_key(f32_next_up(tth[ub][j] + eps) + 0.0f);
+                    uint32_t c = 0u - (uint32_t)(NIB * 16) * kh;
+                    const uint32_t kh1 = kh + 1u;   // no wrap: kh is the key of a finite float
+#pragma unroll
+                    for (int i = 0; i < NIB * 16; ++i) add_med3_u32(c, ks[i], kh, kh1);
+                    tcnt[ub][j] += c;
+                }
+                continue;
+            }
             const int mylen = len[ub];
             // band count of one entry against the step's scores: certainly-above
             // scores add to cnt, near ties are emitted for the FP64 recheck
@@ -670,6 +727,13 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         if (uid[ub] < 0) continue;
         if constexpr (MODE == CM_SCREEN) {
             if (half == 0) a.ent_len[tix[ub]] = len[ub];
+        } else if constexpr (MODE == CM_TABLE) {
+            // both lanes of a pair hold the same user: sum their halves
+#pragma unroll
+            for (int j = 0; j < TC; ++j) {
+                const uint32_t c = pair_sum(tcnt[ub][j]);
+                if (half == 0) atomicAdd(&a.cnt_out[(int64_t)uid[ub] * TABLE_COLS + j], c);
+            }
         } else {
             if (half == 0) {
 #pragma unroll
@@ -791,17 +855,18 @@ static hipError_t dispatch_nks(const CountArgs &a, int nsplit, int variant, hipS
     return hipErrorInvalidValue;
 }
 
+template <int SK>
+static hipError_t dispatch_mode(int mode, const CountArgs &a, int nsplit, int variant, hipStream_t st) {
+    if (mode == CM_SCREEN) return dispatch_nks<SK, CM_SCREEN>(a, nsplit, variant, st);
+    if (mode == CM_EXACT) return dispatch_nks<SK, CM_EXACT>(a, nsplit, variant, st);
+    if (mode == CM_TABLE) return dispatch_nks<SK, CM_TABLE>(a, nsplit, variant, st);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int variant, hipStream_t st) {
-    if (mode != CM_SCREEN && mode != CM_EXACT) return hipErrorInvalidValue;
-    if (sk == SK_BF16)
-        return mode == CM_SCREEN ? dispatch_nks<SK_BF16, CM_SCREEN>(a, nsplit, variant, st)
-                                 : dispatch_nks<SK_BF16, CM_EXACT>(a, nsplit, variant, st);
-    if (sk == SK_F32)
-        return mode == CM_SCREEN ? dispatch_nks<SK_F32, CM_SCREEN>(a, nsplit, variant, st)
-                                 : dispatch_nks<SK_F32, CM_EXACT>(a, nsplit, variant, st);
-    if (sk == SK_FP8)
-        return mode == CM_SCREEN ? dispatch_nks<SK_FP8, CM_SCREEN>(a, nsplit, variant, st)
-                                 : dispatch_nks<SK_FP8, CM_EXACT>(a, nsplit, variant, st);
+    if (sk == SK_BF16) return dispatch_mode<SK_BF16>(mode, a, nsplit, variant, st);
+    if (sk == SK_F32) return dispatch_mode<SK_F32>(mode, a, nsplit, variant, st);
+    if (sk == SK_FP8) return dispatch_mode<SK_FP8>(mode, a, nsplit, variant, st);
     return hipErrorInvalidValue;
 }
 

@@ -57,5 +57,10 @@ hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream
 hipError_t q_tasks_one_per_user(int64_t n, int64_t ntask_pad, const PairSet &ps, int plain, TaskSet &ts,
                                 hipStream_t st);
 hipError_t q_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
+// keep[pid] = 1 for the non-seed pairs the rank table cannot rule out
+// (tab_t, tab_cnt: [n][TABLE_COLS] thresholds and certain counts)
+hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
+                        const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st);
+hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st);
 
 }  // namespace rkr

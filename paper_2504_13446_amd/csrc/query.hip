@@ -263,6 +263,37 @@ __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t nb) {
 }
 
 // ---------------------------------------------------------------------------
+// Rank-table filter (the paper's Lemma 1 (2) with the table of Sec. 4.2 as
+// the source of lower-bound ranks): a non-seed pair (u, q) goes on to the
+// screen unless some column j of u has a threshold t_{u,j} >= t(u,q) whose
+// certain count is >= B[q].  Every item above t_{u,j} is above t(u,q), so
+// such a pair's count reaches B[q] and its rank exceeds the bound, exactly
+// what the screen would find by scanning.  Seeds (already counted) are never
+// kept.
+__global__ void k_table_keep(int64_t npairs, const int32_t *pair_u, const int32_t *pair_q, const double *t64,
+                             const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
+                             const uint32_t *tab_cnt, uint8_t *keep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npairs) return;
+    if (seedflag[i]) {
+        keep[i] = 0;
+        return;
+    }
+    const int64_t u = pair_u[i];
+    const double t = t64[i];
+    uint32_t best = 0;
+#pragma unroll
+    for (int j = 0; j < TABLE_COLS; ++j)
+        if (tab_t[u * TABLE_COLS + j] >= t) best = max(best, tab_cnt[u * TABLE_COLS + j]);
+    keep[i] = (int64_t)best >= (int64_t)bound[pair_q[i]] ? 0 : 1;
+}
+
+// out[i] = the smallest float >= x[i]
+__global__ void k_round_up_f32(const double *x, int64_t n, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = f32_round_up(x[i]);
+}
+
 #define LAUNCH1D(kern, N, ...)                                                              \
     do {                                                                                   \
         if ((N) > 0) hipLaunchKernelGGL(kern, dim3(nblocks((N), 256)), dim3(256), 0, st, __VA_ARGS__); \
@@ -380,6 +411,16 @@ hipError_t q_copy(const void *src, void *dst, int64_t bytes, hipStream_t st) {
 }
 hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream_t st) {
     LAUNCH1D(k_ranks_out, n, cnt, n, ranks);
+    return hipGetLastError();
+}
+
+hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
+                        const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st) {
+    LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound, tab_t, tab_cnt, keep);
+    return hipGetLastError();
+}
+hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st) {
+    LAUNCH1D(k_round_up_f32, n, x, n, out);
     return hipGetLastError();
 }
 

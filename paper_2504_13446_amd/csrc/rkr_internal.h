@@ -96,7 +96,6 @@ struct CountArgs {
     int64_t step_end;
     // exact mode outputs
     uint32_t *cnt_out;            // [npairs] += certain-above count
-    uint32_t *cnt_lo_out;         // interval mode: [npairs] += count of scores >= lo
     int2 *emit;                   // near-tie records (pid, item)
     unsigned long long *emit_count;
     unsigned long long emit_cap;
@@ -109,7 +108,12 @@ struct CountArgs {
     int persistent_ctas;
 };
 
-enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_INTERVAL = 2 };
+// CM_TABLE: the rank table's cells.  Task t is user t (ntask = n, no entry
+// lists); user u's TABLE_COLS thresholds, rounded up to FP32, are read from
+// ent_th[u * TABLE_COLS + j], and cnt_out[u * TABLE_COLS + j] += the count of
+// items certainly above column j (a lower bound of the exact count).
+enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_TABLE = 2 };
+constexpr int TABLE_COLS = 16;
 
 struct DeviceIndex;
 

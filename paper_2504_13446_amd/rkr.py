@@ -26,7 +26,7 @@ SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
            "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
-           "rkr_mlp_grad", "rkr_sketch", "rkr_stats", "rkr_last_error")
+           "rkr_mlp_grad", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
 class RkrError(RuntimeError):
@@ -38,14 +38,14 @@ class RkrError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("score", ctypes.c_int32), ("recheck", ctypes.c_int32),
-                ("sketch_samples", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sketch_samples", ctypes.c_int32), ("rank_table", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
 class QueryOpts(ctypes.Structure):
     _fields_ = [("seed_mult", ctypes.c_int32), ("use_estimator", ctypes.c_int32),
                 ("approx_refine", ctypes.c_int32), ("prune_mult", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("graph", ctypes.c_int32), ("no_table", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class QueryStats(ctypes.Structure):
@@ -57,7 +57,8 @@ class QueryStats(ctypes.Structure):
                                         "ms_recheck_kernel")] + [("screen_ctas", ctypes.c_int64),
                                                              ("screen_variant", ctypes.c_int64),
                                                              ("compare_slots", ctypes.c_int64),
-                                                             ("graph_replays", ctypes.c_int64)]
+                                                             ("graph_replays", ctypes.c_int64),
+                                                             ("table_pruned", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -90,6 +91,7 @@ def load(path: str = LIB_PATH):
         "rkr_mlp_set": [vp, vp],
         "rkr_mlp_grad": [vp, vp, vp, i32, vp, ctypes.POINTER(f64)],
         "rkr_sketch": [vp, vp],
+        "rkr_rank_table": [vp, vp, vp],
         "rkr_stats": [vp, ctypes.POINTER(QueryStats)],
         "rkr_last_error": [],
     }
@@ -136,11 +138,11 @@ def _master(x: torch.Tensor) -> int:
 # C-named functions
 # ---------------------------------------------------------------------------
 def rkr_build(U: torch.Tensor, P: torch.Tensor, score: str = "bf16", recheck: bool = True,
-              sketch_samples: int = 0) -> int:
+              sketch_samples: int = 0, rank_table: int = 0) -> int:
     L = load()
     if U.dtype != P.dtype:
         raise ValueError("U and P must share a dtype")
-    opts = BuildOpts(SCORES[score], 1 if recheck else 0, int(sketch_samples), 0, _stream())
+    opts = BuildOpts(SCORES[score], 1 if recheck else 0, int(sketch_samples), int(rank_table), _stream())
     h = ctypes.c_void_p()
     n, d = U.shape
     m = P.shape[0]
@@ -155,9 +157,9 @@ def rkr_destroy(h: int) -> None:
 
 
 def rkr_configure(h: int, seed_mult: int = 0, use_estimator: bool = False, approx_refine: int = 0,
-                  prune_mult: int = 0, graph: bool = False) -> None:
+                  prune_mult: int = 0, graph: bool = False, no_table: bool = False) -> None:
     o = QueryOpts(int(seed_mult), 1 if use_estimator else 0, int(approx_refine), int(prune_mult),
-                  1 if graph else 0)
+                  1 if graph else 0, 1 if no_table else 0)
     _check(load().rkr_configure(h, ctypes.byref(o)))
 
 
@@ -239,6 +241,14 @@ def rkr_sketch(h: int, n: int, device="cuda") -> torch.Tensor:
     return out
 
 
+def rkr_rank_table(h: int, n: int, device="cuda"):
+    """(thresholds [n, 16] float64, certain counts [n, 16] int32 holding uint32)."""
+    t = torch.empty((n, 16), dtype=torch.float64, device=device)
+    c = torch.empty((n, 16), dtype=torch.int32, device=device)
+    _check(load().rkr_rank_table(h, _ptr(t), _ptr(c)))
+    return t, c
+
+
 def rkr_stats(h: int) -> dict:
     s = QueryStats()
     _check(load().rkr_stats(h, ctypes.byref(s)))
@@ -250,11 +260,12 @@ class Index:
     """An index over device tensors U [n, d] and P [m, d] (float32 or bfloat16)."""
 
     def __init__(self, U: torch.Tensor, P: torch.Tensor, score: str = "bf16", recheck: bool = True,
-                 sketch_samples: int = 0):
+                 sketch_samples: int = 0, rank_table: int = 0):
         self.n, self.d = U.shape
         self.m = P.shape[0]
         self.device = U.device
-        self.h = rkr_build(U, P, score=score, recheck=recheck, sketch_samples=sketch_samples)
+        self.h = rkr_build(U, P, score=score, recheck=recheck, sketch_samples=sketch_samples,
+                           rank_table=rank_table)
 
     def close(self) -> None:
         if getattr(self, "h", None):
@@ -290,6 +301,9 @@ class Index:
 
     def sketch(self):
         return rkr_sketch(self.h, self.n, self.device)
+
+    def rank_table(self):
+        return rkr_rank_table(self.h, self.n, self.device)
 
     def stats(self) -> dict:
         return rkr_stats(self.h)

@@ -59,6 +59,9 @@ def test_build_validation_before_device_work(L):
     assert L.rkr_build(dummy, 1 << 31, dummy, 10, 8, 0, None, ctypes.byref(h)) == rkr.RKR_E_UNSUPPORTED
     bad_score = rkr.BuildOpts(9, 1, 0, 0, None)
     assert L.rkr_build(dummy, 10, dummy, 10, 8, 0, ctypes.byref(bad_score), ctypes.byref(h)) == rkr.RKR_E_INVALID
+    bad_table = rkr.BuildOpts(1, 1, 0, -5, None)
+    assert L.rkr_build(dummy, 10, dummy, 10, 8, 0, ctypes.byref(bad_table), ctypes.byref(h)) == rkr.RKR_E_INVALID
+    assert "rank_table" in _err(L)
     # d beyond what the count kernel supports for BF16 scoring
     assert L.rkr_build(dummy, 10, dummy, 10, 4000, 0, None, ctypes.byref(h)) == rkr.RKR_E_UNSUPPORTED
     assert h.value is None
@@ -73,6 +76,7 @@ def test_null_index_calls(L):
     assert "c must be >= 1" in _err(L)
     assert L.rkr_query_approx(None, None, 5, float("nan"), None, None) == rkr.RKR_E_INVALID
     assert L.rkr_ranks(None, None, None) == rkr.RKR_E_INVALID
+    assert L.rkr_rank_table(None, None, None) == rkr.RKR_E_INVALID
     assert L.rkr_configure(None, None) == rkr.RKR_E_INVALID
     s = rkr.QueryStats()
     assert L.rkr_stats(None, ctypes.byref(s)) == rkr.RKR_E_INVALID
