@@ -3,21 +3,23 @@
 
 A step is one rkr_query_batch call: 256 queries over |U| = |P| = 1,000,000,
 d = 200, BF16 masters, k = 100, exact answers (Def. 2), all of the hot path
-(thresholds, seeds, screening count, refine with FP64 near-tie recheck,
-top-k).  Inputs are synthetic (seeded, see workloads.py) and resident in HBM
-before the timed region; the index is built once, outside it.
+(thresholds, seeds, rank-table filter, screening count, refine with FP64
+near-tie recheck, top-k).  Inputs are synthetic (seeded, see workloads.py) and
+resident in HBM before the timed region; the index (with its rank table) is
+built once, outside it, and its build time is reported.
 
 Printed (one JSON line on stdout):
   value         queries/s of the BF16 + recheck path (exact)
   gcompare_per_s dense-equivalent rank comparisons per second (n * m * Q / t)
+  without_rank_table  the same batch with the table switched off
   fp32_plain    the same batch with FP32 scoring and a plain compare (no
                 band, no recheck), timed once, and the speed-up over it
-  roofline      the screening count kernel (the dominant kernel, bound by its
-                vector-ALU compare loop): (user, query, item) comparisons per
-                launch over its HIP-event duration, against one compare per
-                32-bit lane-op; HBM traffic from the committed counter record
-                while the kernel sources match it; the matrix-core view
-                (2 n m d flop against the BF16 dense peak) beside it
+  roofline      the count kernel (every launch of a step: screening phases,
+                seed and refine exact passes), bound by the matrix cores on
+                these sparse user sets: executed MFMA flop over the summed
+                HIP-event durations against the BF16 dense peak; HBM traffic
+                from the committed counter record while the kernel sources
+                match it; the compare-loop view beside it
   cpu_baseline  the CPU oracle on a bounded sample of users (all queries),
                 scaled to queries/s
   single_all_ranks  secondary: exact ranks of all 100k users for one query on
@@ -40,7 +42,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12     # 32-bit vector lane-ops/s (39.3 T)
-TRAFFIC = os.path.join(ROOT, "profiles", "k_count_screen_batch_1M_traffic.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "k_count_batch_1M_traffic.json")
 
 
 def code_digest(path: str) -> str:
@@ -56,9 +58,9 @@ def code_digest(path: str) -> str:
 
 
 def screen_traffic(key: dict, candidate: int):
-    """HBM bytes per screening launch from the committed counter record, or
-    None when the workload, the launch candidate or the kernel sources differ
-    from the ones it was taken on."""
+    """HBM bytes of a step's count-kernel launches from the committed counter
+    record, or None when the workload, the launch candidate or the kernel
+    sources differ from the ones it was taken on."""
     try:
         rec = json.load(open(TRAFFIC))
         if rec["workload_key"] != key or rec["screen_candidate"] != candidate:
@@ -66,7 +68,7 @@ def screen_traffic(key: dict, candidate: int):
         for path, digest in rec["sources_sha256"].items():
             if code_digest(os.path.join(ROOT, path)) != digest:
                 return None
-        return rec["hbm_bytes_per_launch"]
+        return rec["hbm_bytes_per_step"]
     except (OSError, KeyError, ValueError):
         return None
 METRIC = "queries/s + Gcompare/s at |U|=|P|=1M,d=200, exact top-k; BF16+recheck vs FP32 plain"
@@ -95,6 +97,7 @@ def main() -> int:
     ap.add_argument("--no-single", action="store_true", help="skip the single-query all-ranks line")
     ap.add_argument("--rank-table", type=int, default=4096,
                     help="sample items for the index's rank table (0: no table)")
+    ap.add_argument("--seed-mult", type=int, default=2, help="seeds per query, in units of k")
     ap.add_argument("--no-table-compare", action="store_true",
                     help="skip timing the same batch with the rank table switched off")
     ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")
@@ -132,6 +135,7 @@ def main() -> int:
     torch.cuda.synchronize()
     build_ms = (time.time() - t) * 1e3
     log("index built in %.0f ms" % build_ms)
+    idx.configure(seed_mult=args.seed_mult)
 
     for i in range(args.warmup):
         idx.query_batch(Q, w.k)
@@ -149,12 +153,15 @@ def main() -> int:
     qps = nq * args.steps / (t1 - t0)
     gcmp = n * m * nq / (ms_step / 1e3) / 1e9
     st = per[-1]
-    screen_ms = float(np.mean([s["ms_screen_kernel"] for s in per]))
-    flop = 2.0 * n * m * d
-    achieved = flop / (screen_ms / 1e3) / 1e12 if screen_ms > 0 else 0.0
+    # every launch of the count kernel in a step (screening phases, seed and
+    # refine exact passes): executed matrix-core flop over their summed
+    # HIP-event durations
+    kern_ms = float(np.mean([s["ms_screen_kernel"] + s["ms_exact_kernel"] for s in per]))
+    flop = float(np.mean([s["mfma_flop"] for s in per]))
+    achieved = flop / (kern_ms / 1e3) / 1e12 if kern_ms > 0 else 0.0
     peak = PEAK_TFLOPS[args.score]
-    cmp = float(np.mean([s["compares"] for s in per]))   # the exact passes' share is < 0.5 %
-    cmp_rate = cmp / (screen_ms / 1e3) / 1e12 if screen_ms > 0 else 0.0
+    cmp = float(np.mean([s["compares"] for s in per]))
+    cmp_rate = cmp / (kern_ms / 1e3) / 1e12 if kern_ms > 0 else 0.0
     ids_np = ids.cpu().numpy()
     rk_np = rk.cpu().numpy()
 
@@ -183,25 +190,27 @@ def main() -> int:
                                                       "ms_exact_kernel", "ms_recheck_kernel")},
         "counters": {k: int(st[k]) for k in ("pairs", "seed_pairs", "survivors", "refined_pairs",
                                              "uncertain", "flips", "compares", "compare_slots", "screen_ctas",
-                                             "screen_variant", "table_pruned")},
-        # The screening kernel is bound by its vector-ALU compare loop (VALU busy
-        # ~60 %, matrix cores ~16 %, see profiles/): achieved = (user, query, item)
-        # comparisons per launch / launch time, against one compare per lane-op
-        # (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz).  The matrix-core view of the
-        # same launch (2 n m d flop) is kept beside it.
-        "roofline": {"kernel": "k_count<screen>", "bound": "alu", "achieved": round(cmp_rate, 3),
-                     "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": round(cmp_rate / ALU_PEAK_TOPS, 4),
+                                             "screen_variant", "table_pruned", "mfma_flop")},
+        # With the rank table the count kernel runs on sparse user sets (about one
+        # pair per user), where its work is the U.P^T tile on the matrix cores:
+        # achieved = executed MFMA flop of all count launches of a step / their
+        # summed duration, against the BF16 dense peak.  The compare-loop view
+        # (comparisons against one compare per 32-bit lane-op) is kept beside it.
+        "roofline": {"kernel": "k_count (screening phases + exact passes)", "bound": "mfma",
+                     "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4),
                      "traffic": screen_traffic({"workload": w.name, "n": n, "m": m, "d": d, "queries": nq,
-                                                 "score": args.score}, int(st["screen_variant"])),
-                     "ops_per_launch": cmp, "kernel_ms": round(screen_ms, 3),
-                     "mfma_view": {"achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                                   "frac": round(achieved / peak, 4), "flop_per_launch": flop}},
+                                                 "score": args.score, "rank_table": args.rank_table},
+                                                int(st["screen_variant"])),
+                     "flop_per_step": flop, "kernel_ms": round(kern_ms, 3),
+                     "alu_view": {"achieved": round(cmp_rate, 4), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                                  "frac": round(cmp_rate / ALU_PEAK_TOPS, 5), "compares_per_step": cmp}},
     }
 
     if args.rank_table > 0 and not args.no_table_compare:
         # the same batch with the table switched off (the screen then scans
         # every non-seed pair); warm-up lets the tuner settle on its own key
-        idx.configure(no_table=True)
+        idx.configure(no_table=True, seed_mult=args.seed_mult)
         for _ in range(6):
             idx.query_batch(Q, w.k)
         torch.cuda.synchronize()
@@ -216,7 +225,7 @@ def main() -> int:
                                      "screen_kernel_ms": round(s_nt["ms_screen_kernel"], 2),
                                      "same_answers": same}
         out["speedup_from_rank_table"] = round(ms_nt / ms_step, 3)
-        idx.configure(no_table=False)
+        idx.configure(no_table=False, seed_mult=args.seed_mult)
         log("without the rank table: %.1f ms/step (same answers: %s)" % (ms_nt, same))
 
     if not args.no_single:

@@ -120,6 +120,7 @@ typedef struct {
                             /* compare_slots is the SIMD efficiency of the entry loops      */
     int64_t graph_replays;  /* 1 if the call replayed a captured graph                      */
     int64_t table_pruned;   /* pairs the rank table ruled out before the screen             */
+    int64_t mfma_flop;      /* matrix-core flop the count kernels executed (padded shapes)  */
 } rkr_query_stats;
 
 /*

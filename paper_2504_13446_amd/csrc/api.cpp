@@ -816,11 +816,12 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(launch_select(x->candkeys.as<uint64_t>(), x->candoff.as<int64_t>(), x->kdev.as<int32_t>(), nq,
                         x->bestoff.as<int64_t>(), x->ans.as<uint64_t>(), st));
     HIPCK(q_write_answer(x->ans.as<uint64_t>(), ksum, ids_out, ranks_out, st));
-    unsigned long long ctr[3] = {0, 0, 0};
-    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 24, hipMemcpyDeviceToHost, st));
+    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 48, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
+    x->stats.mfma_flop = (int64_t)ctr[5];
     {
         unsigned long long slots = 0;
         HIPCK(hipMemcpyAsync(&slots, x->ctr.as<unsigned long long>() + 3, 8, hipMemcpyDeviceToHost, st));
@@ -894,11 +895,12 @@ static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     rkr_status rs = exact_count(x, ps, x->allpid.as<int32_t>(), n);
     if (rs != RKR_OK) return rs;
     HIPCK(q_ranks_out(x->cnt.as<uint32_t>(), n, ranks_out, st));
-    unsigned long long ctr[3] = {0, 0, 0};
-    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 24, hipMemcpyDeviceToHost, st));
+    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 48, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
+    x->stats.mfma_flop = (int64_t)ctr[5];
     x->stats.refined_pairs = n;
     x->stats.ms_total = now_ms() - t0;
     return RKR_OK;
@@ -996,9 +998,9 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
     HIPCK(q_copy(q, g.qbuf.p, (int64_t)x->d * mes, st));
     HIPCK(hipGraphLaunch(g.ge, st));
-    unsigned long long ctr[3] = {0, 0, 0};
+    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
     int flags = 0;
-    HIPCK(hipMemcpyAsync(ctr, g.ctr.p, 24, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(ctr, g.ctr.p, 48, hipMemcpyDeviceToHost, st));
     HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
@@ -1016,6 +1018,7 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     x->stats.uncertain = (int64_t)ctr[0];
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
+    x->stats.mfma_flop = (int64_t)ctr[5];
     x->stats.ms_total = now_ms() - t0;
     x->stats.graph_replays = 1;
     return RKR_OK;

@@ -146,7 +146,7 @@ __device__ inline void wait_vm() {
 
 template <int SK, int MODE, int NKS, int NUB, int NIB>
 __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, uint64_t &ncmp,
-                                  uint64_t &nslot) {
+                                  uint64_t &nslot, uint64_t &nstep) {
     using FT = typename FragT<SK>::T;
     constexpr int FB = frag_fb(SK);
     constexpr int KS = frag_ks(SK);
@@ -413,6 +413,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     };
 
     for (int64_t st = s_begin; st < s_end; ++st) {
+        ++nstep;
         const uint8_t *tile = lds + cbuf * STAGE;
         // prefetch step st + NBUF - 1 straight into its LDS stage; that stage was
         // last read in the previous step, before the barrier that ended it
@@ -755,9 +756,9 @@ template <int SK, int MODE, int NKS, int NUB, int NIB, bool PERSIST>
 __global__ __launch_bounds__(512) void k_count(CountArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int lane = threadIdx.x & 63;
-    uint64_t ncmp = 0, nslot = 0;
+    uint64_t ncmp = 0, nslot = 0, nstep = 0;
     if constexpr (!PERSIST) {
-        count_tile<SK, MODE, NKS, NUB, NIB>(a, (int64_t)blockIdx.x, lds, ncmp, nslot);
+        count_tile<SK, MODE, NKS, NUB, NIB>(a, (int64_t)blockIdx.x, lds, ncmp, nslot, nstep);
     } else {
         __shared__ int64_t sh_tile;
         for (;;) {
@@ -766,7 +767,7 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
             const int64_t t = sh_tile;
             __syncthreads();
             if (t >= a.ntiles) break;
-            count_tile<SK, MODE, NKS, NUB, NIB>(a, t, lds, ncmp, nslot);
+            count_tile<SK, MODE, NKS, NUB, NIB>(a, t, lds, ncmp, nslot, nstep);
             __syncthreads();   // the next tile reuses the LDS buffers
         }
     }
@@ -781,6 +782,11 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
         atomicAdd(a.stat, (unsigned long long)tot);
         atomicAdd(a.stat + 2, (unsigned long long)tslot);   // lane slots, active or not
     }
+    // executed matrix-core flop: every step of a workgroup multiplies its
+    // 8 x NUB x 32 users by NIB x 32 items over the padded dimension
+    constexpr unsigned long long FLOP_PER_STEP =
+        2ull * WAVES_PER_WG * NUB * USER_BLOCK * NIB * 32 * NKS * frag_ks(SK);
+    if (threadIdx.x == 0 && a.stat) atomicAdd(a.stat + 4, (unsigned long long)nstep * FLOP_PER_STEP);
 }
 
 template <int SK, int MODE, int NKS, int NUB, int NIB>

@@ -270,22 +270,25 @@ __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t nb) {
 // such a pair's count reaches B[q] and its rank exceeds the bound, exactly
 // what the screen would find by scanning.  Seeds (already counted) are never
 // kept.
-__global__ void k_table_keep(int64_t npairs, const int32_t *pair_u, const int32_t *pair_q, const double *t64,
-                             const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
-                             const uint32_t *tab_cnt, uint8_t *keep) {
+// Dense domains (nq > 0) number pairs u * nq + q, so the pair arrays are not
+// read.
+__global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, const int32_t *pair_q,
+                             const double *t64, const uint8_t *seedflag, const int32_t *bound,
+                             const double *tab_t, const uint32_t *tab_cnt, uint8_t *keep) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npairs) return;
     if (seedflag[i]) {
         keep[i] = 0;
         return;
     }
-    const int64_t u = pair_u[i];
+    const int64_t u = nq > 0 ? i / nq : pair_u[i];
+    const int q = nq > 0 ? (int)(i - u * nq) : pair_q[i];
     const double t = t64[i];
     uint32_t best = 0;
 #pragma unroll
     for (int j = 0; j < TABLE_COLS; ++j)
         if (tab_t[u * TABLE_COLS + j] >= t) best = max(best, tab_cnt[u * TABLE_COLS + j]);
-    keep[i] = (int64_t)best >= (int64_t)bound[pair_q[i]] ? 0 : 1;
+    keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
 }
 
 // out[i] = the smallest float >= x[i]
@@ -416,7 +419,8 @@ hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream
 
 hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
                         const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st) {
-    LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound, tab_t, tab_cnt, keep);
+    LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, ps.dense ? ps.nq : 0, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound,
+             tab_t, tab_cnt, keep);
     return hipGetLastError();
 }
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st) {

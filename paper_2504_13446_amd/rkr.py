@@ -58,7 +58,8 @@ class QueryStats(ctypes.Structure):
                                                              ("screen_variant", ctypes.c_int64),
                                                              ("compare_slots", ctypes.c_int64),
                                                              ("graph_replays", ctypes.c_int64),
-                                                             ("table_pruned", ctypes.c_int64)]
+                                                             ("table_pruned", ctypes.c_int64),
+                                                             ("mfma_flop", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
