@@ -97,7 +97,8 @@ def main() -> int:
     ap.add_argument("--no-single", action="store_true", help="skip the single-query all-ranks line")
     ap.add_argument("--rank-table", type=int, default=4096,
                     help="sample items for the index's rank table (0: no table)")
-    ap.add_argument("--seed-mult", type=int, default=2, help="seeds per query, in units of k")
+    ap.add_argument("--seed-mult", type=int, default=0,
+                    help="seeds per query, in units of k (0: the library's default)")
     ap.add_argument("--no-table-compare", action="store_true",
                     help="skip timing the same batch with the rank table switched off")
     ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")

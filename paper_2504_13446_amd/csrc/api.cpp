@@ -9,6 +9,8 @@
 //   4. exact count of the seed pairs (screen + FP64 near-tie recheck)
 //   5. bound      B_q = k-th smallest seed rank >= R_k (the k-th smallest rank
 //                 over all users); X_q = B_q (exact) or floor(B_q / c) (approx.)
+//   5b. table     with a rank table (Sec. 4.2), pairs whose table lower bound
+//                 already exceeds X_q are dropped without a scan
 //   6. screen     every pair is scanned against norm-sorted P and dropped once
 //                 1 + certain count > X_q (the paper's Lemma 1 (2))
 //   7. refine     exact count of the pairs still live after the screen
@@ -225,7 +227,7 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     x->n = n; x->m = m; x->d = d; x->dpad = dpad; x->nks = nks; x->sk = sk; x->recheck = recheck;
     x->mk = dt == RKR_BF16 ? MK_BF16 : MK_F32;
     x->st = st;
-    x->qo.seed_mult = 2;
+    x->qo.seed_mult = 0;   // chosen per call (see run_batch)
     x->qo.approx_refine = 4;
     x->tuner.load();
     {
@@ -336,7 +338,6 @@ extern "C" rkr_status rkr_configure(rkr_index *x, const rkr_query_opts *o) {
     if (o->seed_mult < 0 || o->approx_refine < 0 || o->prune_mult < 0) return fail(RKR_E_INVALID, "negative option");
     if (o->use_estimator && !x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
     rkr_query_opts q = *o;
-    if (q.seed_mult == 0) q.seed_mult = 2;
     if (q.approx_refine == 0) q.approx_refine = 4;
     x->qo = q;
     return RKR_OK;
@@ -639,7 +640,12 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
                         x->est.pred.as<float>(), 0, 0, st));
         pred = x->est.pred.as<float>();
     }
-    const int64_t mult = pruned ? std::max(1, x->qo.prune_mult) : std::max(1, x->qo.seed_mult);
+    // default seeds: 2k per query, or k when the rank table prunes (then a
+    // seed missed by the heuristic costs one screened and refined pair, less
+    // than counting a second k of seeds exactly)
+    const bool table_on = x->has_table && !x->qo.no_table;
+    const int seed_mult = x->qo.seed_mult > 0 ? x->qo.seed_mult : (table_on ? 1 : 2);
+    const int64_t mult = pruned ? std::max(1, x->qo.prune_mult) : seed_mult;
     for (int q = 0; q < nq; ++q) {
         S[q] = std::min<int64_t>(dom[q], std::min<int64_t>(4096, std::max<int64_t>(k[q], mult * k[q])));
         Sv[q] = (int32_t)S[q];
