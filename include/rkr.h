@@ -39,6 +39,9 @@
 
 #include <stdint.h>
 
+/* Columns (thresholds) per user of the rank table (rkr_rank_table). */
+#define RKR_TABLE_COLS 32
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -72,9 +75,10 @@ typedef struct {
     int32_t sketch_samples; /* >0: build the per-user score sketch for the estimator    */
                             /*     from this many norm-stratified items (e.g. 4096)     */
     int32_t rank_table;     /* >0: build the rank table (Sec. 4.2) from this many       */
-                            /*     norm-stratified items (at most 4096): 16 thresholds  */
-                            /*     per user with certain counts over all of P; batch    */
-                            /*     queries then skip the pairs it rules out (Lemma 1)   */
+                            /*     norm-stratified items (at most 4096): RKR_TABLE_COLS */
+                            /*     thresholds per user with certain counts over all of  */
+                            /*     P; batch queries then skip the pairs it rules out    */
+                            /*     (Lemma 1)                                            */
     void *stream;           /* hipStream_t for all work on this index; NULL = default   */
 } rkr_build_opts;
 
@@ -179,13 +183,15 @@ rkr_status rkr_query_batch(rkr_index *idx, int32_t nq, const void *Qm, const int
                            int32_t *ids_out, int32_t *ranks_out);
 
 /*
- * The rank table (Sec. 4.2) of an index built with rank_table > 0.  Column j
- * of user u holds a threshold t_out[u * 16 + j] (FP64: the user's spec score
- * against a sample item, columns in descending order) and cnt_out[u * 16 + j],
+ * The rank table (Sec. 4.2) of an index built with rank_table > 0, with
+ * RKR_TABLE_COLS columns per user.  Column j of user u holds a threshold
+ * t_out[u * RKR_TABLE_COLS + j] (FP64: the user's spec score against a sample
+ * item; thresholds do not increase with j) and cnt_out[u * RKR_TABLE_COLS + j],
  * a count of items p with s64(u,p) > t certainly (a lower bound of the exact
  * count: items within the score error of t are left out).  The paper's cell
- * is 1 + that count.  t_out [device, n x 16 double], cnt_out [device, n x 16
- * uint32], caller-allocated.  RKR_E_STATE if the index has no table.
+ * is 1 + that count.  t_out [device, n x RKR_TABLE_COLS double], cnt_out
+ * [device, n x RKR_TABLE_COLS uint32], caller-allocated.  RKR_E_STATE if the
+ * index has no table.
  */
 rkr_status rkr_rank_table(const rkr_index *idx, double *t_out, uint32_t *cnt_out);
 

@@ -190,6 +190,7 @@ struct rkr_index {
 // ---------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------
+static_assert(TABLE_COLS == RKR_TABLE_COLS, "the kernels' table width is the ABI's");
 static rkr_status build_rank_table(rkr_index *x, int samples);
 
 extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t m, int32_t d, rkr_dtype dt,
@@ -508,8 +509,8 @@ static rkr_status build_rank_table(rkr_index *x, int samples) {
     HIPCK(x->tab_t.ensure(cells * 8));
     HIPCK(x->tab_th.ensure(cells * 4));
     HIPCK(x->tab_cnt.ensure(cells * 4));
-    rkr_status rs = sample_levels(x->Um.p, n, x->Pm.p, x->m, x->d, x->mk, samples, nullptr, x->tab_t.as<double>(),
-                                  x->sc, st);
+    rkr_status rs = sample_levels(x->Um.p, n, x->Pm.p, x->m, x->d, x->mk, samples, TABLE_COLS, nullptr,
+                                  x->tab_t.as<double>(), x->sc, st);
     if (rs != RKR_OK) return fail(rs, "rank table: sample scores");
     HIPCK(q_round_up_f32(x->tab_t.as<double>(), cells, x->tab_th.as<float>(), st));
     HIPCK(launch_fill_u32(x->tab_cnt.as<uint32_t>(), 0, cells, st));

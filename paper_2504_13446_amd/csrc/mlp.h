@@ -28,11 +28,12 @@ rkr_status est_build_sketch(Estimator &e, const void *Um, int64_t n, const void 
                             const double *unorm3, int samples, Scratch &sc, hipStream_t st);
 // For each user: the spec scores against min(samples, 4096, m) norm-stratified
 // items (the middle item of each of S equal buckets of the norm-sorted P),
-// sorted descending and read at SKETCH_LEVELS positions spaced geometrically
-// from 1 to S.  sketch_out[u][j] = fl32(score / |u|), raw_out[u][j] = the
-// FP64 score; either may be null.  RKR_E_INVALID if m = 0 or samples <= 0.
+// sorted descending and read at `levels` (2..64) positions spaced
+// geometrically from 1 to S, ceil(S^(j / (levels - 1))).  sketch_out[u][j] =
+// fl32(score / |u|), raw_out[u][j] = the FP64 score; either may be null.
+// RKR_E_INVALID if m = 0, samples <= 0 or levels is out of range.
 rkr_status sample_levels(const void *Um, int64_t n, const void *Pm_sorted, int64_t m, int d, int mk, int samples,
-                         float *sketch_out, double *raw_out, Scratch &sc, hipStream_t st);
+                         int levels, float *sketch_out, double *raw_out, Scratch &sc, hipStream_t st);
 hipError_t est_features(const int32_t *pids, int64_t N, const int32_t *pair_u, const double *t64,
                         const double *unorm3, const float *sketch, const uint32_t *cnt, float *X, float *z,
                         hipStream_t st);

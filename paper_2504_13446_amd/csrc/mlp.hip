@@ -81,10 +81,10 @@ __global__ __launch_bounds__(256) void k_sketch_scores(const void *Um, int64_t u
 
 // One workgroup per user: bitonic sort (descending) of the S scores in LDS,
 // then out[u][j] = fl32(score at 1-based position pos[j] / |u|) and raw[u][j]
-// = that score itself (either output may be null).
+// = that score itself, for j < levels (either output may be null).
 __global__ __launch_bounds__(1024) void k_sketch_select(const void *Um, int64_t u0, int64_t nb, const double *scores,
-                                                        int S, int d, int mk, const int *pos, float *out,
-                                                        double *raw) {
+                                                        int S, int d, int mk, const int *pos, int levels,
+                                                        float *out, double *raw) {
     __shared__ double s[4096];
     __shared__ double nrm;
     const int64_t i = blockIdx.x;
@@ -114,10 +114,10 @@ __global__ __launch_bounds__(1024) void k_sketch_select(const void *Um, int64_t 
             }
             __syncthreads();
         }
-    if (threadIdx.x < SKETCH_LEVELS) {
+    if ((int)threadIdx.x < levels) {
         const double sv = s[pos[threadIdx.x] - 1];
-        if (out) out[u * SKETCH_LEVELS + threadIdx.x] = (float)(nrm > 0.0 ? sv / nrm : 0.0);
-        if (raw) raw[u * SKETCH_LEVELS + threadIdx.x] = sv;
+        if (out) out[u * levels + threadIdx.x] = (float)(nrm > 0.0 ? sv / nrm : 0.0);
+        if (raw) raw[u * levels + threadIdx.x] = sv;
     }
 }
 
@@ -445,23 +445,24 @@ rkr_status est_build_sketch(Estimator &e, const void *Um, int64_t n, const void 
         e.has_sketch = true;
         return RKR_OK;
     }
-    rkr_status rs = sample_levels(Um, n, Pm_sorted, m, d, mk, S, e.sketch.as<float>(), nullptr, sc, st);
+    rkr_status rs = sample_levels(Um, n, Pm_sorted, m, d, mk, S, SKETCH_LEVELS, e.sketch.as<float>(), nullptr, sc,
+                                  st);
     if (rs != RKR_OK) return rs;
     e.has_sketch = true;
     return RKR_OK;
 }
 
 rkr_status sample_levels(const void *Um, int64_t n, const void *Pm_sorted, int64_t m, int d, int mk, int samples,
-                         float *sketch_out, double *raw_out, Scratch &sc, hipStream_t st) {
+                         int levels, float *sketch_out, double *raw_out, Scratch &sc, hipStream_t st) {
     const int S = (int)std::min<int64_t>((int64_t)std::min(samples, 4096), m);
-    if (S <= 0) return RKR_E_INVALID;
-    int pos[SKETCH_LEVELS];
-    for (int j = 0; j < SKETCH_LEVELS; ++j) {
-        double v = std::ceil(std::pow((double)S, (double)j / (SKETCH_LEVELS - 1)) - 1e-9);
+    if (S <= 0 || levels < 2 || levels > 64) return RKR_E_INVALID;
+    int pos[64] = {};
+    for (int j = 0; j < levels; ++j) {
+        double v = std::ceil(std::pow((double)S, (double)j / (levels - 1)) - 1e-9);
         int p = (int)v;
         pos[j] = p < 1 ? 1 : (p > S ? S : p);
     }
-    int *dpos = (int *)sc.take(64);
+    int *dpos = (int *)sc.take(sizeof(pos));
     const int64_t nbmax = std::max<int64_t>(64, std::min<int64_t>(n, ((int64_t)1 << 31) / ((int64_t)S * 8)));
     double *scr = (double *)sc.take(nbmax * S * 8);
     if (!dpos || !scr) return RKR_E_NOMEM;
@@ -471,7 +472,7 @@ rkr_status sample_levels(const void *Um, int64_t n, const void *Pm_sorted, int64
         dim3 g1(nblocks(S, 64), nblocks(nb, 64));
         hipLaunchKernelGGL(k_sketch_scores, g1, dim3(256), 0, st, Um, u0, nb, Pm_sorted, m, S, d, mk, scr);
         hipLaunchKernelGGL(k_sketch_select, dim3((unsigned)nb), dim3(1024), 0, st, Um, u0, nb, (const double *)scr, S,
-                           d, mk, (const int *)dpos, sketch_out, raw_out);
+                           d, mk, (const int *)dpos, levels, sketch_out, raw_out);
         if (hipGetLastError() != hipSuccess) return RKR_E_DEVICE;
     }
     if (hipStreamSynchronize(st) != hipSuccess) return RKR_E_DEVICE;

@@ -284,10 +284,17 @@ __global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, cons
     const int64_t u = nq > 0 ? i / nq : pair_u[i];
     const int q = nq > 0 ? (int)(i - u * nq) : pair_q[i];
     const double t = t64[i];
-    uint32_t best = 0;
+    // the columns' thresholds do not increase: L = the number of columns
+    // with t_{u,j} >= t, by binary search; column L - 1 is the tightest of
+    // them (any one of them gives a valid bound)
+    static_assert((TABLE_COLS & (TABLE_COLS - 1)) == 0, "binary search over a power of two");
+    const double *tt = tab_t + u * TABLE_COLS;
+    int L = 0;
 #pragma unroll
-    for (int j = 0; j < TABLE_COLS; ++j)
-        if (tab_t[u * TABLE_COLS + j] >= t) best = max(best, tab_cnt[u * TABLE_COLS + j]);
+    for (int step = TABLE_COLS / 2; step >= 1; step >>= 1)
+        if (tt[L + step - 1] >= t) L += step;
+    if (tt[L] >= t) L += 1;
+    const uint32_t best = L > 0 ? tab_cnt[u * TABLE_COLS + L - 1] : 0u;
     keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
 }
 

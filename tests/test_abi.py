@@ -94,3 +94,9 @@ def test_error_message_is_thread_local(L):
     t.start(); t.join()
     assert seen == [""]
     assert "n must be positive" in _err(L)
+
+
+def test_table_width_matches_header():
+    src = open(HEADER).read()
+    m = re.search(r"#define\s+RKR_TABLE_COLS\s+(\d+)", src)
+    assert m and int(m.group(1)) == rkr.TABLE_COLS

@@ -43,16 +43,16 @@ def test_table_against_oracle(score):
     c = c.cpu().numpy().astype(np.int64)
     idx.close()
     sample = O.stratified_sample(w.P, S)
-    want_t, want_c = O.rank_table(w.U, w.P, sample, O.sketch_positions(S))
+    want_t, want_c = O.rank_table(w.U, w.P, sample, O.sketch_positions(S, rkr.TABLE_COLS))
     assert np.array_equal(t, want_t)
     assert np.all(c <= want_c), np.argwhere(c > want_c)[:5]
     # the shortfall is made of near ties only
     sc = O.dots(w.U, w.P)
     delta = REL_ERR[score] * O.norms(w.U)[:, None] * O.norms(w.P).max()
     near = np.stack([np.sum((sc > want_t[:, j:j + 1]) & (sc <= want_t[:, j:j + 1] + delta), axis=1)
-                     for j in range(16)], axis=1)
+                     for j in range(rkr.TABLE_COLS)], axis=1)
     assert np.all(want_c - c <= near)
-    assert (want_c - c).sum() <= MISS[score] * want_c.sum() + 16 * w.n
+    assert (want_c - c).sum() <= MISS[score] * want_c.sum() + rkr.TABLE_COLS * w.n
 
 
 @pytest.mark.parametrize("score", ["bf16", "fp8", "f32"])
@@ -124,7 +124,7 @@ def test_table_edge_cases():
     P = rng.standard_normal((5, 9)).astype(np.float32)
     idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score="bf16", rank_table=4096)
     t, c = idx.rank_table()
-    want_t, want_c = O.rank_table(U, P, O.stratified_sample(P, 5), O.sketch_positions(5))
+    want_t, want_c = O.rank_table(U, P, O.stratified_sample(P, 5), O.sketch_positions(5, rkr.TABLE_COLS))
     assert np.array_equal(t.cpu().numpy(), want_t)
     assert np.all(c.cpu().numpy() <= want_c)
     R = O.ranks(U, P, P[:2])
