@@ -76,23 +76,29 @@ def test_approx_c1_equals_exact():
 
 
 def test_full_size_batch_sampled():
-    """1M users x 1M items x d=200, 256 queries, k=100 (the benchmark's
-    configuration).  For two queries: the ranks of all 100 returned users are
-    recomputed by the oracle, and 3,000 random other users are certified not
-    to beat the k-th (rank, id)."""
+    """1M users x 1M items x d=200, 256 queries, k=100, with the rank table
+    of the benchmark's configuration.  For two queries: the ranks of all 100
+    returned users are recomputed by the oracle, and 3,000 other users are
+    certified not to beat the k-th (rank, id): 1,500 at random and the 1,500
+    best by u.q/|u| outside the answer (the ones most likely to)."""
     w = W.make("batch")
-    idx = rkr.Index(_dev(w.U, "bf16"), _dev(w.P, "bf16"), score="bf16")
+    idx = rkr.Index(_dev(w.U, "bf16"), _dev(w.P, "bf16"), score="bf16", rank_table=4096)
     ids, rk, off = idx.query_batch(_dev(w.Qv, "bf16"), w.k)
     ids = ids.cpu().numpy(); rk = rk.cpu().numpy()
     st = idx.stats()
     idx.close()
     assert st["pairs"] == 256 * 1_000_000
+    assert st["table_pruned"] > 0.99 * (st["pairs"] - st["seed_pairs"])
     Uw, Pw = O.widen(w.U), O.widen(w.P)
+    unorm = np.sqrt(np.einsum("ij,ij->i", Uw, Uw))
     rng = np.random.default_rng(3)
     for i in (0, 137):
         a_ids, a_rk = ids[off[i]:off[i + 1]], rk[off[i]:off[i + 1]]
         assert len(set(a_ids.tolist())) == 100
         assert np.all(np.diff(a_rk) >= 0)
-        sample = rng.choice(w.n, 3000, replace=False)
+        h = (Uw @ O.widen(w.Qv[i])) / np.maximum(unorm, 1e-300)
+        best = [u for u in np.argsort(-h)[:1700] if u not in set(a_ids.tolist())][:1500]
+        rand = rng.choice(w.n, 1500, replace=False)
+        sample = np.unique(np.concatenate([np.asarray(best, np.int64), rand]))
         bad_rank, bad_set, _ = O.certify(Uw, Pw, O.widen(w.Qv[i]), 100, a_ids, a_rk, check=sample)
         assert (bad_rank, bad_set) == (0, 0), i
