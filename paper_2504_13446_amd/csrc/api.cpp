@@ -443,6 +443,15 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int va
     return a;
 }
 
+// Largest near-tie record buffer an exact pass may grow to: half of the
+// device memory free beyond the current buffer (at least 2^24 records).
+static int64_t max_emit_records(const rkr_index *x) {
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return (int64_t)1 << 24;
+    const int64_t have = (int64_t)x->emit_cap;
+    return std::max<int64_t>((int64_t)1 << 24, have + (int64_t)(freeb / 2 / 8));
+}
+
 // Exact counts (certain-above + FP64 recheck of near ties) of the pairs
 // pids[0..N) (ascending); adds into cnt[pid] after zeroing it.
 static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pids, int64_t N) {
@@ -489,7 +498,21 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
             return RKR_OK;
         }
         x->stats.emit_retries += 1;
-        x->emit_cap = (int64_t)(ne + ne / 4 + 1024);
+        const int64_t max_emit = max_emit_records(x);
+        if ((int64_t)ne + (int64_t)(ne / 4) > max_emit && N > 1) {
+            // more near ties than the device has room for (wide bands, e.g.
+            // FP8 scores): count the pairs in parts, each sized for about
+            // half of that room if the ties spread evenly (a part that still
+            // overflows splits again; a single pair emits at most m records)
+            const int64_t parts = std::min<int64_t>(N, ((int64_t)ne + max_emit / 2 - 1) / (max_emit / 2));
+            const int64_t chunk = (N + parts - 1) / parts;
+            for (int64_t p0 = 0; p0 < N; p0 += chunk) {
+                rkr_status r = exact_count(x, ps, pids + p0, std::min<int64_t>(chunk, N - p0));
+                if (r != RKR_OK) return r;
+            }
+            return RKR_OK;
+        }
+        x->emit_cap = std::min<int64_t>((int64_t)(ne + ne / 4 + 1024), std::max<int64_t>(max_emit, x->m + 1024));
         HIPCK(x->emit.ensure((size_t)x->emit_cap * 8));
     }
     return fail(RKR_E_DEVICE, "near-tie buffer kept overflowing");
@@ -579,6 +602,8 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     ps.nq = nq;
     ps.dense = dense ? 1 : 0;
     const int64_t npairs = dense ? n * nq : cand_off[nq];
+    // pair ids are 32-bit
+    if (npairs >= ((int64_t)1 << 31)) return fail(RKR_E_UNSUPPORTED, "2^31 or more (user, query) pairs: split the batch");
     ps.npairs = npairs;
     x->stats.pairs = npairs;
     HIPCK(x->pair_u.ensure(npairs * 4));

@@ -353,24 +353,33 @@ __device__ inline double spec_dot_rows(const void *A, int64_t ra, const void *B,
     return acc;
 }
 
+// A grid of at most 2^16 workgroups strides over the records (a launch's
+// work-items must stay below 2^32; wide bands can emit more records).
 __global__ void k_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, const double *t64,
                           const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                           unsigned long long *flips) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool flip = false;
-    if (i < nrec) {
-        const int2 r = rec[i];
-        const int pid = r.x;
-        const int64_t item = r.y & 0x7FFFFFFF;
-        const bool plain = (r.y >> 31) & 1;
-        const int64_t u = pair_u[pid];
-        const double acc = spec_dot_rows(Um, u, Pm, item, d, mk);
-        const bool above = acc > t64[pid];
-        if (above) atomicAdd(&cnt[pid], 1u);
-        flip = above != plain;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // every wave runs the same number of iterations (the ballot needs them all)
+    const int64_t iters = (nrec + stride - 1) / stride;
+    unsigned long long nflip = 0;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t i = i0 + it * stride;
+        bool flip = false;
+        if (i < nrec) {
+            const int2 r = rec[i];
+            const int pid = r.x;
+            const int64_t item = r.y & 0x7FFFFFFF;
+            const bool plain = (r.y >> 31) & 1;
+            const int64_t u = pair_u[pid];
+            const double acc = spec_dot_rows(Um, u, Pm, item, d, mk);
+            const bool above = acc > t64[pid];
+            if (above) atomicAdd(&cnt[pid], 1u);
+            flip = above != plain;
+        }
+        nflip += (unsigned long long)__popcll(__ballot(flip));
     }
-    unsigned long long b = __ballot(flip);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(flips, (unsigned long long)__popcll(b));
+    if ((threadIdx.x & 63) == 0 && nflip) atomicAdd(flips, nflip);
 }
 
 // The same with the record count read from device memory (graph replays):
@@ -501,8 +510,8 @@ hipError_t launch_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, 
                           const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                           unsigned long long *flips, hipStream_t st) {
     if (nrec <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_recheck, dim3(nblocks(nrec, 256)), dim3(256), 0, st, rec, nrec, pair_u, t64, Um,
-                       Pm, d, mk, cnt, flips);
+    const unsigned nb = nblocks(std::min<int64_t>(nrec, (int64_t)65536 * 256), 256);
+    hipLaunchKernelGGL(k_recheck, dim3(nb), dim3(256), 0, st, rec, nrec, pair_u, t64, Um, Pm, d, mk, cnt, flips);
     return hipGetLastError();
 }
 

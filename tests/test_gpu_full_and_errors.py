@@ -102,3 +102,17 @@ def test_full_size_batch_sampled():
         sample = np.unique(np.concatenate([np.asarray(best, np.int64), rand]))
         bad_rank, bad_set, _ = O.certify(Uw, Pw, O.widen(w.Qv[i]), 100, a_ids, a_rk, check=sample)
         assert (bad_rank, bad_set) == (0, 0), i
+
+
+def test_too_many_pairs_is_rejected():
+    """Pair ids are 32-bit: a batch of 2^31 or more (user, query) pairs is
+    refused before any work (2^21 users x 1,024 queries, d = 1)."""
+    n, nq = 1 << 21, 1024
+    U = torch.ones((n, 1), dtype=torch.float32, device="cuda")
+    P = torch.ones((8, 1), dtype=torch.float32, device="cuda")
+    idx = rkr.Index(U, P, score="f32")
+    Q = torch.ones((nq, 1), dtype=torch.float32, device="cuda")
+    with pytest.raises(rkr.RkrError) as e:
+        idx.query_batch(Q, [1] * nq)
+    assert e.value.status == rkr.RKR_E_UNSUPPORTED
+    idx.close()

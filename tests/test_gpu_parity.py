@@ -175,3 +175,22 @@ def test_uneven_candidates_exact_and_approx(score):
         v, _ = O.def3_check(true, wr, 1.5)
         assert v == 0, i
     idx.close()
+
+
+def test_recheck_of_many_near_ties():
+    """Entries in {-1, 0, 1}, d = 3: every score is a small integer and about a
+    quarter of the items tie with the query for every user, so one all-ranks
+    call emits tens of millions of near-tie records, more than one grid of
+    the recheck kernel covers (it strides over them)."""
+    rng = np.random.default_rng(29)
+    n, m, d = 20000, 8000, 3
+    U = rng.integers(-1, 2, size=(n, d)).astype(np.float32)
+    P = rng.integers(-1, 2, size=(m, d)).astype(np.float32)
+    q = P[5].copy()
+    R = O.ranks(U, P, q[None, :])[0]
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score="bf16")
+    got = idx.ranks(_dev(q, "f32")).cpu().numpy()
+    st = idx.stats()
+    idx.close()
+    assert st["uncertain"] > 65536 * 256, st["uncertain"]
+    assert np.array_equal(got, R), np.flatnonzero(got != R)[:10]
