@@ -176,7 +176,8 @@ rkr_status rkr_query_approx(rkr_index *idx, const void *q, int32_t k, double c,
  *   ids_out, ranks_out [device, sum(k)]  answers concatenated in query order
  * Errors: RKR_E_INVALID for k[i] < 1 or above its domain size, c[i] < 1 or
  * NaN, non-monotone offsets, ids out of range or duplicated within a list;
- * RKR_E_UNSUPPORTED for nq > 65535 or k[i] > 4096.
+ * RKR_E_UNSUPPORTED for nq > 65535, k[i] > 4096, or 2^31 or more (user,
+ * query) pairs in the batch (n * nq, or the candidate lists' total).
  */
 rkr_status rkr_query_batch(rkr_index *idx, int32_t nq, const void *Qm, const int32_t *k,
                            const double *c, const int64_t *cand_off, const int32_t *cand_ids,
@@ -210,7 +211,8 @@ rkr_status rkr_ranks(rkr_index *idx, const void *q, int32_t *ranks_out);
 rkr_status rkr_train(rkr_index *idx, int32_t nq, const void *Qm, int32_t pairs_per_query,
                      int32_t epochs, int32_t batch, float lr, uint64_t seed);
 
-/* Predicted ln r for nq queries x every user: out [device, nq x n float]. */
+/* Predicted ln r for nq queries x every user: out [device, nq x n float].
+ * RKR_E_UNSUPPORTED if nq * n >= 2^31 (as for rkr_train's training queries). */
 rkr_status rkr_predict(rkr_index *idx, int32_t nq, const void *Qm, float *out);
 
 /*

@@ -1088,6 +1088,7 @@ extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_
     ps.nq = nq;
     ps.dense = 1;
     const int64_t npairs = n * nq;
+    if (npairs >= ((int64_t)1 << 31)) return fail(RKR_E_UNSUPPORTED, "2^31 or more (user, query) pairs: fewer queries");
     ps.npairs = npairs;
     HIPCK(x->pair_u.ensure(npairs * 4));
     HIPCK(x->pair_q.ensure(npairs * 4));
@@ -1193,6 +1194,7 @@ extern "C" rkr_status rkr_predict(rkr_index *x, int32_t nq, const void *Qm, floa
     if (nq < 1 || nq > 65535) return fail(RKR_E_INVALID, "nq must be in 1..65535");
     hipStream_t st = x->st;
     const int64_t n = x->n, npairs = n * nq;
+    if (npairs >= ((int64_t)1 << 31)) return fail(RKR_E_UNSUPPORTED, "2^31 or more (user, query) pairs: fewer queries");
     x->sc.reset();
     HIPCK(x->pair_u.ensure(npairs * 4));
     HIPCK(x->pair_q.ensure(npairs * 4));
