@@ -705,9 +705,10 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(x->seedpid.ensure(nsel * 4));
     HIPCK(x->allpid.ensure(npairs * 4));
     int64_t nseed = 0;
-    // seeds (counted exactly below) and the other pairs (the ones to screen)
+    // seeds (counted exactly below) and the other pairs (the ones to screen;
+    // with a rank table the filter lists them instead)
     HIPCK(q_split_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), &nseed,
-                        x->allpid.as<int32_t>(), st, x->sc));
+                        table_on ? nullptr : x->allpid.as<int32_t>(), st, x->sc));
     x->stats.seed_pairs = nseed;
     // ---- 4. exact count of the seeds
     HIPCK(x->cnt.ensure(npairs * 4));

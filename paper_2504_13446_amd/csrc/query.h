@@ -24,7 +24,6 @@ struct TView {
     const uint32_t *ent_cnt;    // screening: remaining budgets
 };
 
-hipError_t scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st);
 
 hipError_t q_seed_keys(const QView &v, const int32_t *pair_u, const double *t64, const double *unorm3,
                        const float *pred, int64_t total, uint64_t *keys, hipStream_t st);

@@ -112,22 +112,6 @@ __global__ void k_mark_selected(QView v, const uint64_t *sel, const int64_t *sel
     flag[pid_of(v, q, i)] = 1;
 }
 
-__global__ void k_scatter_flagged(const uint8_t *flag, const int64_t *excl, int64_t N, int32_t *out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N && flag[i]) out[excl[i]] = (int32_t)i;
-}
-
-// Both sides of a flag array: flagged indices to out1 (ascending), the others
-// to out0 (ascending), from one exclusive scan of the flags.
-__global__ void k_scatter_split(const uint8_t *flag, const int64_t *excl, int64_t N, int32_t *out1, int32_t *out0) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    if (flag[i])
-        out1[excl[i]] = (int32_t)i;
-    else
-        out0[i - excl[i]] = (int32_t)i;
-}
-
 __global__ void k_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) cnt[pids[i]] = 0;
@@ -263,6 +247,86 @@ __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t nb) {
 }
 
 // ---------------------------------------------------------------------------
+// Stream compaction of a 0/1 byte array (flags) into the ascending indices
+// of its set (and, optionally, unset) bytes.  A block owns FC_CHUNK bytes,
+// read 16 at a time per thread in FC_ITER coalesced sweeps; pass 1 counts the
+// set bytes per block, an exclusive scan of the block counts gives each
+// block's output offset, pass 2 re-reads the chunk and writes the indices in
+// element order (sweep, thread, byte).  No per-element offsets are stored.
+constexpr int FC_BS = 256, FC_ITER = 4, FC_CHUNK = FC_BS * 16 * FC_ITER;
+
+// The lane's 16 flags at byte offset o (fewer past n; bytes past n read as 0)
+__device__ inline uint4 flags16(const uint8_t *flag, int64_t n, int64_t o) {
+    if (o + 16 <= n) return *(const uint4 *)(flag + o);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (int j = 0; j < 16; ++j)
+        if (o + j < n) w[j >> 2] |= (uint32_t)flag[o + j] << (8 * (j & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+__device__ inline int count16(uint4 v) {
+    return __popc(v.x & 0x01010101u) + __popc(v.y & 0x01010101u) + __popc(v.z & 0x01010101u) +
+           __popc(v.w & 0x01010101u);
+}
+// block-wide exclusive prefix of v over threads, and the block total
+__device__ inline int block_excl(int v, int *tot) {
+    __shared__ int ws[FC_BS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < FC_BS / 64; ++w) {
+        before += w < wave ? ws[w] : 0;
+        all += ws[w];
+    }
+    __syncthreads();   // ws is reused by the next call
+    *tot = all;
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(FC_BS) void k_flag_count(const uint8_t *flag, int64_t n, int64_t *counts) {
+    const int64_t base = (int64_t)blockIdx.x * FC_CHUNK;
+    int c = 0;
+#pragma unroll
+    for (int it = 0; it < FC_ITER; ++it) c += count16(flags16(flag, n, base + it * (FC_BS * 16) + threadIdx.x * 16));
+    int tot;
+    (void)block_excl(c, &tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+// out1: indices of set bytes; out0 (may be null): indices of the others
+__global__ __launch_bounds__(FC_BS) void k_flag_scatter(const uint8_t *flag, int64_t n, const int64_t *offs,
+                                                        int32_t *out1, int32_t *out0) {
+    const int64_t base = (int64_t)blockIdx.x * FC_CHUNK;
+    int64_t run1 = offs[blockIdx.x];
+    int64_t run0 = base - run1;   // unset bytes before the block
+    for (int it = 0; it < FC_ITER; ++it) {
+        const int64_t o = base + it * (FC_BS * 16) + threadIdx.x * 16;
+        const uint4 v = flags16(flag, n, o);
+        const int c1 = count16(v);
+        const int valid = o >= n ? 0 : (int)min<int64_t>(16, n - o);
+        int tot1, tot0;
+        int64_t p1 = run1 + block_excl(c1, &tot1);
+        int64_t p0 = run0 + block_excl(valid - c1, &tot0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        for (int j = 0; j < valid; ++j) {
+            const bool set = (w[j >> 2] >> (8 * (j & 3))) & 1u;
+            if (set)
+                out1[p1++] = (int32_t)(o + j);
+            else if (out0)
+                out0[p0++] = (int32_t)(o + j);
+        }
+        run1 += tot1;
+        run0 += tot0;
+    }
+}
+
 // Rank-table filter (the paper's Lemma 1 (2) with the table of Sec. 4.2 as
 // the source of lower-bound ranks): a non-seed pair (u, q) goes on to the
 // screen unless some column j of u has a threshold t_{u,j} >= t(u,q) whose
@@ -325,27 +389,35 @@ hipError_t q_mark_selected(const QView &v, const uint64_t *sel, const int64_t *s
     LAUNCH1D(k_mark_selected, total, v, sel, sel_off, total, flag);
     return hipGetLastError();
 }
+// flags -> ascending indices of the set bytes (out1, *count1) and, when out0
+// is not null, of the unset ones
+static hipError_t flag_compact(const uint8_t *flag, int64_t N, int32_t *out1, int64_t *count1, int32_t *out0,
+                               Scratch &sc, hipStream_t st) {
+    if (N <= 0) {
+        *count1 = 0;
+        return hipSuccess;
+    }
+    const int64_t nb = (N + FC_CHUNK - 1) / FC_CHUNK;
+    int64_t *counts = (int64_t *)sc.take(nb * 8 + 8);
+    int64_t *offs = (int64_t *)sc.take(nb * 8 + 8);
+    int64_t *dtot = (int64_t *)sc.take(16);
+    if (!counts || !offs || !dtot) return hipErrorOutOfMemory;
+    hipLaunchKernelGGL(k_flag_count, dim3((unsigned)nb), dim3(FC_BS), 0, st, flag, N, counts);
+    hipError_t e = scan_i64(counts, nb, offs, dtot, sc, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_flag_scatter, dim3((unsigned)nb), dim3(FC_BS), 0, st, flag, N, (const int64_t *)offs, out1,
+                       out0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(count1, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
 hipError_t q_compact_flags(const uint8_t *flag, int64_t N, int32_t *out, int64_t *count, Scratch &sc,
                            hipStream_t st) {
-    int64_t *excl = (int64_t *)sc.take(N * 8 + 8);
-    int64_t *dtot = (int64_t *)sc.take(16);
-    if (!excl || !dtot) return hipErrorOutOfMemory;
-    hipError_t e = scan_u8(flag, N, excl, dtot, sc, st);
-    if (e != hipSuccess) return e;
-    LAUNCH1D(k_scatter_flagged, N, flag, excl, N, out);
-    if ((e = hipMemcpyAsync(count, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    return hipStreamSynchronize(st);
+    return flag_compact(flag, N, out, count, nullptr, sc, st);
 }
 hipError_t q_split_flags(const uint8_t *flag, int64_t N, int32_t *out1, int64_t *count1, int32_t *out0,
                          hipStream_t st, Scratch &sc) {
-    int64_t *excl = (int64_t *)sc.take(N * 8 + 8);
-    int64_t *dtot = (int64_t *)sc.take(16);
-    if (!excl || !dtot) return hipErrorOutOfMemory;
-    hipError_t e = scan_u8(flag, N, excl, dtot, sc, st);
-    if (e != hipSuccess) return e;
-    LAUNCH1D(k_scatter_split, N, flag, excl, N, out1, out0);
-    if ((e = hipMemcpyAsync(count1, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    return hipStreamSynchronize(st);
+    return flag_compact(flag, N, out1, count1, out0, sc, st);
 }
 hipError_t q_zero_at(const int32_t *pids, int64_t N, uint32_t *cnt, hipStream_t st) {
     LAUNCH1D(k_zero_at, N, pids, N, cnt);

@@ -102,9 +102,6 @@ hipError_t scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *total, 
 hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st) {
     return scan_impl<int64_t>(in, n, out, total, sc, st);
 }
-hipError_t scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st) {
-    return scan_impl<uint8_t>(in, n, out, total, sc, st);
-}
 
 // ---------------------------------------------------------------------------
 // Segmented selection of the K smallest 64-bit keys (keys unique within a
