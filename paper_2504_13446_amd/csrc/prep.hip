@@ -265,8 +265,10 @@ __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
 // order, so the values equal the per-pair kernel's.  pid = u * nq + q.
 __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk,
                                                       double *t64, float *th, float *tl, float *tm) {
-    __shared__ double su[32][65];
-    __shared__ double sq[32][65];
+    // rows of 66 doubles: 16-byte aligned, so a thread's four consecutive
+    // operands are two 16-byte LDS reads
+    __shared__ __attribute__((aligned(16))) double su[32][66];
+    __shared__ __attribute__((aligned(16))) double sq[32][66];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int64_t ub = (int64_t)blockIdx.y * 64;
     const int qb = blockIdx.x * 64;
@@ -284,8 +286,9 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
         __syncthreads();
         const int kmax = min(32, d - k0);
         for (int kk = 0; kk < kmax; ++kk) {
-            double a[4], b[4];
-            for (int t = 0; t < 4; ++t) { a[t] = su[kk][ty * 4 + t]; b[t] = sq[kk][tx * 4 + t]; }
+            const double2 a01 = *(const double2 *)&su[kk][ty * 4], a23 = *(const double2 *)&su[kk][ty * 4 + 2];
+            const double2 b01 = *(const double2 *)&sq[kk][tx * 4], b23 = *(const double2 *)&sq[kk][tx * 4 + 2];
+            const double a[4] = {a01.x, a01.y, a23.x, a23.y}, b[4] = {b01.x, b01.y, b23.x, b23.y};
             for (int x = 0; x < 4; ++x)
                 for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
         }
