@@ -138,7 +138,7 @@ def test_training_and_exactness_with_estimator(lowrank):
             assert np.array_equal(ids[off[i]:off[i + 1]], wi) and np.array_equal(rk[off[i]:off[i + 1]], wr)
     print("compares without / with estimator:", s0["compares"], s1["compares"],
           "survivors:", s0["survivors"], s1["survivors"])
-    # approximate mode, verified (the screen is the judge): zero Def. 3 violations
+    # approximate mode, verified by the screen: zero Def. 3 violations
     ids, rk, off = idx.query_batch(_dev(Qte, "f32"), ks, c=1.5)
     ids = ids.cpu().numpy()
     for i in range(Qte.shape[0]):
