@@ -463,15 +463,32 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                     acc[ib][ub] = mfma_step<SK>(acc[ib][ub], af, bfrag[ub][s], pscale[ib], uscale[ub]);
             }
         }
+        {
+            // Issue order of the block above: PIPE fragment reads in flight
+            // ahead of the matrix-core instructions that consume them (left
+            // alone, the scheduler waits for every read right before its use).
+            constexpr int NRD = NKS * NIB;
+            constexpr int RPF = sizeof(FT) >= 16 ? (int)sizeof(FT) / 16 : 1;   // LDS reads per fragment
+            constexpr int PIPE = NRD < 4 ? NRD : 4;
+            __builtin_amdgcn_sched_group_barrier(0x100, PIPE * RPF, 0);
+#pragma unroll
+            for (int i = 0; i < NRD - PIPE; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, NUB, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, RPF, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, PIPE * NUB, 0);
+        }
         // items past the end never count: make their scores -inf
         const int64_t item0 = st * (NIB * 32);
         if (item0 + NIB * 32 > a.m) {
+            // item - item0 is a constant per register plus 4 * half: compare
+            // the constant part with one per-lane limit
+            const int lim = (int)(a.m - item0) - 4 * half;
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                    if (item >= a.m) {
+                    if (ib * 32 + 8 * (r >> 2) + (r & 3) >= lim) {
 #pragma unroll
                         for (int ub = 0; ub < NUB; ++ub) acc[ib][ub][r] = -__builtin_inff();
                     }

@@ -211,7 +211,8 @@ hipError_t launch_select(const uint64_t *keys, const int64_t *seg_off, const int
 // ---------------------------------------------------------------------------
 // Task-set builder.  Input: pids[N], ascending (hence grouped by user, since
 // pairs are numbered user-major).  Output (TaskSet): one task per distinct
-// user, its entry list in block-interleaved layout.
+// user, its entry list in block-interleaved layout.  Screening tasks stay in
+// user order; exact tasks are grouped by list length (see k_task_permute).
 // ---------------------------------------------------------------------------
 __global__ void k_user_change(const int32_t *pids, int64_t N, const int32_t *pair_u, int32_t *flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,6 +242,27 @@ __global__ void k_task_len(const int64_t *task_start, int64_t ntask, int64_t N, 
         len[t] = 0;
         task_user[t] = -1;
     }
+}
+
+// Exact passes: tasks with several entries first, then the single-entry
+// tasks, each group in user order.  A wave scans as long as its longest list and the waves of a
+// workgroup meet at every step's barrier, so a few users with several pairs
+// spread over many waves would hold all of them back.
+__global__ void k_multi_flag(const int32_t *len, int64_t ntask, int32_t *multi) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask) return;
+    multi[t] = len[t] > 1 ? 1 : 0;
+}
+
+__global__ void k_task_permute(const int64_t *start_in, const int32_t *user_in, const int32_t *len_in,
+                               const int32_t *multi, const int64_t *mex, const int64_t *nmulti, int64_t ntask,
+                               int64_t *start_out, int32_t *user_out, int32_t *len_out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask) return;
+    const int64_t pos = multi[t] ? mex[t] : nmulti[0] + t - mex[t];
+    start_out[pos] = start_in[t];
+    user_out[pos] = user_in[t];
+    len_out[pos] = len_in[t];
 }
 
 __global__ void k_block_cap(const int32_t *len, int64_t nblk, int64_t *cap32) {
@@ -338,6 +360,22 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
                        task_start, ts.task_user);
     hipLaunchKernelGGL(k_task_len, dim3(nblocks(ntask_pad, 256)), dim3(256), 0, st, task_start, ntask, N,
                        ntask_pad, ts.task_user, ts.len);
+    if (!bound && ntask > 32) {
+        int32_t *multi = (int32_t *)sc.take(ntask * 4);
+        int64_t *mex = (int64_t *)sc.take(ntask * 8);
+        int64_t *nmulti = (int64_t *)sc.take(16);
+        int64_t *start2 = (int64_t *)sc.take((ntask + 1) * 8);
+        int32_t *user0 = (int32_t *)sc.take(ntask * 4);
+        int32_t *len0 = (int32_t *)sc.take(ntask * 4);
+        if (!multi || !mex || !nmulti || !start2 || !user0 || !len0) return hipErrorOutOfMemory;
+        hipLaunchKernelGGL(k_multi_flag, dim3(nblocks(ntask, 256)), dim3(256), 0, st, ts.len, ntask, multi);
+        if ((e = scan_i32(multi, ntask, mex, nmulti, sc, st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(user0, ts.task_user, ntask * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(len0, ts.len, ntask * 4, hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_task_permute, dim3(nblocks(ntask, 256)), dim3(256), 0, st, task_start, user0, len0,
+                           multi, mex, nmulti, ntask, start2, ts.task_user, ts.len);
+        task_start = start2;
+    }
     hipLaunchKernelGGL(k_block_cap, dim3(nblocks(nblk, 256)), dim3(256), 0, st, ts.len, nblk, cap32);
     if ((e = scan_i64(cap32, nblk, ts.blk_base, dtot, sc, st)) != hipSuccess) return e;
     int64_t cap_total = 0;
