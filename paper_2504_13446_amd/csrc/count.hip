@@ -633,8 +633,19 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                         for (int r = 0; r < 16; ++r)
                             pmask |= (acc[ib][ub][r] > tmv) ? (1u << (ib * 16 + r)) : 0u;
                     const uint32_t nu = __popc(umask);
-                    const uint32_t incl = wave_incl_scan(nu, lane);
-                    const uint32_t total = __shfl(incl, 63, 64);
+                    // record offsets: with at most one record per lane (the
+                    // usual case) they are the lane's rank among the lanes
+                    // that have one; otherwise a prefix sum over the wave
+                    uint32_t incl, total;
+                    const uint64_t has = __ballot(nu != 0);
+                    if (__ballot(nu > 1) == 0ull) {
+                        incl = __builtin_amdgcn_mbcnt_hi((uint32_t)(has >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)has, 0u)) + nu;
+                        total = (uint32_t)__popcll(has);
+                    } else {
+                        incl = wave_incl_scan(nu, lane);
+                        total = __shfl(incl, 63, 64);
+                    }
                     if (rb_n + (int)total > REC_PER_WAVE) flush_records();
                     auto put = [&](auto &&store) {
                         uint32_t mm = umask;
