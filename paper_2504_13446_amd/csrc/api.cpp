@@ -173,6 +173,7 @@ struct rkr_index {
         candkeys, ans, seedpid, surv, emit, ctr, bound, seedkth, kdev, sdev, cdev, segoff, seloff, bestoff,
         candoff, cursor, qcount, flags, allpid, keep;
     TaskSet ts_screen, ts_screen2, ts_exact;
+    DBuf sp_len, sp_pid, sp_th, sp_cnt;   // per-split lists of a split screen phase
     // rank table (Sec. 4.2): [n][TABLE_COLS] FP64 thresholds, their FP32
     // round-ups, and certain counts over all of P
     DBuf tab_t, tab_th, tab_cnt;
@@ -320,7 +321,7 @@ extern "C" void rkr_destroy(rkr_index *x) {
                     &x->tm, &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
                     &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
-                    &x->qcount, &x->flags, &x->allpid};
+                    &x->qcount, &x->flags, &x->allpid, &x->sp_len, &x->sp_pid, &x->sp_th, &x->sp_cnt};
     for (DBuf *b : bufs) b->release();
     x->ts_screen.release();
     x->ts_screen2.release();
@@ -765,7 +766,8 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         // quarter or so of P, then users die fast; after a phase whose end
         // leaves fewer than half of the current tasks live, the live pairs are
         // compacted, with their remaining budgets, into a new dense task set,
-        // so that later steps run only tiles of live users.
+        // so that later steps run only tiles of live users.  A phase with
+        // fewer tiles than compute units is split over item ranges.
         static const int kPhaseEnd32[] = {9, 10, 11, 12, 14, 16, 20, 32};   // in 32nds of the scan
         HIPCK(ensure_events(x));
         TaskSet *cur = &x->ts_screen, *nxt = &x->ts_screen2;
@@ -781,19 +783,52 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
             a.step0 = s0;
             a.step_end = s1;
             a.steps_per_split = s1 - s0;
-            if (persistent) {
+            const int64_t tiles = (cur->ntask + tpw - 1) / tpw;
+            // Too few tiles of live users to fill the device: split the phase
+            // over item ranges (a grid launch, whatever the candidate), each
+            // split on its own copy of the lists (entry offsets stay 32-bit),
+            // and merge the copies afterwards.
+            const bool pers_phase = persistent && tiles >= x->num_cus;
+            int64_t nsplit = 1;
+            if (tiles < x->num_cus) {
+                nsplit = std::min<int64_t>(pick_nsplit(tiles, s1 - s0, x->num_cus), 16);
+                while (nsplit > 1 && cur->cap_total * nsplit >= ((int64_t)1 << 30)) --nsplit;
+                if (nsplit > 1) {
+                    a.steps_per_split = (s1 - s0 + nsplit - 1) / nsplit;
+                    nsplit = (s1 - s0 + a.steps_per_split - 1) / a.steps_per_split;
+                }
+            }
+            if (nsplit > 1) {
+                const int64_t cap = cur->cap_total, ntp = cur->ntask_pad;
+                HIPCK(x->sp_len.ensure(ntp * nsplit * 4));
+                HIPCK(x->sp_pid.ensure(cap * nsplit * 4));
+                HIPCK(x->sp_th.ensure(cap * nsplit * 4));
+                HIPCK(x->sp_cnt.ensure(cap * nsplit * 4));
+                HIPCK(q_replicate_u32((const uint32_t *)cur->len, ntp, x->sp_len.as<uint32_t>(), (int)nsplit, st));
+                HIPCK(q_replicate_u32((const uint32_t *)cur->ent_pid, cap, x->sp_pid.as<uint32_t>(), (int)nsplit, st));
+                HIPCK(q_replicate_u32((const uint32_t *)cur->ent_th, cap, x->sp_th.as<uint32_t>(), (int)nsplit, st));
+                HIPCK(q_replicate_u32(cur->ent_cnt, cap, x->sp_cnt.as<uint32_t>(), (int)nsplit, st));
+                a.ent_len = x->sp_len.as<int32_t>();
+                a.len_stride = ntp;
+                a.ent_pid = x->sp_pid.as<int32_t>();
+                a.ent_th = x->sp_th.as<float>();
+                a.ent_cnt = x->sp_cnt.as<uint32_t>();
+            }
+            if (pers_phase) {
                 HIPCK(launch_fill_u32(x->ctr.as<uint32_t>() + 8, 0, 2, st));
                 a.tile_counter = x->ctr.as<unsigned long long>() + 4;
                 a.persistent_ctas = x->num_cus;
             }
             HIPCK(hipEventRecord(x->ev[0], st));
-            HIPCK(launch_count(x->sk, CM_SCREEN, a, 1, variant, st));
+            HIPCK(launch_count(x->sk, CM_SCREEN, a, (int)nsplit, variant, st));
             HIPCK(hipEventRecord(x->ev[1], st));
+            if (nsplit > 1)
+                HIPCK(q_screen_merge(*cur, (int)nsplit, x->sp_len.as<int32_t>(), x->sp_pid.as<int32_t>(),
+                                     x->sp_cnt.as<uint32_t>(), st));
             HIPCK(hipStreamSynchronize(st));
             ms_kernel += event_ms(x->ev[0], x->ev[1]);
-            const int64_t tiles = (cur->ntask + tpw - 1) / tpw;
             x->stats.screen_ctas = std::max<int64_t>(x->stats.screen_ctas,
-                                                     persistent ? std::min<int64_t>(x->num_cus, tiles) : tiles);
+                                                     pers_phase ? std::min<int64_t>(x->num_cus, tiles) : tiles * nsplit);
             s0 = s1;
             if (s0 >= nsteps) break;
             int64_t nlive = 0;

@@ -22,7 +22,10 @@
 // Screen mode counts only certain-above scores and drops a pair as soon as
 // 1 + count exceeds the query's bound B[q] (a proven upper bound on the k-th
 // smallest rank): its rank is then > B >= R_k, so it cannot be in the answer
-// (Def. 2), the counts only grow.  This is the paper's Lemma 1 (2) filter
+// (Def. 2), the counts only grow.  A screen split over item ranges (blockIdx.y)
+// gives every split its own copy of the lists; a split's partial count above
+// the budget already proves the pair out, and the host merges the splits'
+// lists after the launch.  This is the paper's Lemma 1 (2) filter
 // applied to exact partial counts.  A screen entry holds (pid, th, rem) with
 // rem = B[q] - 1 - count: the pair dies when rem turns negative; survivors are
 // compacted to the front of the user's list every step.  With enough live
@@ -191,8 +194,10 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             ebase[ub] = 0;
         } else {
             u = (t < a.ntask) ? a.task_user[t] : -1;
-            len[ub] = (u >= 0) ? a.ent_len[t] : 0;
+            len[ub] = (u >= 0) ? a.ent_len[split * a.len_stride + t] : 0;
             ebase[ub] = a.blk_base[t >> 5] + l32;
+            // a split screen works on its own copy of the lists
+            if constexpr (MODE == CM_SCREEN) ebase[ub] += (int64_t)split * a.cap_total;
         }
         uid[ub] = u;
         un_hat[ub] = un_del[ub] = un_full[ub] = 0.0;
@@ -755,7 +760,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     for (int ub = 0; ub < NUB; ++ub) {
         if (uid[ub] < 0) continue;
         if constexpr (MODE == CM_SCREEN) {
-            if (half == 0) a.ent_len[tix[ub]] = len[ub];
+            if (half == 0) a.ent_len[split * a.len_stride + tix[ub]] = len[ub];
         } else if constexpr (MODE == CM_TABLE) {
             // both lanes of a pair hold the same user: sum their halves
 #pragma unroll

@@ -43,6 +43,13 @@ hipError_t q_split_flags(const uint8_t *flag, int64_t N, int32_t *out1, int64_t 
 // also each pair's remaining budget at rem_out[pid]
 hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, int64_t *count, Scratch &sc,
                        hipStream_t st, uint32_t *rem_out = nullptr);
+// dst[s * n + i] = src[i] for s < ns (the per-split copies of a split screen)
+hipError_t q_replicate_u32(const uint32_t *src, int64_t n, uint32_t *dst, int ns, hipStream_t st);
+// after a screen split ns ways (ns <= 16) over item ranges: keep the pairs
+// every split kept whose summed partial counts stay within the budget, with
+// the budget left (sp_*: the splits' lists, [ns][ntask_pad] and [ns][cap_total])
+hipError_t q_screen_merge(TaskSet &ts, int ns, const int32_t *sp_len, const int32_t *sp_pid,
+                          const uint32_t *sp_rem, hipStream_t st);
 // number of tasks whose list is not empty
 hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, int64_t *count, hipStream_t st);
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,

@@ -449,6 +449,79 @@ hipError_t q_survivors(const TView &t, const uint8_t *seedflag, int32_t *out, in
     LAUNCH1D(k_surv_write, t.ntask, t, seedflag, off, out, rem_out);
     return hipGetLastError();
 }
+// dst[s * n + i] = src[i] for s < ns
+__global__ void k_replicate_u32(const uint32_t *src, int64_t n, uint32_t *dst, int ns) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = src[i];
+    for (int s = 0; s < ns; ++s) dst[(int64_t)s * n + i] = v;
+}
+
+// Merge of a split screen, one thread per task.  Every split started from the
+// task's list (pid, th, rem0) and kept, in order, the entries its own items
+// did not rule out, with rem_s = rem0 - (its partial count).  A pair lives on
+// iff every split kept it and rem0 - (sum of the partial counts) =
+// sum_s rem_s - (ns - 1) rem0 is not negative; the live entries are written
+// back, in order, over the task's list with that remaining budget.
+constexpr int MERGE_MAX_SPLITS = 16;
+__global__ void k_screen_merge(int64_t ntask, const int64_t *blk_base, int64_t cap_total, int64_t len_stride,
+                               int ns, int32_t *len, int32_t *pid, float *th, uint32_t *rem,
+                               const int32_t *sp_len, const int32_t *sp_pid, const uint32_t *sp_rem) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask) return;
+    const int L = len[t];
+    if (L == 0) return;
+    const int64_t base = blk_base[t >> 5] + (t & 31);
+    int ptr[MERGE_MAX_SPLITS], lsz[MERGE_MAX_SPLITS];
+#pragma unroll
+    for (int s = 0; s < MERGE_MAX_SPLITS; ++s) {
+        ptr[s] = 0;
+        lsz[s] = s < ns ? sp_len[(int64_t)s * len_stride + t] : 0;
+    }
+    int w = 0;
+    for (int i = 0; i < L; ++i) {
+        const int64_t e = base + (int64_t)i * 32;
+        const int32_t p = pid[e];
+        const int64_t rem0 = (int32_t)rem[e];
+        const float h = th[e];
+        bool alive = true;
+        int64_t sum = 0;
+#pragma unroll
+        for (int s = 0; s < MERGE_MAX_SPLITS; ++s) {
+            if (s < ns) {
+                const int64_t es = (int64_t)s * cap_total + base + (int64_t)ptr[s] * 32;
+                if (ptr[s] < lsz[s] && sp_pid[es] == p) {
+                    sum += (int32_t)sp_rem[es];
+                    ++ptr[s];
+                } else {
+                    alive = false;
+                }
+            }
+        }
+        const int64_t r = sum - (int64_t)(ns - 1) * rem0;
+        if (alive && r >= 0) {
+            const int64_t ew = base + (int64_t)w * 32;
+            pid[ew] = p;
+            th[ew] = h;
+            rem[ew] = (uint32_t)r;
+            ++w;
+        }
+    }
+    len[t] = w;
+}
+
+hipError_t q_replicate_u32(const uint32_t *src, int64_t n, uint32_t *dst, int ns, hipStream_t st) {
+    LAUNCH1D(k_replicate_u32, n, src, n, dst, ns);
+    return hipGetLastError();
+}
+hipError_t q_screen_merge(TaskSet &ts, int ns, const int32_t *sp_len, const int32_t *sp_pid,
+                          const uint32_t *sp_rem, hipStream_t st) {
+    if (ns < 1 || ns > MERGE_MAX_SPLITS) return hipErrorInvalidValue;
+    LAUNCH1D(k_screen_merge, ts.ntask, ts.ntask, ts.blk_base, ts.cap_total, ts.ntask_pad, ns, ts.len, ts.ent_pid,
+             ts.ent_th, ts.ent_cnt, sp_len, sp_pid, sp_rem);
+    return hipGetLastError();
+}
+
 hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, int64_t *count, hipStream_t st) {
     *count = 0;
     hipError_t e = launch_fill_u32((uint32_t *)dev, 0, 2, st);

@@ -79,10 +79,12 @@ struct CountArgs {
     const int32_t *task_user;     // [ntask_pad] user id, -1 for padding
     int64_t ntask;                // real tasks (ntask_pad is a multiple of 512)
     const int64_t *blk_base;
-    int32_t *ent_len;             // [ntask_pad]
+    int32_t *ent_len;             // [ntask_pad]; split screens: [nsplit][len_stride]
+    int64_t len_stride;           // split screens: each split's own lists (0: one copy)
     int32_t *ent_pid;
     int32_t *ent_q;
     uint32_t *ent_cnt;            // exact: [nsplit][cap_total] counts; screen: remaining budget
+                                  // (split screens: pid, th and cnt are [nsplit][cap_total] too)
     float *ent_th;                // FP32 value >= the FP64 threshold
     float *ent_tl;                // FP32 value <= the FP64 threshold
     const float *ent_tm;          // fl32 of the FP64 threshold (plain verdict of near ties)
