@@ -362,6 +362,35 @@ __global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, cons
     keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
 }
 
+// The same filter on a dense batch (pair u * nq + q): one workgroup per user
+// and up to 256 queries reads the user's row of thresholds and counts into
+// LDS once; the number of columns with t_{u,j} >= t is counted directly.
+__global__ __launch_bounds__(256) void k_table_keep_dense(int nq, const double *t64, const uint8_t *seedflag,
+                                                          const int32_t *bound, const double *tab_t,
+                                                          const uint32_t *tab_cnt, uint8_t *keep) {
+    __shared__ double srow[TABLE_COLS];
+    __shared__ uint32_t scnt[TABLE_COLS];
+    const int64_t u = blockIdx.x;
+    const int q = (int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x;
+    if (threadIdx.x < TABLE_COLS) {
+        srow[threadIdx.x] = tab_t[u * TABLE_COLS + threadIdx.x];
+        scnt[threadIdx.x] = tab_cnt[u * TABLE_COLS + threadIdx.x];
+    }
+    __syncthreads();
+    if (q >= nq) return;
+    const int64_t i = u * nq + q;
+    if (seedflag[i]) {
+        keep[i] = 0;
+        return;
+    }
+    const double t = t64[i];
+    int L = 0;
+#pragma unroll
+    for (int j = 0; j < TABLE_COLS; ++j) L += srow[j] >= t ? 1 : 0;
+    const uint32_t best = L > 0 ? scnt[L - 1] : 0u;
+    keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
+}
+
 // out[i] = the smallest float >= x[i]
 __global__ void k_round_up_f32(const double *x, int64_t n, float *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -571,8 +600,16 @@ hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream
 
 hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
                         const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st) {
-    LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, ps.dense ? ps.nq : 0, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound,
-             tab_t, tab_cnt, keep);
+    if (ps.dense && ps.nq > 0) {
+        const int64_t n = ps.npairs / ps.nq;
+        const int bs = ps.nq >= 192 ? 256 : (ps.nq + 63) / 64 * 64;
+        if (n > 0)
+            hipLaunchKernelGGL(k_table_keep_dense, dim3((unsigned)n, (unsigned)((ps.nq + bs - 1) / bs)), dim3(bs), 0,
+                               st, ps.nq, ps.t64, seedflag, bound, tab_t, tab_cnt, keep);
+        return hipGetLastError();
+    }
+    LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, 0, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound, tab_t, tab_cnt,
+             keep);
     return hipGetLastError();
 }
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st) {

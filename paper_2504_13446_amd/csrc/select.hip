@@ -109,6 +109,7 @@ hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, 
 // ---------------------------------------------------------------------------
 constexpr int SEL_BS = 1024;
 constexpr int SEL_MAX = 4096;
+constexpr int SEL_UNROLL = 8;
 
 __device__ inline void lds_bitonic_sort(uint64_t *s, int npow2) {
     for (int k = 2; k <= npow2; k <<= 1) {
@@ -154,9 +155,18 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
             for (int i = tid; i < 16 * 256; i += SEL_BS) (&hist[0][0])[i] = 0;
             __syncthreads();
             const uint64_t pre = sh_prefix, msk = sh_mask;
-            for (int64_t i = tid; i < len; i += SEL_BS) {
-                uint64_t v = x[i];
-                if ((v & msk) == pre) atomicAdd(&hist[wave][(v >> shift) & 255], 1u);
+            // SEL_UNROLL independent loads in flight per thread
+            for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * SEL_UNROLL) {
+                uint64_t v[SEL_UNROLL];
+#pragma unroll
+                for (int r = 0; r < SEL_UNROLL; ++r) {
+                    const int64_t i = i0 + (int64_t)r * SEL_BS;
+                    v[r] = i < len ? x[i] : 0ull;
+                }
+#pragma unroll
+                for (int r = 0; r < SEL_UNROLL; ++r)
+                    if (i0 + (int64_t)r * SEL_BS < len && (v[r] & msk) == pre)
+                        atomicAdd(&hist[wave][(v[r] >> shift) & 255], 1u);
             }
             __syncthreads();
             if (tid < 256) {
@@ -184,11 +194,19 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
     }
     if (tid == 0) sh_cnt = 0;
     __syncthreads();
-    for (int64_t i = tid; i < len; i += SEL_BS) {
-        uint64_t v = x[i];
-        if (v <= T) {
-            uint32_t p = atomicAdd(&sh_cnt, 1u);
-            if (p < SEL_MAX) s[p] = v;
+    for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * SEL_UNROLL) {
+        uint64_t v[SEL_UNROLL];
+#pragma unroll
+        for (int r = 0; r < SEL_UNROLL; ++r) {
+            const int64_t i = i0 + (int64_t)r * SEL_BS;
+            v[r] = i < len ? x[i] : ~0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < SEL_UNROLL; ++r) {
+            if (i0 + (int64_t)r * SEL_BS < len && v[r] <= T) {
+                uint32_t p = atomicAdd(&sh_cnt, 1u);
+                if (p < SEL_MAX) s[p] = v[r];
+            }
         }
     }
     __syncthreads();
