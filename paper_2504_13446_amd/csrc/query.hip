@@ -362,33 +362,51 @@ __global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, cons
     keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
 }
 
-// The same filter on a dense batch (pair u * nq + q): one workgroup per user
-// and up to 256 queries reads the user's row of thresholds and counts into
-// LDS once; the number of columns with t_{u,j} >= t is counted directly.
-__global__ __launch_bounds__(256) void k_table_keep_dense(int nq, const double *t64, const uint8_t *seedflag,
-                                                          const int32_t *bound, const double *tab_t,
-                                                          const uint32_t *tab_cnt, uint8_t *keep) {
-    __shared__ double srow[TABLE_COLS];
-    __shared__ uint32_t scnt[TABLE_COLS];
-    const int64_t u = blockIdx.x;
+// The same filter on a dense batch (pair u * nq + q): one workgroup per
+// TK_USERS users and up to 256 queries.  The pair loads are issued first, then
+// the users' rows of thresholds and counts go through LDS; the number of
+// columns with t_{u,j} >= t is counted directly.
+constexpr int TK_USERS = 4;
+__global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, const double *t64,
+                                                          const uint8_t *seedflag, const int32_t *bound,
+                                                          const double *tab_t, const uint32_t *tab_cnt,
+                                                          uint8_t *keep) {
+    __shared__ double srow[TK_USERS][TABLE_COLS];
+    __shared__ uint32_t scnt[TK_USERS][TABLE_COLS];
+    const int64_t u0 = (int64_t)blockIdx.x * TK_USERS;
     const int q = (int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x;
-    if (threadIdx.x < TABLE_COLS) {
-        srow[threadIdx.x] = tab_t[u * TABLE_COLS + threadIdx.x];
-        scnt[threadIdx.x] = tab_cnt[u * TABLE_COLS + threadIdx.x];
+    double t[TK_USERS];
+    uint8_t sf[TK_USERS];
+#pragma unroll
+    for (int k = 0; k < TK_USERS; ++k) {
+        const bool ok = q < nq && u0 + k < n;
+        t[k] = ok ? t64[(u0 + k) * nq + q] : 0.0;
+        sf[k] = ok ? seedflag[(u0 + k) * nq + q] : (uint8_t)1;
+    }
+    const int32_t B = q < nq ? bound[q] : 0;
+    if (threadIdx.x < TK_USERS * TABLE_COLS) {
+        const int k = threadIdx.x / TABLE_COLS, j = threadIdx.x % TABLE_COLS;
+        if (u0 + k < n) {
+            srow[k][j] = tab_t[(u0 + k) * TABLE_COLS + j];
+            scnt[k][j] = tab_cnt[(u0 + k) * TABLE_COLS + j];
+        }
     }
     __syncthreads();
     if (q >= nq) return;
-    const int64_t i = u * nq + q;
-    if (seedflag[i]) {
-        keep[i] = 0;
-        return;
-    }
-    const double t = t64[i];
-    int L = 0;
 #pragma unroll
-    for (int j = 0; j < TABLE_COLS; ++j) L += srow[j] >= t ? 1 : 0;
-    const uint32_t best = L > 0 ? scnt[L - 1] : 0u;
-    keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
+    for (int k = 0; k < TK_USERS; ++k) {
+        if (u0 + k >= n) break;
+        const int64_t i = (u0 + k) * nq + q;
+        if (sf[k]) {
+            keep[i] = 0;
+            continue;
+        }
+        int L = 0;
+#pragma unroll
+        for (int j = 0; j < TABLE_COLS; ++j) L += srow[k][j] >= t[k] ? 1 : 0;
+        const uint32_t best = L > 0 ? scnt[k][L - 1] : 0u;
+        keep[i] = (int64_t)best >= (int64_t)B ? 0 : 1;
+    }
 }
 
 // out[i] = the smallest float >= x[i]
@@ -602,10 +620,12 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
                         const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st) {
     if (ps.dense && ps.nq > 0) {
         const int64_t n = ps.npairs / ps.nq;
-        const int bs = ps.nq >= 192 ? 256 : (ps.nq + 63) / 64 * 64;
+        // at least TK_USERS * TABLE_COLS threads: they stage the rows
+        const int bs = ps.nq >= 192 ? 256 : 128;
         if (n > 0)
-            hipLaunchKernelGGL(k_table_keep_dense, dim3((unsigned)n, (unsigned)((ps.nq + bs - 1) / bs)), dim3(bs), 0,
-                               st, ps.nq, ps.t64, seedflag, bound, tab_t, tab_cnt, keep);
+            hipLaunchKernelGGL(k_table_keep_dense, dim3((unsigned)((n + TK_USERS - 1) / TK_USERS),
+                                                        (unsigned)((ps.nq + bs - 1) / bs)),
+                               dim3(bs), 0, st, n, ps.nq, ps.t64, seedflag, bound, tab_t, tab_cnt, keep);
         return hipGetLastError();
     }
     LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, 0, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound, tab_t, tab_cnt,
