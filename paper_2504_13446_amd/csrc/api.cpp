@@ -762,13 +762,15 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         const int cand = x->tuner.pick(key, 2 * ntv);
         const int variant = cand % ntv;
         const bool persistent = cand >= ntv;
-        // The scan runs in phases.  Every user stays live through the first
-        // quarter or so of P, then users die fast; after a phase whose end
-        // leaves fewer than half of the current tasks live, the live pairs are
-        // compacted, with their remaining budgets, into a new dense task set,
-        // so that later steps run only tiles of live users.  A phase with
-        // fewer tiles than compute units is split over item ranges.
-        static const int kPhaseEnd32[] = {9, 10, 11, 12, 14, 16, 20, 32};   // in 32nds of the scan
+        // The scan runs in phases.  Without the rank table every user stays
+        // live through the first quarter or so of P, then users die fast;
+        // after the table most pairs die within the first tenth.  After a
+        // phase whose end leaves fewer than half of the current tasks live,
+        // the live pairs are compacted, with their remaining budgets, into a
+        // new dense task set, so that later steps run only tiles of live
+        // users.  A phase with fewer tiles than compute units is split over
+        // item ranges.
+        static const int kPhaseEnd32[] = {3, 6, 9, 12, 16, 20, 32};   // in 32nds of the scan
         HIPCK(ensure_events(x));
         TaskSet *cur = &x->ts_screen, *nxt = &x->ts_screen2;
         const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
