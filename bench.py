@@ -63,7 +63,7 @@ def screen_traffic(key: dict, candidate: int):
     sources differ from the ones it was taken on."""
     try:
         rec = json.load(open(TRAFFIC))
-        if rec["workload_key"] != key or rec["screen_candidate"] != candidate:
+        if rec["workload_key"] != key or candidate not in rec.get("screen_candidates", [rec["screen_candidate"]]):
             return None
         for path, digest in rec["sources_sha256"].items():
             if code_digest(os.path.join(ROOT, path)) != digest:
