@@ -116,7 +116,7 @@ __device__ inline void stage_step(const uint8_t *src, uint8_t *dst, int step_byt
 }
 
 // LDS stages of P: the exact and table passes (little work per step) keep up
-// to four steps in flight, screening (long steps) double-buffers.  150 KB of LDS at most.
+// to five stages, screening (long steps) double-buffers.  150 KB of LDS at most.
 // Exact passes also keep a near-tie record buffer per wave in LDS: records
 // are appended there and copied out with one global atomic per flush.
 constexpr int REC_PER_WAVE = 256;
@@ -128,7 +128,7 @@ template <int MODE>
 constexpr int stage_buffers(int step_bytes) {
     if (MODE == CM_SCREEN) return 2;
     const int nb = (153600 - record_bytes<MODE>()) / step_bytes;
-    return nb < 2 ? 2 : (nb > 4 ? 4 : nb);
+    return nb < 2 ? 2 : (nb > 5 ? 5 : nb);
 }
 // Staging loads the last wave of a workgroup issues per step (the fewest of
 // any wave): a lower bound on the vector-memory operations a step's staging
@@ -161,9 +161,16 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     constexpr int step_bytes = STEP_BYTES_MAX;
     constexpr int STAGE = STEP_BYTES_MAX + 32;     // P tile + the step's coefficients
     constexpr int NBUF = stage_buffers<MODE>(STAGE);
-    // when step st + 1 must have landed, the staging of at most NBUF - 2 later
-    // steps (each >= LOADS_MIN operations) may still be in flight
-    constexpr int WAIT_N = (NBUF - 2) * stage_loads_min(STEP_BYTES_MAX);
+    // Screening stages the next step and meets at a barrier after every step.
+    // Exact and table passes with four or more stages stage PF = NBUF - 2
+    // steps ahead and meet after every second step: step st writes the stage
+    // of step st - 2, which every wave has left by then (a barrier follows
+    // st - 2 or st - 1), and at a barrier the next two steps have landed.
+    constexpr bool SYNC2 = MODE != CM_SCREEN && NBUF >= 4;
+    constexpr int PF = SYNC2 ? NBUF - 2 : NBUF - 1;
+    // at a barrier, the staging of at most this many later operations may
+    // still be in flight (each step adds >= stage_loads_min per wave)
+    constexpr int WAIT_N = (SYNC2 ? PF - 2 : PF - 1) * stage_loads_min(STEP_BYTES_MAX);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -376,13 +383,13 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
     if (!__syncthreads_or(any_live) || s_begin >= s_end) return;
 
-    // ---- prologue: stage the first NBUF - 1 steps (direct global -> LDS, 16
-    // bytes per lane); wait for the first
-    const int64_t npro = std::min<int64_t>(NBUF - 1, s_end - s_begin);
+    // ---- prologue: stage the first PF steps (direct global -> LDS, 16 bytes
+    // per lane); wait for the first (the first two with SYNC2)
+    const int64_t npro = std::min<int64_t>(PF, s_end - s_begin);
     for (int64_t k = 0; k < npro; ++k)
         stage_step<LOADS_MAX>(a.plp + (s_begin + k) * (int64_t)step_bytes, lds + k * STAGE, step_bytes, tid,
                               a.step_coef + 4 * (s_begin + k));
-    if (s_begin + NBUF - 2 < s_end)
+    if (npro == PF)
         wait_vm<WAIT_N>();
     else
         wait_vm<0>();
@@ -426,10 +433,10 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
 #pragma unroll
             for (int ub = 0; ub < NUB; ++ub) fetch_first(ub);
         }
-        if (st + NBUF - 1 < s_end) {
-            const int pb = cbuf + NBUF - 1 >= NBUF ? cbuf - 1 : cbuf + NBUF - 1;
-            stage_step<LOADS_MAX>(a.plp + (st + NBUF - 1) * (int64_t)step_bytes, lds + pb * STAGE, step_bytes,
-                                  tid, a.step_coef + 4 * (st + NBUF - 1));
+        if (st + PF < s_end) {
+            const int pb = cbuf + PF >= NBUF ? cbuf + PF - NBUF : cbuf + PF;
+            stage_step<LOADS_MAX>(a.plp + (st + PF) * (int64_t)step_bytes, lds + pb * STAGE, step_bytes,
+                                  tid, a.step_coef + 4 * (st + PF));
         }
         if constexpr (MODE == CM_SCREEN) {
             if (late && have_prev) {
@@ -717,13 +724,14 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
 
         have_prev = late;
-        // step st + 1 has landed (same-wave entry stores stay ordered before
-        // the next step's loads of the same slots)
-        if (st + NBUF - 1 < s_end)
+        cbuf = cbuf + 1 == NBUF ? 0 : cbuf + 1;
+        if (SYNC2 && ((st - s_begin) & 1) == 0) continue;
+        // step st + 1 (with SYNC2, st + 2 too) has landed (same-wave entry
+        // stores stay ordered before the next step's loads of the same slots)
+        if (st + PF < s_end)
             wait_vm<WAIT_N>();
         else
             wait_vm<0>();
-        cbuf = cbuf + 1 == NBUF ? 0 : cbuf + 1;
         int live = 0;
 #pragma unroll
         for (int ub = 0; ub < NUB; ++ub) live |= (len[ub] > 0);
