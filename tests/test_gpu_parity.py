@@ -138,6 +138,23 @@ def test_bf16_masters_batch():
     idx.close()
 
 
+@pytest.mark.parametrize("masters", ["bf16", "f32"])
+def test_batch_of_many_queries(masters):
+    """A dense batch of 80 queries (a full 64-query threshold tile and a
+    ragged one) over a dimension that is not a multiple of 32: exact answers
+    equal the oracle's, with and without the rank table."""
+    w = W.make("batch", n=3000, m=4000, d=45, nq=80)
+    ks = np.array([(7 * i) % 40 + 1 for i in range(80)], np.int32)
+    R = O.ranks(w.U, w.P, w.Qv)
+    # the generator's BF16 bits, widened exactly for FP32 masters
+    wide = (lambda x: (x.astype(np.uint32) << 16).view(np.float32)) if masters == "f32" else (lambda x: x)
+    for table in (0, 512):
+        idx = rkr.Index(_dev(wide(w.U), masters), _dev(wide(w.P), masters), score="bf16", rank_table=table)
+        ans = _answers(*idx.query_batch(_dev(wide(w.Qv), masters), ks))
+        _check_exact(R, ans, ks)
+        idx.close()
+
+
 def test_single_lowrank_scaled_all_ranks():
     w = W.make("single", n=12000, m=9000)
     idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16")
