@@ -165,6 +165,27 @@ rkr_status rkr_query_approx(rkr_index *idx, const void *q, int32_t k, double c,
                             int32_t *ids_out, int32_t *rank_ub_out);
 
 /*
+ * The paper's own query on the rank table (Sec. 4.3, steps 1-3) for one query
+ * q [device, d, master dtype], c >= 1; the index must hold a rank table.
+ * Step 1: with L = the number of the user's columns whose threshold is at or
+ * above u.q (columns descend), the rank is bracketed by r_lo = 1 + cell[L-1]
+ * (1 when L = 0) and r_hi = 1 + cell[L] (1 + m when L = RKR_TABLE_COLS);
+ * R_lo_k, R_hi_k are the k-th smallest of each.  Step 2: if c R_lo_k >= R_hi_k
+ * the answer is the k users of smallest r_hi; otherwise the users with
+ * r_hi <= c R_lo_k come first, users with r_lo > R_hi_k are ruled out (Lemma 1
+ * (2)), and step 3 fills the answer with the remaining users of smallest
+ * estimate, r_lo + (r_hi - r_lo) (t[L-1] - u.q) / (t[L-1] - t[L]) (r_lo at
+ * the ends of the row), ordered in FP32, ties by user id.  This is an
+ * estimate: Def. 3 is not guaranteed (the cells count certain-above items at
+ * sampled thresholds).  Writes ids_out[k] [device, int32] in answer order and
+ * est_out[k] [device, double]: the bound or estimate each user was chosen by.
+ * Errors: RKR_E_STATE without a table; RKR_E_INVALID for k outside [1, n],
+ * c < 1 or not finite, a non-finite query; RKR_E_UNSUPPORTED if k > 4096.
+ */
+rkr_status rkr_query_table(rkr_index *idx, const void *q, int32_t k, double c, int32_t *ids_out,
+                           double *est_out);
+
+/*
  * Batch of nq queries Qm [device, nq x d] sharing one pass over U.P^T.
  *   k        [host, nq]      answer size per query
  *   c        [host, nq]      NULL: exact answers (Def. 2); else c[i] >= 1

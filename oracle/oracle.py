@@ -203,6 +203,59 @@ def rank_table(U, P, sample, pos, threads: int = 0):
     return t, cnt
 
 
+def table_query(t, cnt, tq, m: int, k: int, c: float):
+    """The paper's query on a rank table (Sec. 4.3, steps 1-3), for one query.
+
+    t[u][j]: user u's thresholds, descending in j; cnt[u][j]: the count of
+    items above t[u][j] (a table cell minus its leading 1); tq[u] = u.q (the
+    spec FP64 dot); m = |P|.  Readings where the text is loose:
+      * step 1: with L = #{j : t[u][j] >= u.q}, the query score lies between
+        columns L-1 and L, so r_lo = 1 + cnt[L-1] (1 when L = 0) and r_hi =
+        1 + cnt[L] (1 + m when L = tau);
+      * step 2 ranks users by r_hi ("smallest r"), admits r_hi <= c R_lo_k,
+        and drops users with r_lo > R_hi_k (Lemma 1 (2), strict);
+      * step 3 interpolates linearly in u.q between the two columns:
+        est = r_lo + (r_hi - r_lo) * ((t[L-1] - u.q) / (t[L-1] - t[L])), and
+        est = r_lo at either end of the table or between equal thresholds;
+        the estimate is rounded to FP32 for ordering, ties by user id.
+    Returns (ids, est): the k users in answer order and the rank each was
+    chosen by (r_hi for the users admitted in step 2, est after them)."""
+    t = np.asarray(t, np.float64)
+    cnt = np.asarray(cnt, np.int64)
+    tq = np.asarray(tq, np.float64)
+    n, tau = t.shape
+    ids_all = np.arange(n, dtype=np.int64)
+    # step 1: brackets
+    L = np.sum(t >= tq[:, None], axis=1)
+    r_lo = np.where(L > 0, 1 + cnt[ids_all, np.maximum(L - 1, 0)], 1)
+    r_hi = np.where(L < tau, 1 + cnt[ids_all, np.minimum(L, tau - 1)], 1 + m)
+    R_lo_k = np.sort(r_lo)[k - 1]
+    R_hi_k = np.sort(r_hi)[k - 1]
+    by_hi = np.lexsort((ids_all, r_hi))
+    # step 2
+    if c * float(R_lo_k) >= float(R_hi_k):
+        sel = by_hi[:k]
+        return sel.astype(np.int32), r_hi[sel].astype(np.float64)
+    admit = r_hi.astype(np.float64) <= c * float(R_lo_k)
+    first = by_hi[admit[by_hi]]
+    rest = (~admit) & (r_lo <= R_hi_k)
+    # step 3: interpolation for the users left open
+    est = r_lo.astype(np.float64)
+    inner = (L > 0) & (L < tau)
+    tA = t[ids_all, np.maximum(L - 1, 0)]
+    tB = t[ids_all, np.minimum(L, tau - 1)]
+    span = np.where(inner & (tA > tB), tA - tB, 1.0)
+    frac = np.where(inner & (tA > tB), (tA - tq) / span, 0.0)
+    est = np.where(inner & (tA > tB), r_lo + (r_hi - r_lo).astype(np.float64) * frac, est)
+    est32 = est.astype(np.float32)
+    cand = ids_all[rest]
+    order = cand[np.lexsort((cand, est32[cand]))]
+    fill = order[:k - first.shape[0]]
+    ids = np.concatenate([first, fill]).astype(np.int32)
+    out = np.concatenate([r_hi[first].astype(np.float64), est[fill]])
+    return ids, out
+
+
 # --------------------------------------------------------------------------
 # Def. 3 and the quality criteria of Sec. 5
 # --------------------------------------------------------------------------

@@ -1095,6 +1095,89 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
 }
 
 // ---------------------------------------------------------------------------
+// the paper's table query (Sec. 4.3, steps 1-3) on the index's rank table
+// ---------------------------------------------------------------------------
+extern "C" rkr_status rkr_query_table(rkr_index *x, const void *q, int32_t k, double c, int32_t *ids_out,
+                                      double *est_out) {
+    g_err.clear();
+    if (!x || !q || !ids_out || !est_out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->has_table) return fail(RKR_E_STATE, "index built without a rank table");
+    if (k < 1 || (int64_t)k > x->n) return fail(RKR_E_INVALID, "k must be in [1, n]");
+    if (k > 4096) return fail(RKR_E_UNSUPPORTED, "k above 4096");
+    if (!(c >= 1.0) || c == HUGE_VAL) return fail(RKR_E_INVALID, "c must be finite and at least 1");
+    hipStream_t st = x->st;
+    const int64_t n = x->n;
+    const double t0 = now_ms();
+    x->stats = rkr_query_stats{};
+    x->stats.queries = 1;
+    x->stats.pairs = n;
+    x->sc.reset();
+    HIPCK(x->t64.ensure(n * 8));
+    HIPCK(x->th.ensure(n * 4));
+    HIPCK(x->tl.ensure(n * 4));
+    HIPCK(x->tm.ensure(n * 4));
+    HIPCK(x->ctr.ensure(64));
+    HIPCK(x->segoff.ensure(16));
+    HIPCK(x->seloff.ensure(16));
+    HIPCK(x->kdev.ensure(8));
+    uint64_t *key_lo = (uint64_t *)x->sc.take(n * 8), *key_hi = (uint64_t *)x->sc.take(n * 8);
+    uint64_t *key_c = (uint64_t *)x->sc.take(n * 8), *key_t = (uint64_t *)x->sc.take(n * 8);
+    double *est = (double *)x->sc.take(n * 8);
+    uint64_t *sel_a = (uint64_t *)x->sc.take((int64_t)k * 8), *sel_b = (uint64_t *)x->sc.take((int64_t)k * 8);
+    if (!key_lo || !key_hi || !key_c || !key_t || !est || !sel_a || !sel_b)
+        return fail(RKR_E_NOMEM, "out of device memory (table query)");
+    // step 1: u.q for every user (spec FP64 dots), brackets and estimates
+    HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+    HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, x->t64.as<double>(), x->th.as<float>(),
+                              x->tl.as<float>(), x->tm.as<float>(), st));
+    HIPCK(q_tq_bounds(n, x->m, x->t64.as<double>(), x->tab_t.as<double>(), x->tab_cnt.as<uint32_t>(), key_lo, key_hi,
+                      est, st));
+    const int64_t segoff[2] = {0, n}, outoff[2] = {0, 0};
+    HIPCK(hipMemcpyAsync(x->segoff.p, segoff, 16, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(x->seloff.p, outoff, 16, hipMemcpyHostToDevice, st));
+    auto select = [&](const uint64_t *keys, int32_t kk, uint64_t *out) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(x->kdev.p, &kk, 4, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        e = launch_select(keys, x->segoff.as<int64_t>(), x->kdev.as<int32_t>(), 1, x->seloff.as<int64_t>(), out, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);   // kk lives on this stack frame
+    };
+    // R_lo_k, R_hi_k: the k-th smallest lower and upper bound
+    HIPCK(select(key_lo, k, sel_a));
+    HIPCK(select(key_hi, k, sel_b));
+    uint64_t kth[2] = {0, 0};
+    int flags = 0;
+    HIPCK(hipMemcpyAsync(&kth[0], sel_a + (k - 1), 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(&kth[1], sel_b + (k - 1), 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
+    const uint32_t R_lo_k = (uint32_t)(kth[0] >> 32), R_hi_k = (uint32_t)(kth[1] >> 32);
+    if (c * (double)R_lo_k >= (double)R_hi_k) {
+        // step 2, first case: the k users of smallest upper bound
+        HIPCK(q_tq_answer(sel_b, k, nullptr, 0, est, ids_out, est_out, st));
+    } else {
+        // step 2, second case: admitted users first, step 3 fills the rest
+        HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));
+        HIPCK(q_tq_classify(n, c, R_lo_k, R_hi_k, key_lo, key_hi, est, key_c, key_t, x->ctr.as<unsigned long long>(),
+                            st));
+        unsigned long long nadm = 0;
+        HIPCK(hipMemcpyAsync(&nadm, x->ctr.p, 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        // fewer than k users have r_hi < R_hi_k, and at least k have r_lo <= R_hi_k
+        const int32_t nc = (int32_t)std::min<unsigned long long>(nadm, (unsigned long long)k);
+        if (nc > 0) HIPCK(select(key_c, nc, sel_a));
+        if (k - nc > 0) HIPCK(select(key_t, k - nc, sel_b));
+        HIPCK(q_tq_answer(sel_a, nc, sel_b, k - nc, est, ids_out, est_out, st));
+        x->stats.survivors = (int64_t)nadm;
+    }
+    HIPCK(hipStreamSynchronize(st));
+    x->stats.ms_total = now_ms() - t0;
+    return RKR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // learned rank estimator
 // ---------------------------------------------------------------------------
 static rkr_status ensure_params(rkr_index *x) {

@@ -409,6 +409,71 @@ __global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// The paper's table query (Sec. 4.3, steps 1-3) for one query.  Step 1, per
+// user: L = the number of the user's columns (descending thresholds) at or
+// above u.q; the rank lies between r_lo = 1 + cnt[L - 1] (1 when L = 0) and
+// r_hi = 1 + cnt[L] (1 + m when L = TABLE_COLS); step 3's estimate is linear
+// in u.q between the two columns (r_lo at either end of the row or between
+// equal thresholds).  Keys (r << 32 | u) order users by bound, then id.
+// ---------------------------------------------------------------------------
+__global__ void k_tq_bounds(int64_t n, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
+                            uint64_t *key_lo, uint64_t *key_hi, double *est) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const double s = t64[u];
+    const double *tt = tab_t + u * TABLE_COLS;
+    const uint32_t *cc = tab_cnt + u * TABLE_COLS;
+    int L = 0;
+#pragma unroll
+    for (int j = 0; j < TABLE_COLS; ++j) L += tt[j] >= s ? 1 : 0;
+    const uint32_t rlo = L > 0 ? 1u + cc[L - 1] : 1u;
+    const uint32_t rhi = L < TABLE_COLS ? 1u + cc[L] : (uint32_t)(1 + m);
+    double e = (double)rlo;
+    if (L > 0 && L < TABLE_COLS) {
+        const double tA = tt[L - 1], tB = tt[L];
+        if (tA > tB) e = (double)rlo + (double)(rhi - rlo) * ((tA - s) / (tA - tB));
+    }
+    key_lo[u] = ((uint64_t)rlo << 32) | (uint64_t)u;
+    key_hi[u] = ((uint64_t)rhi << 32) | (uint64_t)u;
+    est[u] = e;
+}
+
+// Step 2 when c R_lo_k < R_hi_k: the admitted users (r_hi <= c R_lo_k) keep
+// their (r_hi, u) key in key_c, the users still open (not admitted, r_lo <=
+// R_hi_k, Lemma 1 (2)) get (fl32(estimate), u) in key_t for step 3; every
+// other key is the largest value.  *nadm counts the admitted users.
+__global__ void k_tq_classify(int64_t n, double c, uint32_t R_lo_k, uint32_t R_hi_k, const uint64_t *key_lo,
+                              const uint64_t *key_hi, const double *est, uint64_t *key_c, uint64_t *key_t,
+                              unsigned long long *nadm) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool admit = false;
+    if (u < n) {
+        const uint64_t kh = key_hi[u];
+        const uint32_t rhi = (uint32_t)(kh >> 32), rlo = (uint32_t)(key_lo[u] >> 32);
+        admit = (double)rhi <= c * (double)R_lo_k;
+        const bool open = !admit && rlo <= R_hi_k;
+        key_c[u] = admit ? kh : ~0ull;
+        key_t[u] = open ? (((uint64_t)f32_order_key((float)est[u]) << 32) | (uint64_t)u) : ~0ull;
+    }
+    const unsigned long long b = __ballot(admit);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nadm, (unsigned long long)__popcll(b));
+}
+
+// Answer: the nc selected (r_hi, u) keys, then the nt selected step-3 keys.
+__global__ void k_tq_answer(const uint64_t *sel_c, int64_t nc, const uint64_t *sel_t, int64_t nt, const double *est,
+                            int32_t *ids, double *est_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) {
+        ids[i] = (int32_t)(sel_c[i] & 0xFFFFFFFFu);
+        est_out[i] = (double)(uint32_t)(sel_c[i] >> 32);
+    } else if (i < nc + nt) {
+        const int32_t u = (int32_t)(sel_t[i - nc] & 0xFFFFFFFFu);
+        ids[i] = u;
+        est_out[i] = est[u];
+    }
+}
+
 // out[i] = the smallest float >= x[i]
 __global__ void k_round_up_f32(const double *x, int64_t n, float *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -630,6 +695,22 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
     }
     LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, 0, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound, tab_t, tab_cnt,
              keep);
+    return hipGetLastError();
+}
+hipError_t q_tq_bounds(int64_t n, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
+                       uint64_t *key_lo, uint64_t *key_hi, double *est, hipStream_t st) {
+    LAUNCH1D(k_tq_bounds, n, n, m, t64, tab_t, tab_cnt, key_lo, key_hi, est);
+    return hipGetLastError();
+}
+hipError_t q_tq_classify(int64_t n, double c, uint32_t R_lo_k, uint32_t R_hi_k, const uint64_t *key_lo,
+                         const uint64_t *key_hi, const double *est, uint64_t *key_c, uint64_t *key_t,
+                         unsigned long long *nadm, hipStream_t st) {
+    LAUNCH1D(k_tq_classify, n, n, c, R_lo_k, R_hi_k, key_lo, key_hi, est, key_c, key_t, nadm);
+    return hipGetLastError();
+}
+hipError_t q_tq_answer(const uint64_t *sel_c, int64_t nc, const uint64_t *sel_t, int64_t nt, const double *est,
+                       int32_t *ids, double *est_out, hipStream_t st) {
+    LAUNCH1D(k_tq_answer, nc + nt, sel_c, nc, sel_t, nt, est, ids, est_out);
     return hipGetLastError();
 }
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st) {

@@ -26,7 +26,7 @@ SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 32   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
-           "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
+           "rkr_query_table", "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
         "rkr_configure": [vp, ctypes.POINTER(QueryOpts)],
         "rkr_query_exact": [vp, vp, i32, vp, vp],
         "rkr_query_approx": [vp, vp, i32, f64, vp, vp],
+        "rkr_query_table": [vp, vp, i32, f64, vp, vp],
         "rkr_query_batch": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rkr_ranks": [vp, vp, vp],
         "rkr_train": [vp, i32, vp, i32, i32, i32, f32, ctypes.c_uint64],
@@ -177,6 +178,14 @@ def rkr_query_approx(h: int, q: torch.Tensor, k: int, c: float):
     rk = torch.empty(k, dtype=torch.int32, device=q.device)
     _check(load().rkr_query_approx(h, _ptr(q), int(k), float(c), _ptr(ids), _ptr(rk)))
     return ids, rk
+
+
+def rkr_query_table(h: int, q: torch.Tensor, k: int, c: float):
+    """The paper's table query (Sec. 4.3): (ids int32, est float64), device."""
+    ids = torch.empty(k, dtype=torch.int32, device=q.device)
+    est = torch.empty(k, dtype=torch.float64, device=q.device)
+    _check(load().rkr_query_table(h, _ptr(q), int(k), float(c), _ptr(ids), _ptr(est)))
+    return ids, est
 
 
 def rkr_query_batch(h: int, Q: torch.Tensor, k, c=None, cand_off=None, cand_ids=None):
@@ -288,6 +297,9 @@ class Index:
 
     def query_approx(self, q, k, c):
         return rkr_query_approx(self.h, q, k, c)
+
+    def query_table(self, q, k, c):
+        return rkr_query_table(self.h, q, k, c)
 
     def query_batch(self, Q, k, c=None, cand_off=None, cand_ids=None):
         return rkr_query_batch(self.h, Q, k, c, cand_off, cand_ids)

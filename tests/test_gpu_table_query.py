@@ -1,0 +1,79 @@
+"""GPU: the paper's own query on the rank table (Sec. 4.3, steps 1-3).
+
+On small-integer data with FP32 scores every score lies a whole unit away
+from any threshold it does not equal, far beyond the FP32 error bound, so the
+table's certain counts are the exact counts: the device table must equal the
+oracle's, and the device answer (ids and the bound or estimate each user was
+chosen by) must equal the oracle's table query element by element, in both
+cases of step 2.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2504_13446_amd import rkr
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    return rkr.to_device(x, "f32")
+
+
+@pytest.fixture(scope="module")
+def case():
+    rng = np.random.default_rng(71)
+    n, m, d, S = 2600, 3100, 6, 256
+    U = rng.integers(-3, 4, size=(n, d)).astype(np.float32)
+    P = rng.integers(-3, 4, size=(m, d)).astype(np.float32)
+    Qv = np.vstack([P[[4, 900, 2500]], rng.integers(-3, 4, size=(2, d)).astype(np.float32)])
+    idx = rkr.Index(_dev(U), _dev(P), score="f32", rank_table=S)
+    t, c = idx.rank_table()
+    want_t, want_c = O.rank_table(U, P, O.stratified_sample(P, S), O.sketch_positions(S, rkr.TABLE_COLS))
+    yield U, P, Qv, idx, (t.cpu().numpy(), c.cpu().numpy().astype(np.int64)), (want_t, want_c)
+    idx.close()
+
+
+def test_table_is_exact_on_integer_data(case):
+    _, _, _, _, (t, c), (want_t, want_c) = case
+    assert np.array_equal(t, want_t)
+    assert np.array_equal(c, want_c)
+
+
+def test_table_query_matches_oracle(case):
+    U, P, Qv, idx, _, (want_t, want_c) = case
+    m = P.shape[0]
+    n, tau = want_t.shape
+    seen = [0, 0]   # step 2: first case (c R_lo_k >= R_hi_k), second case
+    for qi in range(Qv.shape[0]):
+        tq = O.dots(U, Qv[qi:qi + 1])[:, 0]
+        L = np.sum(want_t >= tq[:, None], axis=1)
+        r_lo = np.where(L > 0, 1 + want_c[np.arange(n), np.maximum(L - 1, 0)], 1)
+        r_hi = np.where(L < tau, 1 + want_c[np.arange(n), np.minimum(L, tau - 1)], 1 + m)
+        for k in (1, 10, 100, 700):
+            for c in (1.0, 1.5, 4.0, 1e6):
+                ids, est = idx.query_table(_dev(Qv[qi]), k, c)
+                wi, we = O.table_query(want_t, want_c, tq, m, k, c)
+                assert np.array_equal(ids.cpu().numpy(), wi), (qi, k, c)
+                assert np.array_equal(est.cpu().numpy(), we), (qi, k, c)
+                seen[0 if c * np.sort(r_lo)[k - 1] >= np.sort(r_hi)[k - 1] else 1] += 1
+    assert seen[0] > 0 and seen[1] > 0, seen
+
+
+def test_table_query_errors(case):
+    U, P, Qv, idx, _, _ = case
+    q = _dev(Qv[0])
+    for k, c in ((0, 1.0), (U.shape[0] + 1, 1.0), (5, 0.5), (5, float("inf")), (5, float("nan"))):
+        with pytest.raises(rkr.RkrError) as e:
+            idx.query_table(q, k, c)
+        assert e.value.status == rkr.RKR_E_INVALID, (k, c)
+    plain = rkr.Index(_dev(U[:100]), _dev(P[:200]), score="f32")
+    with pytest.raises(rkr.RkrError) as e:
+        plain.query_table(q, 5, 1.5)
+    assert e.value.status == rkr.RKR_E_STATE
+    plain.close()
+    bad = _dev(np.full(U.shape[1], np.nan, np.float32))
+    with pytest.raises(rkr.RkrError) as e:
+        idx.query_table(bad, 5, 1.5)
+    assert e.value.status == rkr.RKR_E_INVALID

@@ -308,3 +308,81 @@ def test_rank_table_brackets_ranks():
                 assert R[qi, u] >= 1 + cnt[u][above].max()
             if below.any():
                 assert R[qi, u] <= 1 + cnt[u][below].min()
+
+
+def _table_case(seed, integer):
+    rng = np.random.default_rng(seed)
+    if integer:
+        U = rng.integers(-3, 4, size=(250, 6)).astype(np.float32)
+        P = rng.integers(-3, 4, size=(900, 6)).astype(np.float32)
+    else:
+        U = rng.standard_normal((250, 9)).astype(np.float32)
+        P = rng.standard_normal((900, 9)).astype(np.float32)
+    sample = O.stratified_sample(P, 128)
+    t, cnt = O.rank_table(U, P, sample, O.sketch_positions(128, 32))
+    Qv = P[[7, 300, 811]]
+    return U, P, t, cnt, Qv, O.ranks(U, P, Qv), O.dots(U, Qv)
+
+
+@pytest.mark.parametrize("integer", [False, True])
+def test_table_query_first_case_meets_the_c_bound(integer):
+    """Sec. 4.3 step 2, first case: with exact cells R_lo_k is at most the
+    true k-th smallest rank, so every returned user (r <= r_hi <= c R_lo_k)
+    has a rank within c times the k-th best one (checked by brute force)."""
+    U, P, t, cnt, Qv, R, T = _table_case(61, integer)
+    m = P.shape[0]
+    for qi in range(Qv.shape[0]):
+        for k in (1, 5, 20):
+            rho_k = np.sort(R[qi])[k - 1]
+            ids, est = O.table_query(t, cnt, T[:, qi], m, k, 1e9)
+            assert len(ids) == k and len(set(ids.tolist())) == k
+            assert np.all(R[qi][ids] <= est)            # est = r_hi, an upper bound here
+            assert np.all(est <= 1e9 * rho_k)
+            # a tight c: whichever case applies, the k smallest r_hi are never
+            # worse than the k-th smallest r_hi itself
+            ids2, est2 = O.table_query(t, cnt, T[:, qi], m, k, 1.0)
+            assert len(ids2) == k and len(set(ids2.tolist())) == k
+
+
+@pytest.mark.parametrize("integer", [False, True])
+def test_table_query_brackets_and_filter(integer):
+    """Step 1's bracket holds every exact rank (brute force); step 2 keeps
+    the users whose bracket can still beat R_hi_k; step 3's estimates lie in
+    their brackets; the answer lists the admitted users first."""
+    U, P, t, cnt, Qv, R, T = _table_case(62, integer)
+    m, n = P.shape[0], U.shape[0]
+    for qi in range(Qv.shape[0]):
+        tq = T[:, qi]
+        L = np.sum(t >= tq[:, None], axis=1)
+        r_lo = np.where(L > 0, 1 + cnt[np.arange(n), np.maximum(L - 1, 0)], 1)
+        r_hi = np.where(L < t.shape[1], 1 + cnt[np.arange(n), np.minimum(L, t.shape[1] - 1)], 1 + m)
+        assert np.all(r_lo <= R[qi]) and np.all(R[qi] <= r_hi)
+        k = 10
+        R_lo_k, R_hi_k = np.sort(r_lo)[k - 1], np.sort(r_hi)[k - 1]
+        c = 1.0001
+        ids, est = O.table_query(t, cnt, tq, m, k, c)
+        assert len(ids) == k and len(set(ids.tolist())) == k
+        assert np.all(r_lo[ids] <= R_hi_k)                   # nothing Lemma 1 (2) rules out
+        assert np.all(est >= r_lo[ids]) and np.all(est <= r_hi[ids])
+        if c * R_lo_k < R_hi_k:
+            admitted = r_hi[ids] <= c * R_lo_k
+            nadm = int(admitted.sum())
+            assert np.all(admitted[:nadm]) and not np.any(admitted[nadm:])
+            assert nadm == int(np.sum(r_hi <= c * R_lo_k))
+
+
+def test_table_query_interpolation_ends():
+    """Step 3's estimate meets the bracket at the columns' thresholds and
+    falls as u.q rises between them (one user, two columns)."""
+    t = np.array([[5.0, 4.0, 2.0]])
+    cnt = np.array([[5, 12, 40]])
+    m = 100
+    lo_hi = []
+    for x in (4.0 + 1e-12, 4.4, 4.9, 5.0 - 1e-12):
+        # a second user with a sure rank of 1 keeps the first one in step 3
+        tt = np.vstack([t, [[9.0, 8.0, 7.0]]])
+        cc = np.vstack([cnt, [[0, 0, 0]]])
+        ids, est = O.table_query(tt, cc, np.array([x, 10.0]), m, 2, 1.0)
+        lo_hi.append(est[list(ids).index(0)])
+    assert 6.0 <= lo_hi[-1] <= lo_hi[2] <= lo_hi[1] <= lo_hi[0] <= 13.0
+    assert abs(lo_hi[0] - 13.0) < 1e-9 and abs(lo_hi[-1] - 6.0) < 1e-9
