@@ -11,6 +11,8 @@ built once, outside it, and its build time is reported.
 Printed (one JSON line on stdout):
   value         queries/s of the BF16 + recheck path (exact)
   gcompare_per_s dense-equivalent rank comparisons per second (n * m * Q / t)
+  table_query   the paper's own query on the rank table (Sec. 4.3), one query
+                at a time, c = 1.5: time per query and recall of the exact top-k
   without_rank_table  the same batch with the table switched off
   fp32_plain    the same batch with FP32 scoring and a plain compare (no
                 band, no recheck), timed once, and the speed-up over it
@@ -99,6 +101,7 @@ def main() -> int:
                     help="sample items for the index's rank table (0: no table)")
     ap.add_argument("--seed-mult", type=int, default=0,
                     help="seeds per query, in units of k (0: the library's default)")
+    ap.add_argument("--no-table-query", action="store_true", help="skip the paper's table query line")
     ap.add_argument("--no-table-compare", action="store_true",
                     help="skip timing the same batch with the rank table switched off")
     ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")
@@ -228,6 +231,25 @@ def main() -> int:
         out["speedup_from_rank_table"] = round(ms_nt / ms_step, 3)
         idx.configure(no_table=False, seed_mult=args.seed_mult)
         log("without the rank table: %.1f ms/step (same answers: %s)" % (ms_nt, same))
+
+    if args.rank_table > 0 and not args.no_table_query:
+        # the paper's own query on the table (Sec. 4.3 steps 1-3), one query
+        # at a time: an estimate, scored by its recall of the exact answers
+        nt, cq = min(nq, 64), 1.5
+        ks = np.atleast_1d(w.k).astype(np.int64)
+        for i in range(2):
+            idx.query_table(Q[i], int(ks[i]), cq)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        got = [idx.query_table(Q[i], int(ks[i]), cq)[0] for i in range(nt)]
+        torch.cuda.synchronize()
+        ms_tq = (time.perf_counter() - t) * 1e3 / nt
+        rec = [len(set(got[i].cpu().numpy().tolist()) & set(ids_np[off[i]:off[i + 1]].tolist())) / float(ks[i])
+               for i in range(nt)]
+        out["table_query"] = {"ms_per_query": round(ms_tq, 3), "queries_per_s": round(1e3 / ms_tq, 2), "c": cq,
+                              "queries": nt, "recall_of_exact_top_k": round(float(np.mean(rec)), 4),
+                              "min_recall": round(float(np.min(rec)), 4)}
+        log("table query (Sec. 4.3): %.2f ms/query, recall of the exact top-k %.3f" % (ms_tq, np.mean(rec)))
 
     if not args.no_single:
         out["single_all_ranks"] = single_all_ranks(rkr, W)
