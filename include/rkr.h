@@ -186,6 +186,16 @@ rkr_status rkr_query_table(rkr_index *idx, const void *q, int32_t k, double c, i
                            double *est_out);
 
 /*
+ * The same table query for nq queries at once (Sec. 4.3, steps 1-3 per
+ * query): Qm [device, nq x d], k[nq] and c[nq] [host].  Query i's answer is
+ * written at offset k[0] + ... + k[i-1] of ids_out and est_out [device].
+ * Errors as rkr_query_table, plus RKR_E_INVALID for nq outside [1, 65535] and
+ * RKR_E_UNSUPPORTED for n * nq >= 2^31.
+ */
+rkr_status rkr_query_table_batch(rkr_index *idx, int32_t nq, const void *Qm, const int32_t *k,
+                                 const double *c, int32_t *ids_out, double *est_out);
+
+/*
  * Batch of nq queries Qm [device, nq x d] sharing one pass over U.P^T.
  *   k        [host, nq]      answer size per query
  *   c        [host, nq]      NULL: exact answers (Def. 2); else c[i] >= 1

@@ -1097,84 +1097,104 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
 // ---------------------------------------------------------------------------
 // the paper's table query (Sec. 4.3, steps 1-3) on the index's rank table
 // ---------------------------------------------------------------------------
-extern "C" rkr_status rkr_query_table(rkr_index *x, const void *q, int32_t k, double c, int32_t *ids_out,
-                                      double *est_out) {
+extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k,
+                                            const double *c, int32_t *ids_out, double *est_out) {
     g_err.clear();
-    if (!x || !q || !ids_out || !est_out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x || !Qm || !k || !c || !ids_out || !est_out) return fail(RKR_E_INVALID, "NULL argument");
     if (!x->has_table) return fail(RKR_E_STATE, "index built without a rank table");
-    if (k < 1 || (int64_t)k > x->n) return fail(RKR_E_INVALID, "k must be in [1, n]");
-    if (k > 4096) return fail(RKR_E_UNSUPPORTED, "k above 4096");
-    if (!(c >= 1.0) || c == HUGE_VAL) return fail(RKR_E_INVALID, "c must be finite and at least 1");
-    hipStream_t st = x->st;
+    if (nq < 1 || nq > 65535) return fail(RKR_E_INVALID, "nq must be in [1, 65535]");
     const int64_t n = x->n;
+    if (n * (int64_t)nq >= ((int64_t)1 << 31)) return fail(RKR_E_UNSUPPORTED, "n * nq must stay below 2^31");
+    std::vector<int64_t> off(nq + 1, 0), segoff(nq + 1, 0);
+    for (int q = 0; q < nq; ++q) {
+        if (k[q] < 1 || (int64_t)k[q] > n) return fail(RKR_E_INVALID, "k must be in [1, n]");
+        if (k[q] > 4096) return fail(RKR_E_UNSUPPORTED, "k above 4096");
+        if (!(c[q] >= 1.0) || c[q] == HUGE_VAL) return fail(RKR_E_INVALID, "c must be finite and at least 1");
+        off[q + 1] = off[q] + k[q];
+        segoff[q + 1] = segoff[q] + n;
+    }
+    hipStream_t st = x->st;
     const double t0 = now_ms();
+    const int64_t np = n * nq, total = off[nq];
     x->stats = rkr_query_stats{};
-    x->stats.queries = 1;
-    x->stats.pairs = n;
+    x->stats.queries = nq;
+    x->stats.pairs = np;
     x->sc.reset();
-    HIPCK(x->t64.ensure(n * 8));
-    HIPCK(x->th.ensure(n * 4));
-    HIPCK(x->tl.ensure(n * 4));
-    HIPCK(x->tm.ensure(n * 4));
-    HIPCK(x->ctr.ensure(64));
-    HIPCK(x->segoff.ensure(16));
-    HIPCK(x->seloff.ensure(16));
-    HIPCK(x->kdev.ensure(8));
-    uint64_t *key_lo = (uint64_t *)x->sc.take(n * 8), *key_hi = (uint64_t *)x->sc.take(n * 8);
-    uint64_t *key_c = (uint64_t *)x->sc.take(n * 8), *key_t = (uint64_t *)x->sc.take(n * 8);
-    double *est = (double *)x->sc.take(n * 8);
-    uint64_t *sel_a = (uint64_t *)x->sc.take((int64_t)k * 8), *sel_b = (uint64_t *)x->sc.take((int64_t)k * 8);
-    if (!key_lo || !key_hi || !key_c || !key_t || !est || !sel_a || !sel_b)
+    HIPCK(x->t64.ensure(np * 8));
+    HIPCK(x->th.ensure(np * 4));
+    HIPCK(x->tl.ensure(np * 4));
+    HIPCK(x->tm.ensure(np * 4));
+    HIPCK(x->flags.ensure(16));
+    auto take = [&](int64_t bytes) { return x->sc.take(bytes); };
+    uint64_t *key_lo = (uint64_t *)take(np * 8), *key_hi = (uint64_t *)take(np * 8);
+    uint64_t *key_c = (uint64_t *)take(np * 8), *key_t = (uint64_t *)take(np * 8);
+    double *est = (double *)take(np * 8);
+    uint64_t *sel_lo = (uint64_t *)take(total * 8), *sel_hi = (uint64_t *)take(total * 8);
+    uint64_t *sel_c = (uint64_t *)take(total * 8), *sel_t = (uint64_t *)take(total * 8);
+    int64_t *d_off = (int64_t *)take((nq + 1) * 8), *d_seg = (int64_t *)take((nq + 1) * 8);
+    int64_t *d_offc = (int64_t *)take((nq + 1) * 8), *d_offt = (int64_t *)take((nq + 1) * 8);
+    int32_t *d_k = (int32_t *)take(nq * 4), *d_nc = (int32_t *)take(nq * 4), *d_nt = (int32_t *)take(nq * 4);
+    int32_t *d_first = (int32_t *)take(nq * 4);
+    double *d_c = (double *)take(nq * 8);
+    uint32_t *d_Rlo = (uint32_t *)take(nq * 4), *d_Rhi = (uint32_t *)take(nq * 4);
+    unsigned long long *d_nadm = (unsigned long long *)take(nq * 8);
+    if (!key_lo || !key_hi || !key_c || !key_t || !est || !sel_lo || !sel_hi || !sel_c || !sel_t || !d_off ||
+        !d_seg || !d_offc || !d_offt || !d_k || !d_nc || !d_nt || !d_first || !d_c || !d_Rlo || !d_Rhi || !d_nadm)
         return fail(RKR_E_NOMEM, "out of device memory (table query)");
-    // step 1: u.q for every user (spec FP64 dots), brackets and estimates
+    HIPCK(hipMemcpyAsync(d_off, off.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_seg, segoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_k, k, nq * 4, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_c, c, nq * 8, hipMemcpyHostToDevice, st));
+    // step 1: u.q for every (user, query) (spec FP64 dots), brackets, estimates
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
-    HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
-    HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, x->t64.as<double>(), x->th.as<float>(),
+    HIPCK(launch_check_values(Qm, (int64_t)nq * x->d, x->mk, x->flags.as<int>(), st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), x->th.as<float>(),
                               x->tl.as<float>(), x->tm.as<float>(), st));
-    HIPCK(q_tq_bounds(n, x->m, x->t64.as<double>(), x->tab_t.as<double>(), x->tab_cnt.as<uint32_t>(), key_lo, key_hi,
-                      est, st));
-    const int64_t segoff[2] = {0, n}, outoff[2] = {0, 0};
-    HIPCK(hipMemcpyAsync(x->segoff.p, segoff, 16, hipMemcpyHostToDevice, st));
-    HIPCK(hipMemcpyAsync(x->seloff.p, outoff, 16, hipMemcpyHostToDevice, st));
-    auto select = [&](const uint64_t *keys, int32_t kk, uint64_t *out) -> hipError_t {
-        hipError_t e = hipMemcpyAsync(x->kdev.p, &kk, 4, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return e;
-        e = launch_select(keys, x->segoff.as<int64_t>(), x->kdev.as<int32_t>(), 1, x->seloff.as<int64_t>(), out, st);
-        if (e != hipSuccess) return e;
-        return hipStreamSynchronize(st);   // kk lives on this stack frame
-    };
-    // R_lo_k, R_hi_k: the k-th smallest lower and upper bound
-    HIPCK(select(key_lo, k, sel_a));
-    HIPCK(select(key_hi, k, sel_b));
-    uint64_t kth[2] = {0, 0};
+    HIPCK(q_tqb_bounds(n, nq, x->m, x->t64.as<double>(), x->tab_t.as<double>(), x->tab_cnt.as<uint32_t>(), key_lo,
+                       key_hi, est, st));
+    // R_lo_k, R_hi_k per query and the case of step 2
+    HIPCK(launch_select(key_lo, d_seg, d_k, nq, d_off, sel_lo, st));
+    HIPCK(launch_select(key_hi, d_seg, d_k, nq, d_off, sel_hi, st));
+    HIPCK(q_tqb_kth(nq, d_k, d_c, sel_lo, sel_hi, d_off, d_Rlo, d_Rhi, d_first, st));
+    // step 2, second case: admitted users and the users left open
+    HIPCK(launch_fill_u32((uint32_t *)d_nadm, 0, 2 * (int64_t)nq, st));
+    HIPCK(q_tqb_classify(n, nq, d_c, d_Rlo, d_Rhi, d_first, key_lo, key_hi, est, key_c, key_t, d_nadm, st));
+    std::vector<unsigned long long> nadm(nq);
+    std::vector<int32_t> first(nq), nc(nq), nt(nq);
     int flags = 0;
-    HIPCK(hipMemcpyAsync(&kth[0], sel_a + (k - 1), 8, hipMemcpyDeviceToHost, st));
-    HIPCK(hipMemcpyAsync(&kth[1], sel_b + (k - 1), 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(nadm.data(), d_nadm, nq * 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(first.data(), d_first, nq * 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
-    if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
-    const uint32_t R_lo_k = (uint32_t)(kth[0] >> 32), R_hi_k = (uint32_t)(kth[1] >> 32);
-    if (c * (double)R_lo_k >= (double)R_hi_k) {
-        // step 2, first case: the k users of smallest upper bound
-        HIPCK(q_tq_answer(sel_b, k, nullptr, 0, est, ids_out, est_out, st));
-    } else {
-        // step 2, second case: admitted users first, step 3 fills the rest
-        HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));
-        HIPCK(q_tq_classify(n, c, R_lo_k, R_hi_k, key_lo, key_hi, est, key_c, key_t, x->ctr.as<unsigned long long>(),
-                            st));
-        unsigned long long nadm = 0;
-        HIPCK(hipMemcpyAsync(&nadm, x->ctr.p, 8, hipMemcpyDeviceToHost, st));
-        HIPCK(hipStreamSynchronize(st));
-        // fewer than k users have r_hi < R_hi_k, and at least k have r_lo <= R_hi_k
-        const int32_t nc = (int32_t)std::min<unsigned long long>(nadm, (unsigned long long)k);
-        if (nc > 0) HIPCK(select(key_c, nc, sel_a));
-        if (k - nc > 0) HIPCK(select(key_t, k - nc, sel_b));
-        HIPCK(q_tq_answer(sel_a, nc, sel_b, k - nc, est, ids_out, est_out, st));
-        x->stats.survivors = (int64_t)nadm;
+    if (flags) return fail(RKR_E_INVALID, "a query holds a non-finite value or one above 2^50");
+    // fewer than k users have r_hi < R_hi_k, and at least k have r_lo <= R_hi_k
+    std::vector<int64_t> offc(nq + 1, 0), offt(nq + 1, 0);
+    int64_t admitted = 0;
+    for (int q = 0; q < nq; ++q) {
+        nc[q] = first[q] ? 0 : (int32_t)std::min<unsigned long long>(nadm[q], (unsigned long long)k[q]);
+        nt[q] = first[q] ? 0 : k[q] - nc[q];
+        offc[q + 1] = offc[q] + nc[q];
+        offt[q + 1] = offt[q] + nt[q];
+        admitted += (int64_t)nadm[q];
     }
+    HIPCK(hipMemcpyAsync(d_nc, nc.data(), nq * 4, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_nt, nt.data(), nq * 4, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_offc, offc.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_offt, offt.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+    // step 2's admitted users by (r_hi, id); step 3's fill by (fl32(estimate), id)
+    HIPCK(launch_select(key_c, d_seg, d_nc, nq, d_offc, sel_c, st));
+    HIPCK(launch_select(key_t, d_seg, d_nt, nq, d_offt, sel_t, st));
+    HIPCK(q_tqb_answer(nq, n, total, d_off, d_first, d_off, sel_hi, d_nc, d_offc, sel_c, d_offt, sel_t, est, ids_out,
+                       est_out, st));
     HIPCK(hipStreamSynchronize(st));
+    x->stats.survivors = admitted;
     x->stats.ms_total = now_ms() - t0;
     return RKR_OK;
+}
+
+extern "C" rkr_status rkr_query_table(rkr_index *x, const void *q, int32_t k, double c, int32_t *ids_out,
+                                      double *est_out) {
+    return rkr_query_table_batch(x, 1, q, &k, &c, ids_out, est_out);
 }
 
 // ---------------------------------------------------------------------------

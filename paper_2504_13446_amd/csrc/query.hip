@@ -410,68 +410,134 @@ __global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, con
 }
 
 // ---------------------------------------------------------------------------
-// The paper's table query (Sec. 4.3, steps 1-3) for one query.  Step 1, per
-// user: L = the number of the user's columns (descending thresholds) at or
-// above u.q; the rank lies between r_lo = 1 + cnt[L - 1] (1 when L = 0) and
-// r_hi = 1 + cnt[L] (1 + m when L = TABLE_COLS); step 3's estimate is linear
-// in u.q between the two columns (r_lo at either end of the row or between
-// equal thresholds).  Keys (r << 32 | u) order users by bound, then id.
+// The paper's table query (Sec. 4.3, steps 1-3) for a dense batch of
+// queries.  Step 1, per (user, query): L = the number of the user's columns
+// (descending thresholds) at or above u.q; the rank lies between r_lo = 1 +
+// cnt[L - 1] (1 when L = 0) and r_hi = 1 + cnt[L] (1 + m when L =
+// TABLE_COLS); step 3's estimate is linear in u.q between the two columns
+// (r_lo at either end of the row or between equal thresholds).  Keys
+// (r << 32 | u) order users by bound, then id.
 // ---------------------------------------------------------------------------
-__global__ void k_tq_bounds(int64_t n, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
-                            uint64_t *key_lo, uint64_t *key_hi, double *est) {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    const double s = t64[u];
-    const double *tt = tab_t + u * TABLE_COLS;
-    const uint32_t *cc = tab_cnt + u * TABLE_COLS;
+__device__ inline void tq_bracket(const double *tt, const uint32_t *cc, double s, int64_t m, uint32_t &rlo,
+                                  uint32_t &rhi, double &e) {
     int L = 0;
 #pragma unroll
     for (int j = 0; j < TABLE_COLS; ++j) L += tt[j] >= s ? 1 : 0;
-    const uint32_t rlo = L > 0 ? 1u + cc[L - 1] : 1u;
-    const uint32_t rhi = L < TABLE_COLS ? 1u + cc[L] : (uint32_t)(1 + m);
-    double e = (double)rlo;
+    rlo = L > 0 ? 1u + cc[L - 1] : 1u;
+    rhi = L < TABLE_COLS ? 1u + cc[L] : (uint32_t)(1 + m);
+    e = (double)rlo;
     if (L > 0 && L < TABLE_COLS) {
         const double tA = tt[L - 1], tB = tt[L];
         if (tA > tB) e = (double)rlo + (double)(rhi - rlo) * ((tA - s) / (tA - tB));
     }
-    key_lo[u] = ((uint64_t)rlo << 32) | (uint64_t)u;
-    key_hi[u] = ((uint64_t)rhi << 32) | (uint64_t)u;
-    est[u] = e;
 }
 
-// Step 2 when c R_lo_k < R_hi_k: the admitted users (r_hi <= c R_lo_k) keep
-// their (r_hi, u) key in key_c, the users still open (not admitted, r_lo <=
-// R_hi_k, Lemma 1 (2)) get (fl32(estimate), u) in key_t for step 3; every
-// other key is the largest value.  *nadm counts the admitted users.
-__global__ void k_tq_classify(int64_t n, double c, uint32_t R_lo_k, uint32_t R_hi_k, const uint64_t *key_lo,
-                              const uint64_t *key_hi, const double *est, uint64_t *key_c, uint64_t *key_t,
-                              unsigned long long *nadm) {
+// Brackets and estimates of the pairs u * nq + q go to query-major arrays
+// [q * n + u] (one segment per query for the selections) through an LDS tile
+// of 64 users x 32 queries, so the reads of t64 and the writes of the keys
+// both coalesce.
+__global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64,
+                                                    const double *tab_t, const uint32_t *tab_cnt, uint64_t *key_lo,
+                                                    uint64_t *key_hi, double *est) {
+    __shared__ uint32_t s_lo[32][65], s_hi[32][65];
+    __shared__ double s_e[32][65];
+    const int64_t u0 = (int64_t)blockIdx.x * 64;
+    const int q0 = blockIdx.y * 32;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int uu = r * 8 + (tid >> 5), qq = tid & 31;
+        const int64_t u = u0 + uu;
+        const int q = q0 + qq;
+        if (u < n && q < nq) {
+            uint32_t rlo, rhi;
+            double e;
+            tq_bracket(tab_t + u * TABLE_COLS, tab_cnt + u * TABLE_COLS, t64[u * nq + q], m, rlo, rhi, e);
+            s_lo[qq][uu] = rlo;
+            s_hi[qq][uu] = rhi;
+            s_e[qq][uu] = e;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int qq = r * 4 + (tid >> 6), uu = tid & 63;
+        const int64_t u = u0 + uu;
+        const int q = q0 + qq;
+        if (u < n && q < nq) {
+            const int64_t j = (int64_t)q * n + u;
+            key_lo[j] = ((uint64_t)s_lo[qq][uu] << 32) | (uint64_t)u;
+            key_hi[j] = ((uint64_t)s_hi[qq][uu] << 32) | (uint64_t)u;
+            est[j] = s_e[qq][uu];
+        }
+    }
+}
+
+// Per query: R_lo_k, R_hi_k from the k smallest keys of each kind, and
+// which case of step 2 applies (1: c R_lo_k >= R_hi_k).
+__global__ void k_tqb_kth(int nq, const int32_t *k, const double *c, const uint64_t *sel_lo, const uint64_t *sel_hi,
+                          const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int64_t i = sel_off[q] + k[q] - 1;
+    const uint32_t lo = (uint32_t)(sel_lo[i] >> 32), hi = (uint32_t)(sel_hi[i] >> 32);
+    R_lo[q] = lo;
+    R_hi[q] = hi;
+    first_case[q] = c[q] * (double)lo >= (double)hi ? 1 : 0;
+}
+
+// Step 2 when c R_lo_k < R_hi_k, per (query, user): the admitted users
+// (r_hi <= c R_lo_k) keep their (r_hi, u) key in key_c, the users still open
+// (not admitted, r_lo <= R_hi_k, Lemma 1 (2)) get (fl32(estimate), u) in
+// key_t for step 3; every other key is the largest value.  nadm[q] counts
+// the query's admitted users.  Queries in the first case get no keys.
+__global__ void k_tqb_classify(int64_t n, const double *c, const uint32_t *R_lo, const uint32_t *R_hi,
+                               const int32_t *first_case, const uint64_t *key_lo, const uint64_t *key_hi,
+                               const double *est, uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm) {
+    const int q = blockIdx.y;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool admit = false;
     if (u < n) {
-        const uint64_t kh = key_hi[u];
-        const uint32_t rhi = (uint32_t)(kh >> 32), rlo = (uint32_t)(key_lo[u] >> 32);
-        admit = (double)rhi <= c * (double)R_lo_k;
-        const bool open = !admit && rlo <= R_hi_k;
-        key_c[u] = admit ? kh : ~0ull;
-        key_t[u] = open ? (((uint64_t)f32_order_key((float)est[u]) << 32) | (uint64_t)u) : ~0ull;
+        const int64_t j = (int64_t)q * n + u;
+        bool open = false;
+        const uint64_t kh = key_hi[j];
+        if (!first_case[q]) {
+            const uint32_t rhi = (uint32_t)(kh >> 32), rlo = (uint32_t)(key_lo[j] >> 32);
+            admit = (double)rhi <= c[q] * (double)R_lo[q];
+            open = !admit && rlo <= R_hi[q];
+        }
+        key_c[j] = admit ? kh : ~0ull;
+        key_t[j] = open ? (((uint64_t)f32_order_key((float)est[j]) << 32) | (uint64_t)u) : ~0ull;
     }
     const unsigned long long b = __ballot(admit);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(nadm, (unsigned long long)__popcll(b));
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&nadm[q], (unsigned long long)__popcll(b));
 }
 
-// Answer: the nc selected (r_hi, u) keys, then the nt selected step-3 keys.
-__global__ void k_tq_answer(const uint64_t *sel_c, int64_t nc, const uint64_t *sel_t, int64_t nt, const double *est,
-                            int32_t *ids, double *est_out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nc) {
-        ids[i] = (int32_t)(sel_c[i] & 0xFFFFFFFFu);
-        est_out[i] = (double)(uint32_t)(sel_c[i] >> 32);
-    } else if (i < nc + nt) {
-        const int32_t u = (int32_t)(sel_t[i - nc] & 0xFFFFFFFFu);
-        ids[i] = u;
-        est_out[i] = est[u];
+// Answer slot j (queries concatenated, query q from off[q]): the first case
+// takes the k smallest (r_hi, u) keys, the second its nc admitted keys then
+// the step-3 keys.
+__global__ void k_tqb_answer(int nq, int64_t n, const int64_t *off, const int32_t *first_case, const int64_t *sel_off,
+                             const uint64_t *sel_hi, const int32_t *nc, const int64_t *off_c, const uint64_t *sel_c,
+                             const int64_t *off_t, const uint64_t *sel_t, const double *est, int32_t *ids,
+                             double *est_out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= off[nq]) return;
+    const int q = seg_of(off, nq, j);
+    const int64_t i = j - off[q];
+    uint64_t key;
+    double e;
+    if (first_case[q]) {
+        key = sel_hi[sel_off[q] + i];
+        e = (double)(uint32_t)(key >> 32);
+    } else if (i < nc[q]) {
+        key = sel_c[off_c[q] + i];
+        e = (double)(uint32_t)(key >> 32);
+    } else {
+        key = sel_t[off_t[q] + i - nc[q]];
+        e = est[(int64_t)q * n + (int64_t)(key & 0xFFFFFFFFu)];
     }
+    ids[j] = (int32_t)(key & 0xFFFFFFFFu);
+    est_out[j] = e;
 }
 
 // out[i] = the smallest float >= x[i]
@@ -697,20 +763,32 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
              keep);
     return hipGetLastError();
 }
-hipError_t q_tq_bounds(int64_t n, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
-                       uint64_t *key_lo, uint64_t *key_hi, double *est, hipStream_t st) {
-    LAUNCH1D(k_tq_bounds, n, n, m, t64, tab_t, tab_cnt, key_lo, key_hi, est);
+hipError_t q_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
+                        uint64_t *key_lo, uint64_t *key_hi, double *est, hipStream_t st) {
+    if (n <= 0 || nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tqb_bounds, dim3((unsigned)((n + 63) / 64), (unsigned)((nq + 31) / 32)), dim3(256), 0, st, n,
+                       nq, m, t64, tab_t, tab_cnt, key_lo, key_hi, est);
     return hipGetLastError();
 }
-hipError_t q_tq_classify(int64_t n, double c, uint32_t R_lo_k, uint32_t R_hi_k, const uint64_t *key_lo,
-                         const uint64_t *key_hi, const double *est, uint64_t *key_c, uint64_t *key_t,
-                         unsigned long long *nadm, hipStream_t st) {
-    LAUNCH1D(k_tq_classify, n, n, c, R_lo_k, R_hi_k, key_lo, key_hi, est, key_c, key_t, nadm);
+hipError_t q_tqb_kth(int nq, const int32_t *k, const double *c, const uint64_t *sel_lo, const uint64_t *sel_hi,
+                     const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case, hipStream_t st) {
+    LAUNCH1D(k_tqb_kth, nq, nq, k, c, sel_lo, sel_hi, sel_off, R_lo, R_hi, first_case);
     return hipGetLastError();
 }
-hipError_t q_tq_answer(const uint64_t *sel_c, int64_t nc, const uint64_t *sel_t, int64_t nt, const double *est,
-                       int32_t *ids, double *est_out, hipStream_t st) {
-    LAUNCH1D(k_tq_answer, nc + nt, sel_c, nc, sel_t, nt, est, ids, est_out);
+hipError_t q_tqb_classify(int64_t n, int nq, const double *c, const uint32_t *R_lo, const uint32_t *R_hi,
+                          const int32_t *first_case, const uint64_t *key_lo, const uint64_t *key_hi, const double *est,
+                          uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm, hipStream_t st) {
+    if (n <= 0 || nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tqb_classify, dim3((unsigned)((n + 255) / 256), (unsigned)nq), dim3(256), 0, st, n, c, R_lo,
+                       R_hi, first_case, key_lo, key_hi, est, key_c, key_t, nadm);
+    return hipGetLastError();
+}
+hipError_t q_tqb_answer(int nq, int64_t n, int64_t total, const int64_t *off, const int32_t *first_case,
+                        const int64_t *sel_off, const uint64_t *sel_hi, const int32_t *nc, const int64_t *off_c,
+                        const uint64_t *sel_c, const int64_t *off_t, const uint64_t *sel_t, const double *est,
+                        int32_t *ids, double *est_out, hipStream_t st) {
+    LAUNCH1D(k_tqb_answer, total, nq, n, off, first_case, sel_off, sel_hi, nc, off_c, sel_c, off_t, sel_t, est, ids,
+             est_out);
     return hipGetLastError();
 }
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st) {

@@ -26,7 +26,7 @@ SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 32   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
-           "rkr_query_table", "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
+           "rkr_query_table", "rkr_query_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
         "rkr_query_exact": [vp, vp, i32, vp, vp],
         "rkr_query_approx": [vp, vp, i32, f64, vp, vp],
         "rkr_query_table": [vp, vp, i32, f64, vp, vp],
+        "rkr_query_table_batch": [vp, i32, vp, vp, vp, vp, vp],
         "rkr_query_batch": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rkr_ranks": [vp, vp, vp],
         "rkr_train": [vp, i32, vp, i32, i32, i32, f32, ctypes.c_uint64],
@@ -186,6 +187,20 @@ def rkr_query_table(h: int, q: torch.Tensor, k: int, c: float):
     est = torch.empty(k, dtype=torch.float64, device=q.device)
     _check(load().rkr_query_table(h, _ptr(q), int(k), float(c), _ptr(ids), _ptr(est)))
     return ids, est
+
+
+def rkr_query_table_batch(h: int, Q: torch.Tensor, k, c):
+    """The paper's table query for nq queries: (ids int32, est float64) on
+    the device, concatenated by query, and the host offsets [nq + 1]."""
+    nq = int(Q.shape[0])
+    kk = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    cc = np.ascontiguousarray(np.broadcast_to(np.asarray(c, np.float64), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(kk)
+    ids = torch.empty(int(off[-1]), dtype=torch.int32, device=Q.device)
+    est = torch.empty(int(off[-1]), dtype=torch.float64, device=Q.device)
+    _check(load().rkr_query_table_batch(h, nq, _ptr(Q), kk.ctypes.data, cc.ctypes.data, _ptr(ids), _ptr(est)))
+    return ids, est, off
 
 
 def rkr_query_batch(h: int, Q: torch.Tensor, k, c=None, cand_off=None, cand_ids=None):
@@ -300,6 +315,9 @@ class Index:
 
     def query_table(self, q, k, c):
         return rkr_query_table(self.h, q, k, c)
+
+    def query_table_batch(self, Q, k, c):
+        return rkr_query_table_batch(self.h, Q, k, c)
 
     def query_batch(self, Q, k, c=None, cand_off=None, cand_ids=None):
         return rkr_query_batch(self.h, Q, k, c, cand_off, cand_ids)

@@ -77,3 +77,26 @@ def test_table_query_errors(case):
     with pytest.raises(rkr.RkrError) as e:
         idx.query_table(bad, 5, 1.5)
     assert e.value.status == rkr.RKR_E_INVALID
+
+
+def test_table_query_batch_matches_oracle(case):
+    """All queries in one call, each with its own k and c: every query's
+    answer equals the oracle's table query."""
+    U, P, Qv, idx, _, (want_t, want_c) = case
+    m = P.shape[0]
+    rng = np.random.default_rng(72)
+    Qb = np.vstack([Qv, P[rng.choice(P.shape[0], 40, replace=False)],
+                    rng.integers(-3, 4, size=(25, U.shape[1])).astype(np.float32)])
+    ks = rng.integers(1, 300, size=Qb.shape[0]).astype(np.int32)
+    cs = rng.choice([1.0, 1.2, 2.0, 1e6], size=Qb.shape[0])
+    ids, est, off = idx.query_table_batch(_dev(Qb), ks, cs)
+    ids = ids.cpu().numpy()
+    est = est.cpu().numpy()
+    T = O.dots(U, Qb)
+    for i in range(Qb.shape[0]):
+        wi, we = O.table_query(want_t, want_c, T[:, i], m, int(ks[i]), float(cs[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], wi), i
+        assert np.array_equal(est[off[i]:off[i + 1]], we), i
+    with pytest.raises(rkr.RkrError) as e:
+        idx.query_table_batch(_dev(Qb[:3]), [5, 0, 5], [1.5, 1.5, 1.5])
+    assert e.value.status == rkr.RKR_E_INVALID
