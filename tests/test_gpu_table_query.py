@@ -100,3 +100,26 @@ def test_table_query_batch_matches_oracle(case):
     with pytest.raises(rkr.RkrError) as e:
         idx.query_table_batch(_dev(Qb[:3]), [5, 0, 5], [1.5, 1.5, 1.5])
     assert e.value.status == rkr.RKR_E_INVALID
+
+
+def test_table_query_edges():
+    """Fewer users than a tile, more samples than items (every item is a
+    sample), k = n, and a query above every threshold of some users."""
+    rng = np.random.default_rng(73)
+    n, m, d, S = 37, 50, 3, 64
+    U = rng.integers(-2, 3, size=(n, d)).astype(np.float32)
+    P = rng.integers(-2, 3, size=(m, d)).astype(np.float32)
+    Qv = np.vstack([P[0], np.full(d, 3.0, np.float32), np.zeros(d, np.float32)])
+    idx = rkr.Index(_dev(U), _dev(P), score="f32", rank_table=S)
+    want_t, want_c = O.rank_table(U, P, O.stratified_sample(P, min(S, m)), O.sketch_positions(min(S, m), rkr.TABLE_COLS))
+    t, c = idx.rank_table()
+    assert np.array_equal(t.cpu().numpy(), want_t) and np.array_equal(c.cpu().numpy(), want_c)
+    T = O.dots(U, Qv)
+    ks = np.array([n, 1, 7], np.int32)
+    cs = np.array([1.0, 3.0, 1.1])
+    ids, est, off = idx.query_table_batch(_dev(Qv), ks, cs)
+    for i in range(3):
+        wi, we = O.table_query(want_t, want_c, T[:, i], m, int(ks[i]), float(cs[i]))
+        assert np.array_equal(ids.cpu().numpy()[off[i]:off[i + 1]], wi), i
+        assert np.array_equal(est.cpu().numpy()[off[i]:off[i + 1]], we), i
+    idx.close()
