@@ -349,15 +349,12 @@ __global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, cons
     const int q = nq > 0 ? (int)(i - u * nq) : pair_q[i];
     const double t = t64[i];
     // the columns' thresholds do not increase: L = the number of columns
-    // with t_{u,j} >= t, by binary search; column L - 1 is the tightest of
-    // them (any one of them gives a valid bound)
-    static_assert((TABLE_COLS & (TABLE_COLS - 1)) == 0, "binary search over a power of two");
+    // with t_{u,j} >= t; column L - 1 is the tightest of them (any one of
+    // them gives a valid bound)
     const double *tt = tab_t + u * TABLE_COLS;
     int L = 0;
 #pragma unroll
-    for (int step = TABLE_COLS / 2; step >= 1; step >>= 1)
-        if (tt[L + step - 1] >= t) L += step;
-    if (tt[L] >= t) L += 1;
+    for (int j = 0; j < TABLE_COLS; ++j) L += tt[j] >= t ? 1 : 0;
     const uint32_t best = L > 0 ? tab_cnt[u * TABLE_COLS + L - 1] : 0u;
     keep[i] = (int64_t)best >= (int64_t)bound[q] ? 0 : 1;
 }
@@ -752,7 +749,8 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
     if (ps.dense && ps.nq > 0) {
         const int64_t n = ps.npairs / ps.nq;
         // at least TK_USERS * TABLE_COLS threads: they stage the rows
-        const int bs = ps.nq >= 192 ? 256 : 128;
+        static_assert(TK_USERS * TABLE_COLS <= 256, "rows staged by one thread per cell");
+        const int bs = (ps.nq >= 192 || TK_USERS * TABLE_COLS > 128) ? 256 : 128;
         if (n > 0)
             hipLaunchKernelGGL(k_table_keep_dense, dim3((unsigned)((n + TK_USERS - 1) / TK_USERS),
                                                         (unsigned)((ps.nq + bs - 1) / bs)),
