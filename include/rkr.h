@@ -40,7 +40,7 @@
 #include <stdint.h>
 
 /* Columns (thresholds) per user of the rank table (rkr_rank_table). */
-#define RKR_TABLE_COLS 32
+#define RKR_TABLE_COLS 48
 
 #ifdef __cplusplus
 extern "C" {

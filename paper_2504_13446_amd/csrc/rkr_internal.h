@@ -115,7 +115,7 @@ struct CountArgs {
 // ent_th[u * TABLE_COLS + j], and cnt_out[u * TABLE_COLS + j] += the count of
 // items certainly above column j (a lower bound of the exact count).
 enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_TABLE = 2 };
-constexpr int TABLE_COLS = 32;
+constexpr int TABLE_COLS = 48;
 
 struct DeviceIndex;
 

@@ -24,7 +24,7 @@ RKR_F32, RKR_BF16 = 0, 1
 RKR_SCORE_F32, RKR_SCORE_BF16, RKR_SCORE_FP8 = 0, 1, 2
 SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
-TABLE_COLS = 32   # RKR_TABLE_COLS of include/rkr.h
+TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
            "rkr_query_table", "rkr_query_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")

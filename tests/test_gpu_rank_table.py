@@ -17,9 +17,13 @@ from paper_2504_13446_amd import rkr, workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# a loose bound on |low-precision score - spec score| relative to |u| max|p|,
-# and on the share of the exact counts the certain counts may miss
-REL_ERR = {"bf16": 2.0 ** -5, "fp8": 2.0 ** -2, "f32": 2.0 ** -16}
+# a loose bound, relative to |u| max|p|, on how far above a threshold an item
+# the certain count misses can score: the band edge sits one error bound E
+# above the threshold and the low-precision score is itself within E, so the
+# window is 2E (FP32 scores: E <= 2 (dpad + 2) 2^-24 |u| max|p|, 2E about
+# 2^-15.9 at dpad = 64); and on the share of the exact counts the certain
+# counts may miss
+REL_ERR = {"bf16": 2.0 ** -5, "fp8": 2.0 ** -2, "f32": 2.0 ** -14}
 MISS = {"bf16": 0.02, "fp8": 0.4, "f32": 0.001}
 
 
