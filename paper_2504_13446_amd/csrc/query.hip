@@ -432,15 +432,25 @@ __device__ inline void tq_bracket(const double *tt, const uint32_t *cc, double s
 // Brackets and estimates of the pairs u * nq + q go to query-major arrays
 // [q * n + u] (one segment per query for the selections) through an LDS tile
 // of 64 users x 32 queries, so the reads of t64 and the writes of the keys
-// both coalesce.
+// both coalesce; the tile's 64 table rows are read into LDS once.
 __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64,
                                                     const double *tab_t, const uint32_t *tab_cnt, uint64_t *key_lo,
                                                     uint64_t *key_hi, double *est) {
     __shared__ uint32_t s_lo[32][65], s_hi[32][65];
     __shared__ double s_e[32][65];
+    __shared__ double s_t[64][TABLE_COLS];
+    __shared__ uint32_t s_c[64][TABLE_COLS];
     const int64_t u0 = (int64_t)blockIdx.x * 64;
     const int q0 = blockIdx.y * 32;
     const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * TABLE_COLS; e += 256) {
+        const int uu = e / TABLE_COLS, j = e - uu * TABLE_COLS;
+        if (u0 + uu < n) {
+            s_t[uu][j] = tab_t[(u0 + uu) * TABLE_COLS + j];
+            s_c[uu][j] = tab_cnt[(u0 + uu) * TABLE_COLS + j];
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int uu = r * 8 + (tid >> 5), qq = tid & 31;
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m
         if (u < n && q < nq) {
             uint32_t rlo, rhi;
             double e;
-            tq_bracket(tab_t + u * TABLE_COLS, tab_cnt + u * TABLE_COLS, t64[u * nq + q], m, rlo, rhi, e);
+            tq_bracket(s_t[uu], s_c[uu], t64[u * nq + q], m, rlo, rhi, e);
             s_lo[qq][uu] = rlo;
             s_hi[qq][uu] = rhi;
             s_e[qq][uu] = e;
