@@ -138,7 +138,7 @@ struct RanksGraph {
     hipStream_t cs = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
-    DBuf qbuf, rbuf, pair_u, pair_q, t64, th, tl, tm, cnt, ctr, emit;
+    DBuf qbuf, rbuf, pair_u, pair_q, t64, cnt, ctr, emit;
     TaskSet ts;
     int64_t emit_cap = 0;
     void destroy() {
@@ -152,7 +152,7 @@ struct RanksGraph {
         destroy();
         if (cs) (void)hipStreamDestroy(cs);
         cs = nullptr;
-        DBuf *b[] = {&qbuf, &rbuf, &pair_u, &pair_q, &t64, &th, &tl, &tm, &cnt, &ctr, &emit};
+        DBuf *b[] = {&qbuf, &rbuf, &pair_u, &pair_q, &t64, &cnt, &ctr, &emit};
         for (DBuf *x : b) x->release();
         ts.release();
     }
@@ -169,7 +169,7 @@ struct rkr_index {
     DBuf coef_step[3];    // per-step coefficient maxima for steps of 1, 2, 4 blocks
     // per-call buffers
     Scratch sc;
-    DBuf pair_u, pair_q, pair_off, qm_pid, t64, th, tl, tm, cnt, seedflag, keys, sel, selrank, best, cand,
+    DBuf pair_u, pair_q, pair_off, qm_pid, t64, cnt, seedflag, keys, sel, selrank, best, cand,
         candkeys, ans, seedpid, surv, emit, ctr, bound, seedkth, kdev, sdev, cdev, segoff, seloff, bestoff,
         candoff, cursor, qcount, flags, allpid, keep;
     TaskSet ts_screen, ts_screen2, ts_exact;
@@ -317,8 +317,8 @@ extern "C" void rkr_destroy(rkr_index *x) {
     (void)hipStreamSynchronize(x->st);
     DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt,
                     &x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
-                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64, &x->th, &x->tl,
-                    &x->tm, &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
+                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
+                    &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
                     &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
                     &x->qcount, &x->flags, &x->allpid, &x->sp_len, &x->sp_pid, &x->sp_th, &x->sp_cnt};
@@ -630,17 +630,11 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     }
     // ---- 2. thresholds
     HIPCK(x->t64.ensure(npairs * 8));
-    HIPCK(x->th.ensure(npairs * 4));
-    HIPCK(x->tl.ensure(npairs * 4));
-    HIPCK(x->tm.ensure(npairs * 4));
     ps.t64 = x->t64.as<double>();
-    ps.th = x->th.as<float>();
-    ps.tl = x->tl.as<float>();
-    ps.tm = x->tm.as<float>();
     if (dense)
-        HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+        HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st));
     else
-        HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+        HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, st));
     {
         int flags = 0;
         HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
@@ -940,22 +934,16 @@ static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     HIPCK(x->pair_u.ensure(n * 4));
     HIPCK(x->pair_q.ensure(n * 4));
     HIPCK(x->t64.ensure(n * 8));
-    HIPCK(x->th.ensure(n * 4));
-    HIPCK(x->tl.ensure(n * 4));
-    HIPCK(x->tm.ensure(n * 4));
     HIPCK(x->cnt.ensure(n * 4));
     HIPCK(x->allpid.ensure(n * 4));
     HIPCK(x->ctr.ensure(64));
     ps.pair_u = x->pair_u.as<int32_t>();
     ps.pair_q = x->pair_q.as<int32_t>();
     ps.t64 = x->t64.as<double>();
-    ps.th = x->th.as<float>();
-    ps.tl = x->tl.as<float>();
-    ps.tm = x->tm.as<float>();
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
     HIPCK(launch_dense_pairs(n, 1, ps.pair_u, ps.pair_q, st));
-    HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, ps.t64, st));
     int flags = 0;
     HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
@@ -990,9 +978,6 @@ static rkr_status capture_ranks_graph(rkr_index *x) {
     HIPCK(g.pair_u.ensure(n * 4));
     HIPCK(g.pair_q.ensure(n * 4));
     HIPCK(g.t64.ensure(n * 8));
-    HIPCK(g.th.ensure(n * 4));
-    HIPCK(g.tl.ensure(n * 4));
-    HIPCK(g.tm.ensure(n * 4));
     HIPCK(g.cnt.ensure(n * 4));
     HIPCK(g.ctr.ensure(64));
     HIPCK(g.emit.ensure((size_t)g.emit_cap * 8));
@@ -1004,9 +989,6 @@ static rkr_status capture_ranks_graph(rkr_index *x) {
     ps.pair_u = g.pair_u.as<int32_t>();
     ps.pair_q = g.pair_q.as<int32_t>();
     ps.t64 = g.t64.as<double>();
-    ps.th = g.th.as<float>();
-    ps.tl = g.tl.as<float>();
-    ps.tm = g.tm.as<float>();
     g.ts.ntask = n;
     g.ts.ntask_pad = ntask_pad;
     g.ts.cap_total = ntask_pad;
@@ -1029,7 +1011,7 @@ static rkr_status capture_ranks_graph(rkr_index *x) {
     hipError_t e = launch_fill_u32(g.ctr.as<uint32_t>(), 0, 16, cs);
     if (e == hipSuccess) e = launch_dense_pairs(n, 1, ps.pair_u, ps.pair_q, cs);
     if (e == hipSuccess)
-        e = launch_thresh_dense(x->Um.p, n, g.qbuf.p, 1, x->d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, cs);
+        e = launch_thresh_dense(x->Um.p, n, g.qbuf.p, 1, x->d, x->mk, ps.t64, cs);
     if (e == hipSuccess) e = q_tasks_one_per_user(n, ntask_pad, ps, x->recheck ? 0 : 1, g.ts, cs);
     if (e == hipSuccess) e = launch_fill_u32(g.cnt.as<uint32_t>(), 0, n, cs);
     if (e == hipSuccess) e = launch_count(x->sk, CM_EXACT, a, (int)nsplit, xv, cs);
@@ -1121,9 +1103,6 @@ extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void
     x->stats.pairs = np;
     x->sc.reset();
     HIPCK(x->t64.ensure(np * 8));
-    HIPCK(x->th.ensure(np * 4));
-    HIPCK(x->tl.ensure(np * 4));
-    HIPCK(x->tm.ensure(np * 4));
     HIPCK(x->flags.ensure(16));
     auto take = [&](int64_t bytes) { return x->sc.take(bytes); };
     uint64_t *key_lo = (uint64_t *)take(np * 8), *key_hi = (uint64_t *)take(np * 8);
@@ -1148,8 +1127,7 @@ extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void
     // step 1: u.q for every (user, query) (spec FP64 dots), brackets, estimates
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(Qm, (int64_t)nq * x->d, x->mk, x->flags.as<int>(), st));
-    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), x->th.as<float>(),
-                              x->tl.as<float>(), x->tm.as<float>(), st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), st));
     HIPCK(q_tqb_bounds(n, nq, x->m, x->t64.as<double>(), x->tab_t.as<double>(), x->tab_cnt.as<uint32_t>(), key_lo,
                        key_hi, est, st));
     // R_lo_k, R_hi_k per query and the case of step 2
@@ -1234,21 +1212,15 @@ extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_
     HIPCK(x->pair_u.ensure(npairs * 4));
     HIPCK(x->pair_q.ensure(npairs * 4));
     HIPCK(x->t64.ensure(npairs * 8));
-    HIPCK(x->th.ensure(npairs * 4));
-    HIPCK(x->tl.ensure(npairs * 4));
-    HIPCK(x->tm.ensure(npairs * 4));
     HIPCK(x->cnt.ensure(npairs * 4));
     HIPCK(x->ctr.ensure(64));
     ps.pair_u = x->pair_u.as<int32_t>();
     ps.pair_q = x->pair_q.as<int32_t>();
     ps.t64 = x->t64.as<double>();
-    ps.th = x->th.as<float>();
-    ps.tl = x->tl.as<float>();
-    ps.tm = x->tm.as<float>();
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(Qm, (int64_t)nq * d, x->mk, x->flags.as<int>(), st));
     HIPCK(launch_dense_pairs(n, nq, ps.pair_u, ps.pair_q, st));
-    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, ps.th, ps.tl, ps.tm, st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st));
     // best users by t/|u| (select) + stratified users, marked in a pair flag array
     const int top = (int)std::min<int64_t>(std::min<int64_t>(pairs_per_query / 2, 4096), n);
     const int strat = (int)std::min<int64_t>(pairs_per_query - pairs_per_query / 2, n);
@@ -1340,12 +1312,8 @@ extern "C" rkr_status rkr_predict(rkr_index *x, int32_t nq, const void *Qm, floa
     HIPCK(x->pair_u.ensure(npairs * 4));
     HIPCK(x->pair_q.ensure(npairs * 4));
     HIPCK(x->t64.ensure(npairs * 8));
-    HIPCK(x->th.ensure(npairs * 4));
-    HIPCK(x->tl.ensure(npairs * 4));
-    HIPCK(x->tm.ensure(npairs * 4));
     HIPCK(launch_dense_pairs(n, nq, x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), st));
-    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), x->th.as<float>(),
-                              x->tl.as<float>(), x->tm.as<float>(), st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), st));
     HIPCK(est_infer(x->est, nullptr, nullptr, npairs, x->pair_u.as<int32_t>(), x->t64.as<double>(),
                     x->unorm3.as<double>(), out, nq, n, st));
     HIPCK(hipStreamSynchronize(st));

@@ -54,8 +54,7 @@ struct PairSet {
     int32_t *pair_u = nullptr, *pair_q = nullptr;
     int64_t *pair_off = nullptr;    // CSR only: [n + 1]
     int32_t *qm_pid = nullptr;      // CSR only: pid of query-major candidate j
-    double *t64 = nullptr;
-    float *th = nullptr, *tl = nullptr, *tm = nullptr;
+    double *t64 = nullptr;   // FP64 threshold per pair
 };
 
 // Entry lists of a set of tasks (one task = one user and its live pairs).
@@ -114,10 +113,9 @@ hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
 hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out,
                             hipStream_t st);
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
-                         const void *Qm, int d, int mk, double *t64, float *th, float *tl, float *tm,
-                         hipStream_t st);
+                         const void *Qm, int d, int mk, double *t64, hipStream_t st);
 hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
-                               float *th, float *tl, float *tm, hipStream_t st);
+                               hipStream_t st);
 hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
                               const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                               unsigned long long *flips, hipStream_t st);

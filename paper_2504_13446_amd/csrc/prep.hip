@@ -242,11 +242,11 @@ __global__ void k_step_coef(const double *coef, int64_t nblk, int nib, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// FP64 thresholds t(u,q) = spec dot, with the FP32 values bracketing it.
+// FP64 thresholds t(u,q) = spec dot (the FP32 values bracketing it are
+// derived where the count kernel's entries are filled).
 // ---------------------------------------------------------------------------
 __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs,
-                         const void *Um, const void *Qm, int d, int mk, double *t64, float *th,
-                         float *tl, float *tm) {
+                         const void *Um, const void *Qm, int d, int mk, double *t64) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npairs) return;
     const int64_t u = pair_u[i], q = pair_q[i];
@@ -254,9 +254,6 @@ __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
     for (int k = 0; k < d; ++k)
         acc = fma(master_elem(Um, mk, u * d + k), master_elem(Qm, mk, q * d + k), acc);
     t64[i] = acc;
-    th[i] = f32_round_up(acc);
-    tl[i] = f32_round_down(acc);
-    tm[i] = (float)acc;
 }
 
 // Dense thresholds, register-tiled: a block computes 64 users x 64 queries
@@ -264,7 +261,7 @@ __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
 // dimensions at a time; every dot still runs its fma chain in dimension
 // order, so the values equal the per-pair kernel's.  pid = u * nq + q.
 __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk,
-                                                      double *t64, float *th, float *tl, float *tm) {
+                                                      double *t64) {
     // rows of 66 doubles: 16-byte aligned, so a thread's four consecutive
     // operands are two 16-byte LDS reads
     __shared__ __attribute__((aligned(16))) double su[32][66];
@@ -300,12 +297,7 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
         for (int y = 0; y < 4; ++y) {
             const int q = qb + tx * 4 + y;
             if (q >= nq) continue;
-            const int64_t i = u * nq + q;
-            const double v = acc[x][y];
-            t64[i] = v;
-            th[i] = f32_round_up(v);
-            tl[i] = f32_round_down(v);
-            tm[i] = (float)v;
+            t64[u * nq + q] = acc[x][y];
         }
     }
 }
@@ -485,19 +477,18 @@ hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t n
 }
 
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
-                         const void *Qm, int d, int mk, double *t64, float *th, float *tl, float *tm,
-                         hipStream_t st) {
+                         const void *Qm, int d, int mk, double *t64, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_thresh, dim3(nblocks(npairs, 256)), dim3(256), 0, st, pair_u, pair_q, npairs,
-                       Um, Qm, d, mk, t64, th, tl, tm);
+                       Um, Qm, d, mk, t64);
     return hipGetLastError();
 }
 
 hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
-                               float *th, float *tl, float *tm, hipStream_t st) {
+                               hipStream_t st) {
     if (n <= 0 || nq <= 0) return hipSuccess;
     dim3 g((unsigned)((nq + 63) / 64), (unsigned)((n + 63) / 64));
-    hipLaunchKernelGGL(k_thresh_dense, g, dim3(256), 0, st, Um, n, Qm, nq, d, mk, t64, th, tl, tm);
+    hipLaunchKernelGGL(k_thresh_dense, g, dim3(256), 0, st, Um, n, Qm, nq, d, mk, t64);
     return hipGetLastError();
 }
 

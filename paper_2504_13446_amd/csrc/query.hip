@@ -218,8 +218,8 @@ __global__ void k_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks) {
 // One entry per user (single query, every user): task t = user t, block b's
 // entries at 32 b + lane.  Built without host round trips so the whole
 // single-query pipeline can be captured in a graph.
-__global__ void k_tasks_one_per_user(int64_t n, int64_t ntask_pad, const float *th, const float *tl,
-                                     const float *tm, int plain, int32_t *task_user, int32_t *len,
+__global__ void k_tasks_one_per_user(int64_t n, int64_t ntask_pad, const double *t64, int plain,
+                                     int32_t *task_user, int32_t *len,
                                      int64_t *blk_base, int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt,
                                      float *ent_th, float *ent_tl, float *ent_tm) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,11 +231,12 @@ __global__ void k_tasks_one_per_user(int64_t n, int64_t ntask_pad, const float *
     ent_pid[t] = real ? (int32_t)t : 0;
     ent_q[t] = 0;
     ent_cnt[t] = 0;
-    const float h = real ? (plain ? tm[t] : th[t]) : 0.0f;
-    const float l = real ? (plain ? tm[t] : tl[t]) : 0.0f;
-    ent_th[t] = h;
-    ent_tl[t] = l;
-    ent_tm[t] = real ? tm[t] : 0.0f;
+    // the FP32 values bracketing t (see k_fill_entries)
+    const double tv = real ? t64[t] : 0.0;
+    const float tm = (float)tv;
+    ent_th[t] = real ? (plain ? tm : f32_round_up(tv)) : 0.0f;
+    ent_tl[t] = real ? (plain ? tm : f32_round_down(tv)) : 0.0f;
+    ent_tm[t] = real ? tm : 0.0f;
 }
 __global__ void k_copy_words(const uint32_t *src, uint32_t *dst, int64_t nw) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -737,7 +738,7 @@ hipError_t q_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int
 }
 hipError_t q_tasks_one_per_user(int64_t n, int64_t ntask_pad, const PairSet &ps, int plain, TaskSet &ts,
                                 hipStream_t st) {
-    LAUNCH1D(k_tasks_one_per_user, ntask_pad, n, ntask_pad, ps.th, ps.tl, ps.tm, plain, ts.task_user, ts.len,
+    LAUNCH1D(k_tasks_one_per_user, ntask_pad, n, ntask_pad, ps.t64, plain, ts.task_user, ts.len,
              ts.blk_base, ts.ent_pid, ts.ent_q, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     return hipGetLastError();
 }

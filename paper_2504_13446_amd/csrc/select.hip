@@ -300,8 +300,8 @@ template <bool SCREEN>
 __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const int64_t *task_start,
                                                       const int32_t *len, int64_t ntask, const int64_t *blk_base,
                                                       int64_t nblk, int64_t cap_total,
-                                                      const int32_t *pair_q, const float *th, const float *tl,
-                                                      const float *tm, int plain, const int32_t *bound,
+                                                      const int32_t *pair_q, const double *t64, int plain,
+                                                      const int32_t *bound,
                                                       const uint32_t *rem_init, int32_t *ent_pid,
                                                       uint32_t *ent_cnt, float *ent_th,
                                                       float *ent_tl, float *ent_tm) {
@@ -320,14 +320,18 @@ __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const
             if (t < ntask && j < len[t]) {
                 const int32_t pid = pids[task_start[t] + j];
                 s_pid[l][jj] = pid;
-                // plain mode compares the score with fl32(t) itself: both edges = fl32(t)
-                s_a[l][jj] = plain ? tm[pid] : th[pid];
+                // the FP32 values bracketing t: the smallest float >= t, the
+                // largest <= t, and fl32(t); plain mode compares the score
+                // with fl32(t) itself (both edges = fl32(t))
+                const double tv = t64[pid];
+                const float tm = (float)tv;
+                s_a[l][jj] = plain ? tm : f32_round_up(tv);
                 if constexpr (SCREEN) {
                     // a fresh pair starts with B[q] - 1, a carried one with its remaining budget
                     s_b[l][jj] = __uint_as_float(rem_init ? rem_init[pid] : (uint32_t)(bound[pair_q[pid]] - 1));
                 } else {
-                    s_b[l][jj] = plain ? tm[pid] : tl[pid];
-                    s_c[l][jj] = tm[pid];
+                    s_b[l][jj] = plain ? tm : f32_round_down(tv);
+                    s_c[l][jj] = tm;
                 }
             }
         }
@@ -402,11 +406,11 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     if ((e = ts.reserve_entries(cap_total)) != hipSuccess) return e;
     if (bound)
         hipLaunchKernelGGL(k_fill_entries<true>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
-                           ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound,
+                           ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.t64, plain, bound,
                            rem_init, ts.ent_pid, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     else
         hipLaunchKernelGGL(k_fill_entries<false>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
-                           ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.th, ps.tl, ps.tm, plain, bound,
+                           ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.t64, plain, bound,
                            rem_init, ts.ent_pid, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     ts.ntask = ntask;
     ts.ntask_pad = ntask_pad;
