@@ -628,11 +628,15 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
             return fail(RKR_E_INVALID, "candidate ids out of range or duplicated within a list");
         if (e != hipSuccess) return fail_hip(e, "build_csr_pairs");
     }
-    // ---- 2. thresholds
+    // ---- 2. thresholds (dense batches without the estimator: with the
+    // default seed keys written from the same register tile)
     HIPCK(x->t64.ensure(npairs * 8));
+    HIPCK(x->keys.ensure(npairs * 8));
     ps.t64 = x->t64.as<double>();
+    const bool keys_fused = dense && x->qo.use_estimator == 0;
     if (dense)
-        HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st));
+        HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st, keys_fused ? x->unorm3.as<double>() : nullptr,
+                                  keys_fused ? x->keys.as<uint64_t>() : nullptr));
     else
         HIPCK(launch_thresh(ps.pair_u, ps.pair_q, npairs, x->Um.p, Qm, d, x->mk, ps.t64, st));
     {
@@ -691,7 +695,8 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         HIPCK(x->cdev.ensure(nq * 8));
         HIPCK(hipMemcpyAsync(x->cdev.p, c, nq * 8, hipMemcpyHostToDevice, st));
     }
-    HIPCK(q_seed_keys(v, ps.pair_u, ps.t64, x->unorm3.as<double>(), pred, npairs, x->keys.as<uint64_t>(), st));
+    if (!keys_fused)
+        HIPCK(q_seed_keys(v, ps.pair_u, ps.t64, x->unorm3.as<double>(), pred, npairs, x->keys.as<uint64_t>(), st));
     HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
                         x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));
     HIPCK(x->seedflag.ensure(npairs));

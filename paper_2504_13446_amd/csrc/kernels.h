@@ -114,8 +114,9 @@ hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t n
                             hipStream_t st);
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
                          const void *Qm, int d, int mk, double *t64, hipStream_t st);
+// with keys (and unorm3), also the default seed keys, query-major [nq][n]
 hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
-                               hipStream_t st);
+                               hipStream_t st, const double *unorm3 = nullptr, uint64_t *keys = nullptr);
 hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
                               const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                               unsigned long long *flips, hipStream_t st);

@@ -260,8 +260,10 @@ __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
 // (4 x 4 per thread) with both operands staged in LDS as doubles, 32
 // dimensions at a time; every dot still runs its fma chain in dimension
 // order, so the values equal the per-pair kernel's.  pid = u * nq + q.
+// With keys, each pair's default seed key is written too (query-major, as
+// the seed-key kernel writes it: (order key of fl32(-t / |u|)) << 32 | u).
 __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk,
-                                                      double *t64) {
+                                                      double *t64, const double *unorm3, uint64_t *keys) {
     // rows of 66 doubles: 16-byte aligned, so a thread's four consecutive
     // operands are two 16-byte LDS reads
     __shared__ __attribute__((aligned(16))) double su[32][66];
@@ -298,6 +300,11 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
             const int q = qb + tx * 4 + y;
             if (q >= nq) continue;
             t64[u * nq + q] = acc[x][y];
+            if (keys) {
+                const double nu = unorm3[3 * u + 2];
+                const float h = nu > 0.0 ? (float)(-acc[x][y] / nu) : 0.0f;
+                keys[(int64_t)q * n + u] = ((uint64_t)f32_order_key(h) << 32) | (uint32_t)u;
+            }
         }
     }
 }
@@ -485,10 +492,10 @@ hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
 }
 
 hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk, double *t64,
-                               hipStream_t st) {
+                               hipStream_t st, const double *unorm3, uint64_t *keys) {
     if (n <= 0 || nq <= 0) return hipSuccess;
     dim3 g((unsigned)((nq + 63) / 64), (unsigned)((n + 63) / 64));
-    hipLaunchKernelGGL(k_thresh_dense, g, dim3(256), 0, st, Um, n, Qm, nq, d, mk, t64);
+    hipLaunchKernelGGL(k_thresh_dense, g, dim3(256), 0, st, Um, n, Qm, nq, d, mk, t64, unorm3, keys);
     return hipGetLastError();
 }
 
