@@ -53,7 +53,7 @@ typedef enum {
     RKR_E_INVALID = 1,     /* an argument is out of range (message says which) */
     RKR_E_NOMEM = 2,       /* device or host allocation failed */
     RKR_E_DEVICE = 3,      /* a HIP runtime call failed */
-    RKR_E_UNSUPPORTED = 4, /* valid request outside this build's limits */
+    RKR_E_UNSUPPORTED = 4, /* valid request outside the library's limits */
     RKR_E_STATE = 5        /* the index lacks a part the call needs */
 } rkr_status;
 
