@@ -105,7 +105,10 @@ hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, 
 
 // ---------------------------------------------------------------------------
 // Segmented selection of the K smallest 64-bit keys (keys unique within a
-// segment).  One workgroup per segment; output sorted ascending.
+// segment; K <= SEL_MAX, which every caller's limit on k guarantees).  One
+// workgroup per segment: 8-bit radix passes over the segment narrow a bucket
+// until the keys at or below it fit in LDS, one more pass gathers them, and a
+// bitonic sort orders them; output sorted ascending.
 // ---------------------------------------------------------------------------
 constexpr int SEL_BS = 1024;
 constexpr int SEL_MAX = 4096;
@@ -185,7 +188,12 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
                 sh_need = need - cum;
                 sh_prefix = pre | ((uint64_t)v << shift);
                 sh_mask = msk | (255ull << shift);
-                if ((int64_t)hist[0][v] == need - cum) sh_done = 1;
+                // Keys at or below the bucket's upper end: K - (need - cum)
+                // below the bucket plus the bucket itself.  They hold the K
+                // smallest, so once they fit in LDS the sort finishes the job
+                // (no further pass over the segment).
+                const int64_t at_or_below = K - (need - cum) + (int64_t)hist[0][v];
+                if ((int64_t)hist[0][v] == need - cum || at_or_below <= SEL_MAX) sh_done = 1;
             }
             __syncthreads();
             if (sh_done) break;
