@@ -293,6 +293,34 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
         }
         __syncthreads();
     }
+    const int64_t u0 = ub + ty * 4;
+    const int q0 = qb + tx * 4;
+    if (u0 + 3 < n && q0 + 3 < nq && ((n | nq) & 1) == 0) {
+        // full tile, even sizes: a thread's four queries are adjacent in t64
+        // and its four users adjacent in the query-major keys, so both go
+        // out as 16-byte stores (the indices below are even)
+        for (int x = 0; x < 4; ++x) {
+            double2 *o = (double2 *)&t64[(u0 + x) * nq + q0];
+            o[0] = make_double2(acc[x][0], acc[x][1]);
+            o[1] = make_double2(acc[x][2], acc[x][3]);
+        }
+        if (keys) {
+            uint64_t key[4][4];
+            for (int x = 0; x < 4; ++x) {
+                const double nu = unorm3[3 * (u0 + x) + 2];
+                for (int y = 0; y < 4; ++y) {
+                    const float h = nu > 0.0 ? (float)(-acc[x][y] / nu) : 0.0f;
+                    key[y][x] = ((uint64_t)f32_order_key(h) << 32) | (uint32_t)(u0 + x);
+                }
+            }
+            for (int y = 0; y < 4; ++y) {
+                ulonglong2 *o = (ulonglong2 *)&keys[(int64_t)(q0 + y) * n + u0];
+                o[0] = make_ulonglong2(key[y][0], key[y][1]);
+                o[1] = make_ulonglong2(key[y][2], key[y][3]);
+            }
+        }
+        return;
+    }
     for (int x = 0; x < 4; ++x) {
         const int64_t u = ub + ty * 4 + x;
         if (u >= n) continue;
