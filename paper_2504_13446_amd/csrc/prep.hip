@@ -264,8 +264,8 @@ __global__ void k_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t n
 // the seed-key kernel writes it: (order key of fl32(-t / |u|)) << 32 | u).
 __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq, int d, int mk,
                                                       double *t64, const double *unorm3, uint64_t *keys) {
-    // rows of 66 doubles: 16-byte aligned, so a thread's four consecutive
-    // operands are two 16-byte LDS reads
+    // rows of 66 doubles: 16-byte aligned, so each adjacent operand pair of a
+    // thread is one 16-byte LDS read
     __shared__ __attribute__((aligned(16))) double su[32][66];
     __shared__ __attribute__((aligned(16))) double sq[32][66];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -285,47 +285,52 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
         __syncthreads();
         const int kmax = min(32, d - k0);
         for (int kk = 0; kk < kmax; ++kk) {
-            const double2 a01 = *(const double2 *)&su[kk][ty * 4], a23 = *(const double2 *)&su[kk][ty * 4 + 2];
-            const double2 b01 = *(const double2 *)&sq[kk][tx * 4], b23 = *(const double2 *)&sq[kk][tx * 4 + 2];
+            // a thread's users (queries) are tile columns 2t, 2t + 1, 32 + 2t,
+            // 33 + 2t: sixteen lanes read 256 contiguous bytes per 16-byte
+            // read, one per LDS bank
+            const double2 a01 = *(const double2 *)&su[kk][ty * 2], a23 = *(const double2 *)&su[kk][32 + ty * 2];
+            const double2 b01 = *(const double2 *)&sq[kk][tx * 2], b23 = *(const double2 *)&sq[kk][32 + tx * 2];
             const double a[4] = {a01.x, a01.y, a23.x, a23.y}, b[4] = {b01.x, b01.y, b23.x, b23.y};
             for (int x = 0; x < 4; ++x)
                 for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
         }
         __syncthreads();
     }
-    const int64_t u0 = ub + ty * 4;
-    const int q0 = qb + tx * 4;
-    if (u0 + 3 < n && q0 + 3 < nq && ((n | nq) & 1) == 0) {
-        // full tile, even sizes: a thread's four queries are adjacent in t64
-        // and its four users adjacent in the query-major keys, so both go
-        // out as 16-byte stores (the indices below are even)
+    // tile columns of x (users) and y (queries): 0, 1 -> 2t, 2t + 1; 2, 3 -> 32 + 2t, 33 + 2t
+    const int64_t ua = ub + ty * 2, uc = ub + 32 + ty * 2;
+    const int qa = qb + tx * 2, qc = qb + 32 + tx * 2;
+    if (uc + 1 < n && qc + 1 < nq && ((n | nq) & 1) == 0) {
+        // full tile, even sizes: a thread's queries come in adjacent pairs in
+        // t64 and its users in adjacent pairs in the query-major keys, so
+        // both go out as 16-byte stores (the indices below are even)
         for (int x = 0; x < 4; ++x) {
-            double2 *o = (double2 *)&t64[(u0 + x) * nq + q0];
-            o[0] = make_double2(acc[x][0], acc[x][1]);
-            o[1] = make_double2(acc[x][2], acc[x][3]);
+            const int64_t u = (x < 2 ? ua : uc) + (x & 1);
+            *(double2 *)&t64[u * nq + qa] = make_double2(acc[x][0], acc[x][1]);
+            *(double2 *)&t64[u * nq + qc] = make_double2(acc[x][2], acc[x][3]);
         }
         if (keys) {
             uint64_t key[4][4];
             for (int x = 0; x < 4; ++x) {
-                const double nu = unorm3[3 * (u0 + x) + 2];
+                const int64_t u = (x < 2 ? ua : uc) + (x & 1);
+                const double nu = unorm3[3 * u + 2];
                 for (int y = 0; y < 4; ++y) {
                     const float h = nu > 0.0 ? (float)(-acc[x][y] / nu) : 0.0f;
-                    key[y][x] = ((uint64_t)f32_order_key(h) << 32) | (uint32_t)(u0 + x);
+                    key[y][x] = ((uint64_t)f32_order_key(h) << 32) | (uint32_t)u;
                 }
             }
             for (int y = 0; y < 4; ++y) {
-                ulonglong2 *o = (ulonglong2 *)&keys[(int64_t)(q0 + y) * n + u0];
-                o[0] = make_ulonglong2(key[y][0], key[y][1]);
-                o[1] = make_ulonglong2(key[y][2], key[y][3]);
+                const int64_t q = (y < 2 ? qa : qc) + (y & 1);
+                *(ulonglong2 *)&keys[q * n + ua] = make_ulonglong2(key[y][0], key[y][1]);
+                *(ulonglong2 *)&keys[q * n + uc] = make_ulonglong2(key[y][2], key[y][3]);
             }
         }
         return;
     }
     for (int x = 0; x < 4; ++x) {
-        const int64_t u = ub + ty * 4 + x;
+        const int64_t u = (x < 2 ? ua : uc) + (x & 1);
         if (u >= n) continue;
         for (int y = 0; y < 4; ++y) {
-            const int q = qb + tx * 4 + y;
+            const int q = (y < 2 ? qa : qc) + (y & 1);
             if (q >= nq) continue;
             t64[u * nq + q] = acc[x][y];
             if (keys) {
