@@ -106,13 +106,14 @@ hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, 
 // ---------------------------------------------------------------------------
 // Segmented selection of the K smallest 64-bit keys (keys unique within a
 // segment; K <= SEL_MAX, which every caller's limit on k guarantees).  One
-// workgroup per segment: 8-bit radix passes over the segment narrow a bucket
+// workgroup per segment: radix passes over the segment narrow a bucket
 // until the keys at or below it fit in LDS, one more pass gathers them, and a
 // bitonic sort orders them; output sorted ascending.
 // ---------------------------------------------------------------------------
 constexpr int SEL_BS = 1024;
 constexpr int SEL_MAX = 4096;
 constexpr int SEL_UNROLL = 8;
+constexpr int SEL_HIST = 16 * 256;     // histogram counters in LDS
 
 __device__ inline void lds_bitonic_sort(uint64_t *s, int npow2) {
     for (int k = 2; k <= npow2; k <<= 1) {
@@ -138,7 +139,9 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
     __shared__ uint32_t sh_cnt;
     __shared__ uint64_t sh_prefix, sh_mask;
     __shared__ int64_t sh_need;
-    __shared__ int sh_done;
+    __shared__ int sh_done, sh_bin;
+    __shared__ int64_t sh_cum;
+    __shared__ uint32_t sh_wsum[SEL_BS / 64];
     const int seg = blockIdx.x;
     const int64_t b = seg_off[seg], len = seg_off[seg + 1] - b;
     int64_t K = kk[seg];
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
     const int64_t ob = out_off[seg];
     if (K <= 0) return;
     const uint64_t *x = keys + b;
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
     uint64_t T;   // select keys <= T
     if (len <= SEL_MAX) {
@@ -154,10 +157,20 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
     } else {
         if (tid == 0) { sh_prefix = 0; sh_mask = 0; sh_need = K; sh_done = 0; }
         __syncthreads();
-        for (int shift = 56; shift >= 0; shift -= 8) {
-            for (int i = tid; i < 16 * 256; i += SEL_BS) (&hist[0][0])[i] = 0;
+        uint32_t *hf = &hist[0][0];
+        // Digits: bits 63..53 first (an order key's sign, exponent and two
+        // mantissa bits, so one segment's keys spread over many bins), then
+        // 8-bit digits, the last of 5 bits.
+        int width = 11, shift = 53;
+        for (;;) {
+            const int nbins = 1 << width;
+            const int ncopy = min(16, SEL_HIST / nbins);    // copies of the histogram, shared by waves
+            const uint64_t dmask = (uint64_t)(nbins - 1);
+            for (int i = tid; i < SEL_HIST; i += SEL_BS) hf[i] = 0;
+            if (tid == 0) { sh_bin = 0; sh_cum = 0; }
             __syncthreads();
             const uint64_t pre = sh_prefix, msk = sh_mask;
+            uint32_t *hw = hf + (wave % ncopy) * nbins;
             // SEL_UNROLL independent loads in flight per thread
             for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * SEL_UNROLL) {
                 uint64_t v[SEL_UNROLL];
@@ -169,34 +182,58 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
 #pragma unroll
                 for (int r = 0; r < SEL_UNROLL; ++r)
                     if (i0 + (int64_t)r * SEL_BS < len && (v[r] & msk) == pre)
-                        atomicAdd(&hist[wave][(v[r] >> shift) & 255], 1u);
+                        atomicAdd(&hw[(v[r] >> shift) & dmask], 1u);
             }
             __syncthreads();
-            if (tid < 256) {
-                uint32_t t = 0;
-                for (int w = 0; w < 16; ++w) t += hist[w][tid];
-                hist[0][tid] = t;
+            for (int i = tid; i < nbins; i += SEL_BS) {
+                uint32_t t = hf[i];
+                for (int c = 1; c < ncopy; ++c) t += hf[c * nbins + i];
+                hf[i] = t;
+            }
+            __syncthreads();
+            // The bin holding the need-th key: each thread sums a run of
+            // `per` bins, and a block-wide prefix sum of the runs names the
+            // one run (and then the bin) the need-th key falls in.
+            const int per = nbins > SEL_BS ? nbins / SEL_BS : 1;
+            const int64_t need = sh_need;
+            uint32_t mine = 0;
+            if (tid * per < nbins)
+                for (int j = 0; j < per; ++j) mine += hf[tid * per + j];
+            uint32_t incl = mine;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            if (lane == 63) sh_wsum[wave] = incl;
+            __syncthreads();
+            uint32_t wpre = 0;
+            for (int w = 0; w < wave; ++w) wpre += sh_wsum[w];
+            const int64_t before = (int64_t)wpre + incl - mine;    // keys in the bins ahead of this run
+            if (mine > 0 && before < need && need <= before + (int64_t)mine) {
+                int64_t cum = before;
+                int v = tid * per;
+                while (cum + (int64_t)hf[v] < need) { cum += hf[v]; ++v; }
+                sh_bin = v;
+                sh_cum = cum;
             }
             __syncthreads();
             if (tid == 0) {
-                int64_t need = sh_need, cum = 0;
-                int v = 0;
-                for (; v < 256; ++v) {
-                    if (cum + hist[0][v] >= need) break;
-                    cum += hist[0][v];
-                }
+                const int v = sh_bin;
+                const int64_t cum = sh_cum;
                 sh_need = need - cum;
                 sh_prefix = pre | ((uint64_t)v << shift);
-                sh_mask = msk | (255ull << shift);
+                sh_mask = msk | (dmask << shift);
                 // Keys at or below the bucket's upper end: K - (need - cum)
                 // below the bucket plus the bucket itself.  They hold the K
                 // smallest, so once they fit in LDS the sort finishes the job
                 // (no further pass over the segment).
-                const int64_t at_or_below = K - (need - cum) + (int64_t)hist[0][v];
-                if ((int64_t)hist[0][v] == need - cum || at_or_below <= SEL_MAX) sh_done = 1;
+                const int64_t at_or_below = K - (need - cum) + (int64_t)hf[v];
+                if ((int64_t)hf[v] == need - cum || at_or_below <= SEL_MAX) sh_done = 1;
             }
             __syncthreads();
-            if (sh_done) break;
+            if (sh_done || shift == 0) break;
+            width = shift < 8 ? shift : 8;
+            shift -= width;
         }
         T = sh_prefix | ~sh_mask;
     }
