@@ -1,6 +1,8 @@
 // query.hip -- per-call helper kernels of the query pipeline: seed keys,
 // seed marking, compaction of flagged pairs, survivor collection, the per-query
 // rank bound and the answer assembly.
+#include <algorithm>
+
 #include "query.h"
 
 namespace rkr {
@@ -433,16 +435,16 @@ __device__ inline void tq_bracket(const double *tt, const uint32_t *cc, double s
 // Brackets and estimates of the pairs u * nq + q go to query-major arrays
 // [q * n + u] (one segment per query for the selections) through an LDS tile
 // of 64 users x 32 queries, so the reads of t64 and the writes of the keys
-// both coalesce; the tile's 64 table rows are read into LDS once.
+// both coalesce.  A workgroup takes 64 users and a run of qt_per such query
+// tiles, so the users' table rows, read into LDS once, serve all of them.
 __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64,
                                                     const double *tab_t, const uint32_t *tab_cnt, uint64_t *key_lo,
-                                                    uint64_t *key_hi, double *est) {
+                                                    uint64_t *key_hi, double *est, int qt_per) {
     __shared__ uint32_t s_lo[32][65], s_hi[32][65];
     __shared__ double s_e[32][65];
     __shared__ double s_t[64][TABLE_COLS];
     __shared__ uint32_t s_c[64][TABLE_COLS];
     const int64_t u0 = (int64_t)blockIdx.x * 64;
-    const int q0 = blockIdx.y * 32;
     const int tid = threadIdx.x;
     for (int e = tid; e < 64 * TABLE_COLS; e += 256) {
         const int uu = e / TABLE_COLS, j = e - uu * TABLE_COLS;
@@ -452,32 +454,37 @@ __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m
         }
     }
     __syncthreads();
+    const int qt_end = min((nq + 31) / 32, (int)(blockIdx.y + 1) * qt_per);
+    for (int qt = blockIdx.y * qt_per; qt < qt_end; ++qt) {
+        const int q0 = qt * 32;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int uu = r * 8 + (tid >> 5), qq = tid & 31;
-        const int64_t u = u0 + uu;
-        const int q = q0 + qq;
-        if (u < n && q < nq) {
-            uint32_t rlo, rhi;
-            double e;
-            tq_bracket(s_t[uu], s_c[uu], t64[u * nq + q], m, rlo, rhi, e);
-            s_lo[qq][uu] = rlo;
-            s_hi[qq][uu] = rhi;
-            s_e[qq][uu] = e;
+        for (int r = 0; r < 8; ++r) {
+            const int uu = r * 8 + (tid >> 5), qq = tid & 31;
+            const int64_t u = u0 + uu;
+            const int q = q0 + qq;
+            if (u < n && q < nq) {
+                uint32_t rlo, rhi;
+                double e;
+                tq_bracket(s_t[uu], s_c[uu], t64[u * nq + q], m, rlo, rhi, e);
+                s_lo[qq][uu] = rlo;
+                s_hi[qq][uu] = rhi;
+                s_e[qq][uu] = e;
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int qq = r * 4 + (tid >> 6), uu = tid & 63;
-        const int64_t u = u0 + uu;
-        const int q = q0 + qq;
-        if (u < n && q < nq) {
-            const int64_t j = (int64_t)q * n + u;
-            key_lo[j] = ((uint64_t)s_lo[qq][uu] << 32) | (uint64_t)u;
-            key_hi[j] = ((uint64_t)s_hi[qq][uu] << 32) | (uint64_t)u;
-            est[j] = s_e[qq][uu];
+        for (int r = 0; r < 8; ++r) {
+            const int qq = r * 4 + (tid >> 6), uu = tid & 63;
+            const int64_t u = u0 + uu;
+            const int q = q0 + qq;
+            if (u < n && q < nq) {
+                const int64_t j = (int64_t)q * n + u;
+                key_lo[j] = ((uint64_t)s_lo[qq][uu] << 32) | (uint64_t)u;
+                key_hi[j] = ((uint64_t)s_hi[qq][uu] << 32) | (uint64_t)u;
+                est[j] = s_e[qq][uu];
+            }
         }
+        __syncthreads();    // the next query tile rewrites this one's LDS
     }
 }
 
@@ -775,8 +782,14 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
 hipError_t q_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
                         uint64_t *key_lo, uint64_t *key_hi, double *est, hipStream_t st) {
     if (n <= 0 || nq <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tqb_bounds, dim3((unsigned)((n + 63) / 64), (unsigned)((nq + 31) / 32)), dim3(256), 0, st, n,
-                       nq, m, t64, tab_t, tab_cnt, key_lo, key_hi, est);
+    // enough workgroups to fill the chip (about 2048), each with as many
+    // query tiles as that allows
+    const int64_t gx = (n + 63) / 64, ntile = (nq + 31) / 32;
+    const int64_t gy_want = std::max<int64_t>(1, std::min<int64_t>(ntile, (2048 + gx - 1) / gx));
+    const int qt_per = (int)((ntile + gy_want - 1) / gy_want);
+    const unsigned gy = (unsigned)((ntile + qt_per - 1) / qt_per);
+    hipLaunchKernelGGL(k_tqb_bounds, dim3((unsigned)gx, gy), dim3(256), 0, st, n, nq, m, t64, tab_t, tab_cnt, key_lo,
+                       key_hi, est, qt_per);
     return hipGetLastError();
 }
 hipError_t q_tqb_kth(int nq, const int32_t *k, const double *c, const uint64_t *sel_lo, const uint64_t *sel_hi,
