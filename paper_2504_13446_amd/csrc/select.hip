@@ -180,9 +180,22 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
                     v[r] = i < len ? x[i] : 0ull;
                 }
 #pragma unroll
-                for (int r = 0; r < SEL_UNROLL; ++r)
-                    if (i0 + (int64_t)r * SEL_BS < len && (v[r] & msk) == pre)
-                        atomicAdd(&hw[(v[r] >> shift) & dmask], 1u);
+                for (int r = 0; r < SEL_UNROLL; ++r) {
+                    // lanes in the first valid lane's bin add their count in
+                    // one atomic (keys that pile into one bin would otherwise
+                    // serialise on it); the others add one each
+                    const bool valid = i0 + (int64_t)r * SEL_BS < len && (v[r] & msk) == pre;
+                    const uint32_t bin = (uint32_t)((v[r] >> shift) & dmask);
+                    const uint64_t act = __ballot(valid);
+                    if (act == 0) continue;
+                    const int lead = __ffsll((long long)act) - 1;
+                    const uint32_t b0 = __shfl(bin, lead, 64);
+                    const uint64_t same = __ballot(valid && bin == b0);
+                    if (valid) {
+                        if (bin != b0) atomicAdd(&hw[bin], 1u);
+                        else if (lane == lead) atomicAdd(&hw[b0], (uint32_t)__popcll(same));
+                    }
+                }
             }
             __syncthreads();
             for (int i = tid; i < nbins; i += SEL_BS) {
