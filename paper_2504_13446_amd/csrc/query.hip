@@ -434,19 +434,21 @@ __device__ inline void tq_bracket(const double *tt, const uint32_t *cc, double s
 
 // Brackets and estimates of the pairs u * nq + q go to query-major arrays
 // [q * n + u] (one segment per query for the selections) through an LDS tile
-// of 64 users x 32 queries, so the reads of t64 and the writes of the keys
-// both coalesce.  A workgroup takes 64 users and a run of qt_per such query
-// tiles, so the users' table rows, read into LDS once, serve all of them.
+// of TQB_U users x 32 queries, so the reads of t64 and the writes of the
+// keys both coalesce.  A workgroup takes TQB_U users and a run of qt_per such
+// query tiles, so the users' table rows, read into LDS once, serve all of
+// them.  32 users keep the LDS at 35 KB, four workgroups per CU.
+constexpr int TQB_U = 32;
 __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64,
                                                     const double *tab_t, const uint32_t *tab_cnt, uint64_t *key_lo,
                                                     uint64_t *key_hi, double *est, int qt_per) {
-    __shared__ uint32_t s_lo[32][65], s_hi[32][65];
-    __shared__ double s_e[32][65];
-    __shared__ double s_t[64][TABLE_COLS];
-    __shared__ uint32_t s_c[64][TABLE_COLS];
-    const int64_t u0 = (int64_t)blockIdx.x * 64;
+    __shared__ uint32_t s_lo[32][TQB_U + 1], s_hi[32][TQB_U + 1];
+    __shared__ double s_e[32][TQB_U + 1];
+    __shared__ double s_t[TQB_U][TABLE_COLS];
+    __shared__ uint32_t s_c[TQB_U][TABLE_COLS];
+    const int64_t u0 = (int64_t)blockIdx.x * TQB_U;
     const int tid = threadIdx.x;
-    for (int e = tid; e < 64 * TABLE_COLS; e += 256) {
+    for (int e = tid; e < TQB_U * TABLE_COLS; e += 256) {
         const int uu = e / TABLE_COLS, j = e - uu * TABLE_COLS;
         if (u0 + uu < n) {
             s_t[uu][j] = tab_t[(u0 + uu) * TABLE_COLS + j];
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m
     for (int qt = blockIdx.y * qt_per; qt < qt_end; ++qt) {
         const int q0 = qt * 32;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < TQB_U / 8; ++r) {
             const int uu = r * 8 + (tid >> 5), qq = tid & 31;
             const int64_t u = u0 + uu;
             const int q = q0 + qq;
@@ -473,8 +475,8 @@ __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int qq = r * 4 + (tid >> 6), uu = tid & 63;
+        for (int r = 0; r < 32 * TQB_U / 256; ++r) {
+            const int qq = r * (256 / TQB_U) + tid / TQB_U, uu = tid % TQB_U;
             const int64_t u = u0 + uu;
             const int q = q0 + qq;
             if (u < n && q < nq) {
@@ -784,7 +786,7 @@ hipError_t q_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64, const d
     if (n <= 0 || nq <= 0) return hipSuccess;
     // enough workgroups to fill the chip (about 2048), each with as many
     // query tiles as that allows
-    const int64_t gx = (n + 63) / 64, ntile = (nq + 31) / 32;
+    const int64_t gx = (n + TQB_U - 1) / TQB_U, ntile = (nq + 31) / 32;
     const int64_t gy_want = std::max<int64_t>(1, std::min<int64_t>(ntile, (2048 + gx - 1) / gx));
     const int qt_per = (int)((ntile + gy_want - 1) / gy_want);
     const unsigned gy = (unsigned)((ntile + qt_per - 1) / qt_per);
