@@ -401,9 +401,16 @@ __global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, con
             keep[i] = 0;
             continue;
         }
+        // the row does not increase, so the columns at or above t form a
+        // prefix: its length by a branch-free binary search (6 steps, not 48
+        // compares; out-of-row probes count as below)
+        static_assert(TABLE_COLS <= 63, "the search's steps sum to 63");
         int L = 0;
 #pragma unroll
-        for (int j = 0; j < TABLE_COLS; ++j) L += srow[k][j] >= t[k] ? 1 : 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const int j = L + step - 1;
+            if (j < TABLE_COLS && srow[k][j] >= t[k]) L += step;
+        }
         const uint32_t best = L > 0 ? scnt[k][L - 1] : 0u;
         keep[i] = (int64_t)best >= (int64_t)B ? 0 : 1;
     }
