@@ -339,6 +339,22 @@ __global__ __launch_bounds__(FC_BS) void k_flag_scatter(const uint8_t *flag, int
 // kept.
 // Dense domains (nq > 0) number pairs u * nq + q, so the pair arrays are not
 // read.
+// The number of entries at or above s in a table row (TABLE_COLS values that
+// do not increase): they form a prefix, whose length a branch-free binary
+// search finds in 6 steps instead of TABLE_COLS compares (probes past the row
+// count as below).  For rows in LDS; a row in global memory is cheaper to
+// scan with independent loads.
+__device__ inline int cols_at_or_above(const double *row, double s) {
+    static_assert(TABLE_COLS <= 63, "the search's steps sum to 63");
+    int L = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int j = L + step - 1;
+        if (j < TABLE_COLS && row[j] >= s) L += step;
+    }
+    return L;
+}
+
 __global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, const int32_t *pair_q,
                              const double *t64, const uint8_t *seedflag, const int32_t *bound,
                              const double *tab_t, const uint32_t *tab_cnt, uint8_t *keep) {
@@ -401,16 +417,7 @@ __global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, con
             keep[i] = 0;
             continue;
         }
-        // the row does not increase, so the columns at or above t form a
-        // prefix: its length by a branch-free binary search (6 steps, not 48
-        // compares; out-of-row probes count as below)
-        static_assert(TABLE_COLS <= 63, "the search's steps sum to 63");
-        int L = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-            const int j = L + step - 1;
-            if (j < TABLE_COLS && srow[k][j] >= t[k]) L += step;
-        }
+        const int L = cols_at_or_above(srow[k], t[k]);
         const uint32_t best = L > 0 ? scnt[k][L - 1] : 0u;
         keep[i] = (int64_t)best >= (int64_t)B ? 0 : 1;
     }
@@ -427,9 +434,7 @@ __global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, con
 // ---------------------------------------------------------------------------
 __device__ inline void tq_bracket(const double *tt, const uint32_t *cc, double s, int64_t m, uint32_t &rlo,
                                   uint32_t &rhi, double &e) {
-    int L = 0;
-#pragma unroll
-    for (int j = 0; j < TABLE_COLS; ++j) L += tt[j] >= s ? 1 : 0;
+    const int L = cols_at_or_above(tt, s);
     rlo = L > 0 ? 1u + cc[L - 1] : 1u;
     rhi = L < TABLE_COLS ? 1u + cc[L] : (uint32_t)(1 + m);
     e = (double)rlo;
