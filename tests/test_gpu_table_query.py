@@ -102,6 +102,36 @@ def test_table_query_batch_matches_oracle(case):
     assert e.value.status == rkr.RKR_E_INVALID
 
 
+def test_table_query_batch_many_query_tiles():
+    """Enough users that a workgroup of the bracket kernel runs several
+    32-query tiles on the table rows it holds (12,000 users, 200 queries:
+    runs of two tiles and a ragged last one): every answer equals the
+    oracle's table query on the oracle's own table."""
+    rng = np.random.default_rng(74)
+    n, m, d, S = 12000, 3100, 6, 256
+    U = rng.integers(-3, 4, size=(n, d)).astype(np.float32)
+    P = rng.integers(-3, 4, size=(m, d)).astype(np.float32)
+    want_t, want_c = O.rank_table(U, P, O.stratified_sample(P, S), O.sketch_positions(S, rkr.TABLE_COLS))
+    Qb = np.vstack([P[rng.choice(m, 150, replace=False)], rng.integers(-3, 4, size=(50, d)).astype(np.float32)])
+    ks = rng.integers(1, 400, size=Qb.shape[0]).astype(np.int32)
+    cs = rng.choice([1.0, 1.5, 3.0], size=Qb.shape[0])
+    idx = rkr.Index(_dev(U), _dev(P), score="f32", rank_table=S)
+    try:
+        t, c = idx.rank_table()
+        assert np.array_equal(t.cpu().numpy(), want_t)
+        assert np.array_equal(c.cpu().numpy().astype(np.int64), want_c)
+        ids, est, off = idx.query_table_batch(_dev(Qb), ks, cs)
+        ids = ids.cpu().numpy()
+        est = est.cpu().numpy()
+    finally:
+        idx.close()
+    T = O.dots(U, Qb)
+    for i in range(Qb.shape[0]):
+        wi, we = O.table_query(want_t, want_c, T[:, i], m, int(ks[i]), float(cs[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], wi), i
+        assert np.array_equal(est[off[i]:off[i + 1]], we), i
+
+
 def test_table_query_edges():
     """Fewer users than a tile, more samples than items (every item is a
     sample), k = n, and a query above every threshold of some users."""
