@@ -274,13 +274,35 @@ __global__ __launch_bounds__(256) void k_thresh_dense(const void *Um, int64_t n,
     double acc[4][4];
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    // BF16 rows of d % 8 == 0 at 16-byte aligned bases: a thread stages eight
+    // consecutive elements of one user row and one query row per chunk from
+    // one 16-byte load each
+    const bool wide = mk == MK_BF16 && (d & 7) == 0 && (((uintptr_t)Um | (uintptr_t)Qm) & 15) == 0;
     for (int k0 = 0; k0 < d; k0 += 32) {
-        for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-            const int r = e >> 5, kk = e & 31;
+        if (wide && k0 + 32 <= d) {
+            const int r = threadIdx.x >> 2, g = threadIdx.x & 3;
             const int64_t u = ub + r;
             const int q = qb + r;
-            su[kk][r] = (k0 + kk < d && u < n) ? master_elem(Um, mk, u * d + k0 + kk) : 0.0;
-            sq[kk][r] = (k0 + kk < d && q < nq) ? master_elem(Qm, mk, (int64_t)q * d + k0 + kk) : 0.0;
+            const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+            const uint4 wu = u < n ? *(const uint4 *)((const uint16_t *)Um + u * d + k0 + g * 8) : zero;
+            const uint4 wq = q < nq ? *(const uint4 *)((const uint16_t *)Qm + (int64_t)q * d + k0 + g * 8) : zero;
+            const uint32_t au[4] = {wu.x, wu.y, wu.z, wu.w}, aq[4] = {wq.x, wq.y, wq.z, wq.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                // element 2j is the low half of word j, element 2j + 1 the high half
+                su[g * 8 + 2 * j][r] = (double)__uint_as_float(au[j] << 16);
+                su[g * 8 + 2 * j + 1][r] = (double)__uint_as_float(au[j] & 0xFFFF0000u);
+                sq[g * 8 + 2 * j][r] = (double)__uint_as_float(aq[j] << 16);
+                sq[g * 8 + 2 * j + 1][r] = (double)__uint_as_float(aq[j] & 0xFFFF0000u);
+            }
+        } else {
+            for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+                const int r = e >> 5, kk = e & 31;
+                const int64_t u = ub + r;
+                const int q = qb + r;
+                su[kk][r] = (k0 + kk < d && u < n) ? master_elem(Um, mk, u * d + k0 + kk) : 0.0;
+                sq[kk][r] = (k0 + kk < d && q < nq) ? master_elem(Qm, mk, (int64_t)q * d + k0 + kk) : 0.0;
+            }
         }
         __syncthreads();
         const int kmax = min(32, d - k0);
