@@ -20,6 +20,10 @@ What is computed, and where the paper defines it (arXiv 2504.13446):
 * ``accuracy``, ``overall_ratio`` -- Sec. 5, the two quality criteria.
 * ``certify``   -- a checker for a claimed exact answer on all users or a
                    sample of them (see orc_certify).
+* ``topk_exact``-- the Def. 2 answer for large shapes by early abandon: users
+                   whose partial count already puts them behind the k best
+                   found so far stop counting (Lemma 1 (2) on exact counts);
+                   the result equals topk(ranks(...)) (see orc_topk_abandon).
 * ``norm_order``, ``stratified_sample``, ``sketch`` -- the per-user score
                    sketch: P ordered by norm, descending (Sec. 4.2 step 1),
                    split into equal buckets with one sample from the middle
@@ -66,14 +70,16 @@ def lib():
         L.orc_norms.argtypes = [vp, i64, ctypes.c_int, vp]
         L.orc_ranks.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.c_int, vp, i64, vp, ctypes.c_int]
         L.orc_certify.argtypes = [vp, i64, vp, i64, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,
-                                  i64, vp, ctypes.c_int]
+                                  i64, vp, vp, ctypes.c_int]
+        L.orc_topk_abandon.argtypes = [vp, i64, vp, i64, vp, vp, ctypes.c_int, ctypes.c_int, vp,
+                                       i64, vp, vp, vp, ctypes.c_int]
         L.orc_norm_order.argtypes = [vp, i64, vp]
         L.orc_sketch.argtypes = [vp, i64, vp, vp, i64, ctypes.c_int, vp, ctypes.c_int, vp,
                                  ctypes.c_int]
         L.orc_rank_table.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.c_int, vp, ctypes.c_int,
                                      vp, vp, ctypes.c_int]
         for f in (L.orc_dots, L.orc_norms, L.orc_ranks, L.orc_certify, L.orc_norm_order,
-                  L.orc_sketch, L.orc_rank_table):
+                  L.orc_sketch, L.orc_rank_table, L.orc_topk_abandon):
             f.restype = None
         _lib = L
     return _lib
@@ -142,17 +148,55 @@ def topk(rank_row, k: int, uids=None):
     return ids[order], r[order]
 
 
-def certify(U, P, q, k, ids, rks, check=None, threads: int = 0):
-    """Check a claimed exact answer; returns (rank mismatches, set violations, examined)."""
+def certify(U, P, q, k, ids, rks, check=None, order=None, threads: int = 0):
+    """Check a claimed exact answer; returns (rank mismatches, set violations, examined).
+
+    ``order``: the order in which the early-stopping scans visit the items
+    (None: 0..m-1); norm_order(P) makes them stop sooner."""
     U = widen(U); P = widen(P); q = widen(np.asarray(q).reshape(1, -1))
     ids = np.ascontiguousarray(np.asarray(ids, np.int64))
     rks = np.ascontiguousarray(np.asarray(rks, np.int32))
     chk = np.arange(U.shape[0], dtype=np.int64) if check is None else \
         np.ascontiguousarray(np.asarray(check, np.int64))
+    op = None
+    if order is not None:
+        order = np.ascontiguousarray(np.asarray(order, np.int64))
+        assert order.shape[0] == P.shape[0]
+        op = _p(order)
     out = np.zeros(3, np.int64)
     lib().orc_certify(_p(U), U.shape[0], _p(P), P.shape[0], _p(q), U.shape[1], int(k), _p(ids),
-                      _p(rks), _p(chk), chk.shape[0], _p(out), int(threads))
+                      _p(rks), _p(chk), chk.shape[0], op, _p(out), int(threads))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def topk_exact(U, P, q, k: int, uids=None, order=None, threads: int = 0, stats: dict | None = None):
+    """Def. 2 answer of one query by early abandon (see orc_topk_abandon):
+    the same result as topk(ranks(U, P, q)[0], k) restricted to the domain
+    ``uids`` (None: every user), computed without finishing the count of users
+    that cannot enter the answer.  Items are visited in ``order`` (None: the
+    norm order, Sec. 4.2 step 1).  Returns (ids, ranks) by (rank, id); with a
+    dict ``stats``, fills items_visited and users_fully_counted."""
+    U = widen(U); P = widen(P); q = widen(np.asarray(q).reshape(1, -1))
+    n, d = U.shape
+    m = P.shape[0]
+    if order is None:
+        order = norm_order(P)
+    order = np.ascontiguousarray(np.asarray(order, np.int64))
+    assert order.shape[0] == m
+    up, nu = None, n
+    if uids is not None:
+        uids = np.ascontiguousarray(np.asarray(uids, np.int64))
+        up, nu = _p(uids), uids.shape[0]
+    kk = int(min(k, nu))
+    ids = np.empty(kk, np.int64)
+    rks = np.empty(kk, np.int32)
+    st = np.zeros(2, np.int64)
+    lib().orc_topk_abandon(_p(U), n, _p(P), m, _p(order), _p(q), d, int(k), up, nu, _p(ids),
+                           _p(rks), _p(st), int(threads))
+    if stats is not None:
+        stats["items_visited"] = int(st[0])
+        stats["users_fully_counted"] = int(st[1])
+    return ids, rks
 
 
 def norm_order(P) -> np.ndarray:

@@ -116,6 +116,8 @@ void orc_ranks(const double *U, int64_t n, const double *P, int64_t m,
  *
  *   ids[0..k-1], ranks[0..k-1]: the claim, sorted by (rank, id).
  *   check[0..nc-1]: users to examine (all users, or a sample of them).
+ *   order[0..m-1]: the order in which items are visited (NULL: 0..m-1); the
+ *   norm order of Sec. 4.2 step 1 lets the early stop below come sooner.
  *
  * For every claimed user the full rank is recomputed; a mismatch is counted
  * in out[0].  Let R be the worst claimed rank and W the largest claimed id
@@ -128,7 +130,7 @@ void orc_ranks(const double *U, int64_t n, const double *P, int64_t m,
 void orc_certify(const double *U, int64_t n, const double *P, int64_t m,
                  const double *q, int d, int k, const int64_t *ids,
                  const int32_t *ranks, const int64_t *check, int64_t nc,
-                 int64_t *out, int nthreads)
+                 const int64_t *order, int64_t *out, int nthreads)
 {
     set_threads(nthreads);
     int64_t bad_rank = 0, bad_set = 0;
@@ -165,7 +167,7 @@ void orc_certify(const double *U, int64_t n, const double *P, int64_t m,
         double t = spec_dot(u, q, d);
         int64_t c = 0;
         for (int64_t p = 0; p < m && 1 + c <= R; ++p)
-            if (spec_dot(u, P + p * d, d) > t)
+            if (spec_dot(u, P + (order ? order[p] : p) * d, d) > t)
                 c += 1;
         if (1 + c < R || (1 + c == R && uid < W))
             bad_set += 1;
@@ -273,4 +275,184 @@ void orc_rank_table(const double *U, int64_t n, const double *P, int64_t m,
         free(all);
         free(s);
     }
+}
+
+/*
+ * Four spec dots of one vector x against four others: each result is the
+ * spec dot above (its own accumulator, dimensions in order, one fma each);
+ * the four chains only run side by side so that one waits less on the
+ * latency of the previous fma.
+ */
+static void spec_dot4(const double *x, const double *y0, const double *y1, const double *y2,
+                      const double *y3, int d, double out[4])
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        a0 = fma(x[k], y0[k], a0);
+        a1 = fma(x[k], y1[k], a1);
+        a2 = fma(x[k], y2[k], a2);
+        a3 = fma(x[k], y3[k], a3);
+    }
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+    out[3] = a3;
+}
+
+/*
+ * Partial Def. 1 count of one user: the items P[order[0]], P[order[1]], ...
+ * are visited in that order and c counts those with s(u,p) > t.  The scan
+ * stops once ((1 + c) << 32 | uid) exceeds *stop (read atomically, it may
+ * shrink while the scan runs), or after the last item.  Returns c; *done is 1
+ * when every item was visited (then 1 + c is the exact rank), and *seen the
+ * number of items visited.
+ */
+static int64_t scan_user(const double *u, int64_t uid, double t, const double *P,
+                         const int64_t *order, int64_t m, int d, const uint64_t *stop,
+                         int *done, int64_t *seen)
+{
+    int64_t c = 0, j = 0;
+    double s[4];
+    while (j < m) {
+        if (j + 4 <= m) {
+            spec_dot4(u, P + order[j] * d, P + order[j + 1] * d, P + order[j + 2] * d,
+                      P + order[j + 3] * d, d, s);
+            c += (s[0] > t) + (s[1] > t) + (s[2] > t) + (s[3] > t);
+            j += 4;
+        } else {
+            c += spec_dot(u, P + order[j] * d, d) > t;
+            j += 1;
+        }
+        uint64_t key = ((uint64_t)(1 + c) << 32) | (uint64_t)uid;
+        if (stop && key > __atomic_load_n(stop, __ATOMIC_RELAXED))
+            break;
+    }
+    *done = j == m;
+    *seen = j;
+    return c;
+}
+
+/* Max-heap of (rank << 32 | uid) keys. */
+static void heap_down(uint64_t *h, int n, int i)
+{
+    for (;;) {
+        int l = 2 * i + 1, r = l + 1, b = i;
+        if (l < n && h[l] > h[b]) b = l;
+        if (r < n && h[r] > h[b]) b = r;
+        if (b == i) return;
+        uint64_t x = h[i]; h[i] = h[b]; h[b] = x;
+        i = b;
+    }
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* visit order of the users: larger t/|u| first (|u| = 0: first), ties by id */
+struct visit { double key, t; int64_t uid; };
+static int cmp_visit(const void *a, const void *b)
+{
+    const struct visit *x = (const struct visit *)a, *y = (const struct visit *)b;
+    if (x->key > y->key) return -1;
+    if (x->key < y->key) return 1;
+    return (x->uid > y->uid) - (x->uid < y->uid);
+}
+
+/*
+ * Exact reverse k-ranks answer of one query by early abandon (Def. 2, ties on
+ * rank broken by user id; the abandon rule is Lemma 1 (2), Sec. 4, applied to
+ * exact partial counts).  Domain: the users uids[0..nu-1] (all n users when
+ * uids is NULL).  Items are visited in the order order[0..m-1] (a permutation
+ * of 0..m-1; the norm order of Sec. 4.2 step 1 makes abandoning early likely).
+ *
+ *   1. t_u = s(u,q) for every user of the domain;
+ *   2. the users are visited by t_u / |u| descending (|u| = 0 first; such a
+ *      user has rank 1), ties by id;
+ *   3. the first k of them are counted over every item: their (rank, id)
+ *      keys fill a max-heap;
+ *   4. every other user scans the items and is abandoned once
+ *      (1 + partial count, id) exceeds the heap's largest key, since counts
+ *      only grow; a user that reaches the end with a smaller key than the
+ *      heap's largest replaces it;
+ *   5. the answer is the heap by (rank, id) ascending.
+ * Step 4 runs in parallel over users; the heap changes under a lock and its
+ * largest key is published with an atomic store (a stale, larger value only
+ * delays an abandon).  ids_out[k], ranks_out[k]; stats[0] = items visited
+ * over all users, stats[1] = users that visited every item.
+ */
+void orc_topk_abandon(const double *U, int64_t n, const double *P, int64_t m,
+                      const int64_t *order, const double *q, int d, int k,
+                      const int64_t *uids, int64_t nu, int64_t *ids_out, int32_t *ranks_out,
+                      int64_t *stats, int nthreads)
+{
+    set_threads(nthreads);
+    if (!uids)
+        nu = n;
+    struct visit *vis = (struct visit *)malloc(sizeof(struct visit) * (size_t)(nu > 0 ? nu : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < nu; ++j) {
+        const int64_t u = uids ? uids[j] : j;
+        const double *uv = U + u * d;
+        const double t = spec_dot(uv, q, d);
+        const double nrm = sqrt(spec_dot(uv, uv, d));
+        vis[j].key = nrm > 0.0 ? t / nrm : INFINITY;
+        vis[j].t = t;
+        vis[j].uid = u;
+    }
+    qsort(vis, (size_t)nu, sizeof(struct visit), cmp_visit);
+
+    const int kk = (int)(k < nu ? k : nu);
+    uint64_t *heap = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(kk > 0 ? kk : 1));
+    int64_t visited = 0, full = 0;
+    /* step 3: the first kk users, counted over every item */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : visited, full)
+    for (int j = 0; j < kk; ++j) {
+        int done = 0;
+        int64_t seen = 0;
+        const int64_t c = scan_user(U + vis[j].uid * d, vis[j].uid, vis[j].t, P, order, m, d,
+                                    NULL, &done, &seen);
+        heap[j] = ((uint64_t)(1 + c) << 32) | (uint64_t)vis[j].uid;
+        visited += seen;
+        full += 1;
+    }
+    for (int i = kk / 2 - 1; i >= 0; --i)
+        heap_down(heap, kk, i);
+    uint64_t worst = kk > 0 ? heap[0] : 0;
+    /* step 4 */
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : visited, full)
+    for (int64_t j = kk; j < nu; ++j) {
+        int done = 0;
+        int64_t seen = 0;
+        const int64_t uid = vis[j].uid;
+        const int64_t c = scan_user(U + uid * d, uid, vis[j].t, P, order, m, d, &worst, &done,
+                                    &seen);
+        visited += seen;
+        if (!done)
+            continue;
+        full += 1;
+        const uint64_t key = ((uint64_t)(1 + c) << 32) | (uint64_t)uid;
+#pragma omp critical(orc_heap)
+        {
+            if (key < heap[0]) {
+                heap[0] = key;
+                heap_down(heap, kk, 0);
+                __atomic_store_n(&worst, heap[0], __ATOMIC_RELAXED);
+            }
+        }
+    }
+    /* step 5 */
+    qsort(heap, (size_t)kk, sizeof(uint64_t), cmp_u64);
+    for (int i = 0; i < kk; ++i) {
+        ids_out[i] = (int64_t)(heap[i] & 0xffffffffu);
+        ranks_out[i] = (int32_t)(heap[i] >> 32);
+    }
+    if (stats) {
+        stats[0] = visited;
+        stats[1] = full;
+    }
+    free(heap);
+    free(vis);
 }
