@@ -126,6 +126,9 @@ typedef struct {
     int64_t graph_replays;  /* 1 if the call replayed a captured graph                      */
     int64_t table_pruned;   /* pairs the rank table ruled out before the screen             */
     int64_t mfma_flop;      /* matrix-core flop the count kernels executed (padded shapes)  */
+    int64_t scored_pairs;   /* (user, item) scores the count kernels computed for users     */
+                            /* with a live pair (2 d flop each: the algorithmic work)       */
+    int64_t persistent_phases; /* screening phases launched as a persistent grid            */
 } rkr_query_stats;
 
 /*
@@ -261,6 +264,17 @@ rkr_status rkr_mlp_set(rkr_index *idx, const float *params);
  */
 rkr_status rkr_mlp_grad(rkr_index *idx, const float *X, const float *z, int32_t N,
                         float *grad_out, double *loss_out);
+
+/*
+ * One Adam step (Kingma & Ba; b1 = 0.9, b2 = 0.999, eps = 1e-8, bias
+ * correction for the 1-based step count `step`) of the estimator's
+ * parameters with the gradient grad [device, 5441 float, flattened as
+ * above] and learning rate lr; the kernel rkr_train runs per minibatch.
+ * reset = 1 zeroes both moment estimates first.  RKR_E_STATE if the network
+ * has no parameters (rkr_train or rkr_mlp_set first); RKR_E_INVALID for
+ * step < 1 or lr <= 0.
+ */
+rkr_status rkr_mlp_adam(rkr_index *idx, const float *grad, float lr, int32_t step, int32_t reset);
 
 /* Per-user sketch [device, n x 16 float] (needs sketch_samples > 0). */
 rkr_status rkr_sketch(rkr_index *idx, float *out);

@@ -816,6 +816,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
                 a.ent_cnt = x->sp_cnt.as<uint32_t>();
             }
             if (pers_phase) {
+                x->stats.persistent_phases += 1;
                 HIPCK(launch_fill_u32(x->ctr.as<uint32_t>() + 8, 0, 2, st));
                 a.tile_counter = x->ctr.as<unsigned long long>() + 4;
                 a.persistent_ctas = x->num_cus;
@@ -885,12 +886,13 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(launch_select(x->candkeys.as<uint64_t>(), x->candoff.as<int64_t>(), x->kdev.as<int32_t>(), nq,
                         x->bestoff.as<int64_t>(), x->ans.as<uint64_t>(), st));
     HIPCK(q_write_answer(x->ans.as<uint64_t>(), ksum, ids_out, ranks_out, st));
-    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
-    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 48, hipMemcpyDeviceToHost, st));
+    unsigned long long ctr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 64, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
     x->stats.mfma_flop = (int64_t)ctr[5];
+    x->stats.scored_pairs = (int64_t)ctr[7];
     {
         unsigned long long slots = 0;
         HIPCK(hipMemcpyAsync(&slots, x->ctr.as<unsigned long long>() + 3, 8, hipMemcpyDeviceToHost, st));
@@ -958,12 +960,13 @@ static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     rkr_status rs = exact_count(x, ps, x->allpid.as<int32_t>(), n);
     if (rs != RKR_OK) return rs;
     HIPCK(q_ranks_out(x->cnt.as<uint32_t>(), n, ranks_out, st));
-    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
-    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 48, hipMemcpyDeviceToHost, st));
+    unsigned long long ctr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 64, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
     x->stats.mfma_flop = (int64_t)ctr[5];
+    x->stats.scored_pairs = (int64_t)ctr[7];
     x->stats.refined_pairs = n;
     x->stats.ms_total = now_ms() - t0;
     return RKR_OK;
@@ -1055,9 +1058,9 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
     HIPCK(q_copy(q, g.qbuf.p, (int64_t)x->d * mes, st));
     HIPCK(hipGraphLaunch(g.ge, st));
-    unsigned long long ctr[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long ctr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int flags = 0;
-    HIPCK(hipMemcpyAsync(ctr, g.ctr.p, 48, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(ctr, g.ctr.p, 64, hipMemcpyDeviceToHost, st));
     HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
@@ -1076,6 +1079,7 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
     x->stats.mfma_flop = (int64_t)ctr[5];
+    x->stats.scored_pairs = (int64_t)ctr[7];
     x->stats.ms_total = now_ms() - t0;
     x->stats.graph_replays = 1;
     return RKR_OK;
@@ -1359,6 +1363,22 @@ extern "C" rkr_status rkr_mlp_grad(rkr_index *x, const float *X, const float *z,
     HIPCK(hipMemcpyAsync(&l, ld, 8, hipMemcpyDeviceToHost, x->st));
     HIPCK(hipStreamSynchronize(x->st));
     *loss = l / (double)N;
+    return RKR_OK;
+}
+
+extern "C" rkr_status rkr_mlp_adam(rkr_index *x, const float *grad, float lr, int32_t step, int32_t reset) {
+    g_err.clear();
+    if (!x || !grad) return fail(RKR_E_INVALID, "NULL argument");
+    if (step < 1 || !(lr > 0.0f)) return fail(RKR_E_INVALID, "step >= 1 and lr > 0 required");
+    if (!x->est.trained) return fail(RKR_E_STATE, "estimator has no parameters");
+    hipStream_t st = x->st;
+    if (reset) {
+        HIPCK(launch_fill_u32(x->est.adam_m.as<uint32_t>(), 0, MLP_NPARAM, st));
+        HIPCK(launch_fill_u32(x->est.adam_v.as<uint32_t>(), 0, MLP_NPARAM, st));
+    }
+    HIPCK(hipMemcpyAsync(x->est.grads.p, grad, MLP_NPARAM * 4, hipMemcpyDeviceToDevice, st));
+    HIPCK(est_adam(x->est, lr, step, st));
+    HIPCK(hipStreamSynchronize(st));
     return RKR_OK;
 }
 

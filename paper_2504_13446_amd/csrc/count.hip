@@ -149,7 +149,7 @@ __device__ inline void wait_vm() {
 
 template <int SK, int MODE, int NKS, int NUB, int NIB>
 __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, uint64_t &ncmp,
-                                  uint64_t &nslot, uint64_t &nstep) {
+                                  uint64_t &nslot, uint64_t &nstep, uint64_t &nscored) {
     using FT = typename FragT<SK>::T;
     constexpr int FB = frag_fb(SK);
     constexpr int KS = frag_ks(SK);
@@ -426,6 +426,15 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
 
     for (int64_t st = s_begin; st < s_end; ++st) {
         ++nstep;
+        {
+            // (user, item) scores this step owes to users with a live pair
+            // (both lanes of a pair hold the same user and list length)
+            uint32_t lanes = 0;
+#pragma unroll
+            for (int ub = 0; ub < NUB; ++ub) lanes += (uint32_t)__popcll(__ballot(len[ub] > 0));
+            const int64_t rest = a.m - st * (NIB * 32);
+            nscored += (uint64_t)(lanes / 2) * (uint64_t)(rest < NIB * 32 ? rest : NIB * 32);
+        }
         const uint8_t *tile = lds + cbuf * STAGE;
         // prefetch step st + NBUF - 1 straight into its LDS stage; that stage was
         // last read in the previous step, before the barrier that ended it
@@ -797,9 +806,9 @@ template <int SK, int MODE, int NKS, int NUB, int NIB, bool PERSIST>
 __global__ __launch_bounds__(512) void k_count(CountArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int lane = threadIdx.x & 63;
-    uint64_t ncmp = 0, nslot = 0, nstep = 0;
+    uint64_t ncmp = 0, nslot = 0, nstep = 0, nscored = 0;
     if constexpr (!PERSIST) {
-        count_tile<SK, MODE, NKS, NUB, NIB>(a, (int64_t)blockIdx.x, lds, ncmp, nslot, nstep);
+        count_tile<SK, MODE, NKS, NUB, NIB>(a, (int64_t)blockIdx.x, lds, ncmp, nslot, nstep, nscored);
     } else {
         __shared__ int64_t sh_tile;
         for (;;) {
@@ -808,7 +817,7 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
             const int64_t t = sh_tile;
             __syncthreads();
             if (t >= a.ntiles) break;
-            count_tile<SK, MODE, NKS, NUB, NIB>(a, t, lds, ncmp, nslot, nstep);
+            count_tile<SK, MODE, NKS, NUB, NIB>(a, t, lds, ncmp, nslot, nstep, nscored);
             __syncthreads();   // the next tile reuses the LDS buffers
         }
     }
@@ -822,6 +831,7 @@ __global__ __launch_bounds__(512) void k_count(CountArgs a) {
     if (lane == 0 && a.stat) {
         atomicAdd(a.stat, (unsigned long long)tot);
         atomicAdd(a.stat + 2, (unsigned long long)tslot);   // lane slots, active or not
+        atomicAdd(a.stat + 6, (unsigned long long)nscored); // per wave: its users' scores
     }
     // executed matrix-core flop: every step of a workgroup multiplies its
     // 8 x NUB x 32 users by NIB x 32 items over the padded dimension

@@ -101,7 +101,8 @@ struct CountArgs {
     int2 *emit;                   // near-tie records (pid, item)
     unsigned long long *emit_count;
     unsigned long long emit_cap;
-    unsigned long long *stat;     // [0]: executed compares, [2]: compare lane slots, [4]: matrix-core flop
+    unsigned long long *stat;     // [0]: executed compares, [2]: compare lane slots, [4]: matrix-core flop,
+                                  // [6]: (user, item) scores of users with a live pair
     int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
     // persistent launch: workgroups take tiles from *tile_counter (zeroed before
     // the launch) until it passes ntiles; null = one workgroup per tile

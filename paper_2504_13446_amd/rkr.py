@@ -27,7 +27,7 @@ MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
            "rkr_query_table", "rkr_query_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
-           "rkr_mlp_grad", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
+           "rkr_mlp_grad", "rkr_mlp_adam", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
 class RkrError(RuntimeError):
@@ -60,7 +60,9 @@ class QueryStats(ctypes.Structure):
                                                              ("compare_slots", ctypes.c_int64),
                                                              ("graph_replays", ctypes.c_int64),
                                                              ("table_pruned", ctypes.c_int64),
-                                                             ("mfma_flop", ctypes.c_int64)]
+                                                             ("mfma_flop", ctypes.c_int64),
+                                                             ("scored_pairs", ctypes.c_int64),
+                                                             ("persistent_phases", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -94,6 +96,7 @@ def load(path: str = LIB_PATH):
         "rkr_mlp_get": [vp, vp],
         "rkr_mlp_set": [vp, vp],
         "rkr_mlp_grad": [vp, vp, vp, i32, vp, ctypes.POINTER(f64)],
+        "rkr_mlp_adam": [vp, vp, ctypes.c_float, i32, i32],
         "rkr_sketch": [vp, vp],
         "rkr_rank_table": [vp, vp, vp],
         "rkr_stats": [vp, ctypes.POINTER(QueryStats)],
@@ -259,6 +262,11 @@ def rkr_mlp_grad(h: int, X: torch.Tensor, z: torch.Tensor):
     loss = ctypes.c_double()
     _check(load().rkr_mlp_grad(h, _ptr(X), _ptr(z), X.shape[0], _ptr(g), ctypes.byref(loss)))
     return g, loss.value
+
+
+def rkr_mlp_adam(h: int, grad: torch.Tensor, lr: float, step: int, reset: bool = False) -> None:
+    assert grad.numel() == MLP_NPARAM and grad.dtype == torch.float32
+    _check(load().rkr_mlp_adam(h, _ptr(grad), float(lr), int(step), 1 if reset else 0))
 
 
 def rkr_sketch(h: int, n: int, device="cuda") -> torch.Tensor:

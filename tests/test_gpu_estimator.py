@@ -182,3 +182,34 @@ def test_estimator_gain_when_pruning():
     assert res[True][0] > res[False][0]
     assert res[True][1] <= res[False][1]
     idx.close()
+
+
+def test_adam_steps_match_fp64_reference(lowrank):
+    """Six Adam steps of the library's kernel from fixed FP32 gradients against
+    the FP64 Adam of the oracle from the same start.  The kernel computes in
+    FP32: each step moves a parameter by lr * m_hat / (sqrt(v_hat) + eps),
+    with a few FP32 roundings (relative 2^-24 each) in that update and one
+    in the parameter, so the parameters agree to 1e-6 of each tensor's norm
+    and the accumulated updates to 1e-5 of theirs."""
+    w, idx = lowrank
+    p0 = _rand_params(9)
+    flat0 = M.flatten(p0).astype(np.float32)
+    rkr.rkr_mlp_set(idx.h, flat0)
+    ref = M.unflatten(flat0.astype(np.float64))
+    start = M.unflatten(flat0.astype(np.float64))
+    mom = {k: np.zeros(M.SHAPES[k]) for k in M.ORDER}
+    vel = {k: np.zeros(M.SHAPES[k]) for k in M.ORDER}
+    rng = np.random.default_rng(12)
+    lr = 1e-2
+    for t in range(1, 7):
+        g = (rng.standard_normal(M.n_params()) * rng.choice([1e-3, 1e-1, 1.0], M.n_params())).astype(np.float32)
+        rkr.rkr_mlp_adam(idx.h, torch.from_numpy(g).cuda(), lr, t, reset=(t == 1))
+        M.adam_step(ref, M.unflatten(g.astype(np.float64)), mom, vel, t, lr)
+    got = M.unflatten(rkr.rkr_mlp_get(idx.h).astype(np.float64))
+    for k in M.ORDER:
+        a, b, s = got[k], ref[k], start[k]
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), k
+        assert np.linalg.norm((a - s) - (b - s)) <= 1e-5 * np.linalg.norm(b - s), k
+    with pytest.raises(rkr.RkrError) as e:
+        rkr.rkr_mlp_adam(idx.h, torch.zeros(M.n_params(), device="cuda"), lr, 0)
+    assert e.value.status == rkr.RKR_E_INVALID

@@ -1,0 +1,83 @@
+"""GPU parity at full size, against the oracle, with no sampling.
+
+* The single-query workload (100,000 users x 100,000 items x d = 100, low-rank
+  data, FP32 masters): every one of the 100,000 Def. 1 ranks of its query, for
+  BF16 scores + FP64 recheck and FP32 scores + FP64 recheck, eagerly and as a
+  graph replay, equals the oracle's bit for bit (about 1e12 FP64 fma in the
+  oracle: a minute or two on the host's cores).
+* The batch workload (1M users x 1M items x d = 200, 256 queries, k = 100,
+  with the rank table): the answer of the query with the smallest k-th rank
+  equals the oracle's early-abandon exact top-k (Def. 2) element by element.
+  The sampled checks of other queries are in test_gpu_full_and_errors.py.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2504_13446_amd import rkr, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, dtype):
+    return rkr.to_device(x, dtype)
+
+
+def _log(msg):
+    print("[fullsize %.0fs] %s" % (time.time() - _T0, msg), flush=True)
+
+
+_T0 = time.time()
+
+
+@pytest.mark.timeout(900)
+def test_single_query_all_ranks_full_size():
+    w = W.make("single")
+    q = _dev(w.Qv[0], "f32")
+    U, P = _dev(w.U, "f32"), _dev(w.P, "f32")
+    got = {}
+    for score in ("bf16", "f32"):
+        idx = rkr.Index(U, P, score=score)
+        got[score] = idx.ranks(q).cpu().numpy()
+        st = idx.stats()
+        idx.configure(graph=True)
+        idx.ranks(q)                                   # eager run, then capture
+        got[score + "_graph"] = idx.ranks(q).cpu().numpy()
+        assert idx.stats()["graph_replays"] == 1
+        ids, rk = idx.query_exact(q, 50)
+        got[score + "_top"] = (ids.cpu().numpy(), rk.cpu().numpy())
+        idx.close()
+        _log("%s: all ranks on the GPU, %d near ties rechecked" % (score, st["uncertain"]))
+    t = time.time()
+    R = O.ranks(w.U, w.P, w.Qv)[0]
+    _log("oracle: 100,000 ranks in %.1f s on %d threads" % (time.time() - t, O.num_threads()))
+    wi, wr = O.topk(R, 50)
+    for score in ("bf16", "f32"):
+        for key in (score, score + "_graph"):
+            bad = np.flatnonzero(got[key] != R)
+            assert bad.size == 0, (key, bad[:10], got[key][bad[:10]], R[bad[:10]])
+        ids, rk = got[score + "_top"]
+        assert np.array_equal(ids, wi) and np.array_equal(rk, wr), score
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_size_best_query_exact():
+    w = W.make("batch")
+    idx = rkr.Index(_dev(w.U, "bf16"), _dev(w.P, "bf16"), score="bf16", rank_table=4096)
+    ids, rk, off = idx.query_batch(_dev(w.Qv, "bf16"), w.k)
+    idx.close()
+    ids = ids.cpu().numpy(); rk = rk.cpu().numpy()
+    kth = np.array([rk[off[i + 1] - 1] for i in range(w.nq)])
+    i = int(np.argmin(kth))
+    _log("batch answered; query %d has the smallest k-th rank, %d" % (i, kth[i]))
+    Uw, Pw = O.widen(w.U), O.widen(w.P)
+    st = {}
+    t = time.time()
+    wi, wr = O.topk_exact(Uw, Pw, O.widen(w.Qv[i]), int(w.k[i]), stats=st)
+    _log("oracle top-k of query %d in %.1f s on %d threads: %.3g of the pairs visited, %d users "
+         "counted in full" % (i, time.time() - t, O.num_threads(), st["items_visited"] / (w.n * w.m),
+                              st["users_fully_counted"]))
+    assert np.array_equal(ids[off[i]:off[i + 1]], wi)
+    assert np.array_equal(rk[off[i]:off[i + 1]], wr)

@@ -105,3 +105,40 @@ def test_screen_kills_what_it_should():
     st = idx.stats()
     idx.close()
     assert lo <= st["survivors"] <= hi, (lo, st["survivors"], hi)
+
+
+@pytest.mark.parametrize("cand", [3, 4, 5])
+def test_persistent_screen_launch(cand, monkeypatch):
+    """The persistent work-queue launch of the screening pass (workgroups take
+    user tiles from a device counter) runs only on phases with at least one
+    tile per compute unit.  140,000 users x 3,000 items x d = 32 with 16
+    queries and no rank table gives every user a live pair in the first phase:
+    547 tiles of 256 users (274 of 512 for tile variant 0).  Each persistent
+    candidate of the tuner (3 + tile variant) is forced and the answers are
+    compared with the oracle's, element by element."""
+    from paper_2504_13446_amd import workloads as W
+    w = W.make("small", n=140_000, m=3_000, d=32, nq=16, k=10)
+    R = _ranks_cached(w)
+    monkeypatch.setenv("RKR_SCREEN_CANDIDATE", str(cand))
+    monkeypatch.setenv("RKR_AUTOTUNE_CACHE", "off")
+    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16")
+    ids, rk, off = idx.query_batch(_dev(w.Qv, "f32"), w.k)
+    st = idx.stats()
+    idx.close()
+    assert st["screen_variant"] == cand
+    assert st["persistent_phases"] >= 1, st
+    ids = ids.cpu().numpy(); rk = rk.cpu().numpy()
+    for i in range(w.nq):
+        wi, wr = O.topk(R[i], int(w.k[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], wi), i
+        assert np.array_equal(rk[off[i]:off[i + 1]], wr), i
+
+
+_RANKS = {}
+
+
+def _ranks_cached(w):
+    key = (w.name, w.n, w.m, w.d, w.nq)
+    if key not in _RANKS:
+        _RANKS[key] = O.ranks(w.U, w.P, w.Qv)
+    return _RANKS[key]
