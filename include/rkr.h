@@ -129,6 +129,9 @@ typedef struct {
     int64_t scored_pairs;   /* (user, item) scores the count kernels computed for users     */
                             /* with a live pair (2 d flop each: the algorithmic work)       */
     int64_t persistent_phases; /* screening phases launched as a persistent grid            */
+    double ms_seed_kernel;  /* duration of the seed pass's exact count kernel (HIP events)  */
+    int64_t scored_seed;    /* scored_pairs of the seed pass                                */
+    int64_t scored_exact;   /* scored_pairs of every exact pass (seeds, refine)             */
 } rkr_query_stats;
 
 /*

@@ -406,6 +406,10 @@ static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus) {
     return best;
 }
 
+// Tile of the exact passes: v2, 1 x 2 blocks per wave (the low-register
+// tile; FP32 scores have one tile, v0 = 1 x 1).
+static int exact_variant(const rkr_index *x) { return x->sk == SK_F32 ? 0 : 2; }
+
 static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int variant) {
     CountArgs a{};
     const int nib = nib_of(x->sk, x->nks, variant);
@@ -462,7 +466,7 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
     TaskSet &ts = x->ts_exact;
     hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, nullptr, ts, x->sc, st);
     if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
-    const int xv = x->sk == SK_F32 ? 0 : 2;     // exact passes: low-register tile
+    const int xv = exact_variant(x);
     const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
     const int64_t gx = (ts.ntask + tpw - 1) / tpw;
     CountArgs a = count_args(x, ps, ts, xv);
@@ -716,6 +720,11 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 16, st));
     rkr_status rs = exact_count(x, ps, x->seedpid.as<int32_t>(), nseed);
     if (rs != RKR_OK) return rs;
+    x->stats.ms_seed_kernel = x->stats.ms_exact_kernel;
+    unsigned long long scored_after_seed = 0;
+    HIPCK(hipMemcpyAsync(&scored_after_seed, x->ctr.as<unsigned long long>() + 7, 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    x->stats.scored_seed = (int64_t)scored_after_seed;
     // ---- 5. per-query bound
     HIPCK(q_rank_keys_sel(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->cnt.as<uint32_t>(),
                           x->selrank.as<uint64_t>(), st));
@@ -853,6 +862,8 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
     }
+    unsigned long long scored_before_refine = 0;
+    HIPCK(hipMemcpyAsync(&scored_before_refine, x->ctr.as<unsigned long long>() + 7, 8, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     const double t3 = now_ms();
     x->stats.ms_screen = t3 - t2;
@@ -893,6 +904,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     x->stats.flips = (int64_t)ctr[2];
     x->stats.mfma_flop = (int64_t)ctr[5];
     x->stats.scored_pairs = (int64_t)ctr[7];
+    x->stats.scored_exact = (int64_t)scored_after_seed + (int64_t)(ctr[7] - scored_before_refine);
     {
         unsigned long long slots = 0;
         HIPCK(hipMemcpyAsync(&slots, x->ctr.as<unsigned long long>() + 3, 8, hipMemcpyDeviceToHost, st));
@@ -967,6 +979,7 @@ static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     x->stats.flips = (int64_t)ctr[2];
     x->stats.mfma_flop = (int64_t)ctr[5];
     x->stats.scored_pairs = (int64_t)ctr[7];
+    x->stats.scored_exact = (int64_t)ctr[7];
     x->stats.refined_pairs = n;
     x->stats.ms_total = now_ms() - t0;
     return RKR_OK;
@@ -976,7 +989,7 @@ static rkr_status capture_ranks_graph(rkr_index *x) {
     RanksGraph &g = x->rg;
     const int64_t n = x->n;
     const int mes = x->mk == MK_BF16 ? 2 : 4;
-    const int xv = x->sk == SK_F32 ? 0 : 2;
+    const int xv = exact_variant(x);
     const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
     const int64_t ntask_pad = (n + 511) / 512 * 512;
     g.emit_cap = std::max<int64_t>(1 << 20, 2 * x->stats.uncertain + 65536);
@@ -1080,6 +1093,7 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     x->stats.flips = (int64_t)ctr[2];
     x->stats.mfma_flop = (int64_t)ctr[5];
     x->stats.scored_pairs = (int64_t)ctr[7];
+    x->stats.scored_exact = (int64_t)ctr[7];
     x->stats.ms_total = now_ms() - t0;
     x->stats.graph_replays = 1;
     return RKR_OK;

@@ -632,27 +632,33 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             // scores add to cnt, near ties are emitted for the FP64 recheck
             auto exact_entry = [&](bool act, int pid, float th, float tl, float tmv, uint32_t &cnt) {
                 const float hi = a.plain ? th : f32_next_up(th + eps);
-                uint32_t c = 0;
                 const float lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
-                uint32_t umask = 0;
+                // two counts per score: c of scores above hi (certainly above
+                // the threshold), cl of scores at or above lo; every score above
+                // hi is at or above lo, so near ties (lo <= score <= hi) exist
+                // exactly when cl > c.  Plain mode has lo = next_up(hi): none.
+                uint32_t c = 0, cl = 0;
 #pragma unroll
                 for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const float sv = acc[ib][ub][r];
-                        const bool gt = sv > hi;
-                        c += gt ? 1u : 0u;
-                        umask |= (!gt && sv >= lo) ? (1u << (ib * 16 + r)) : 0u;
+                        c += (sv > hi) ? 1u : 0u;
+                        cl += (sv >= lo) ? 1u : 0u;
                     }
-                if (!act) umask = 0;
-                if (__ballot(umask != 0) != 0ull) {
-                    // rare: the plain FP32 verdicts (score > fl32(t)) of this entry's scores
-                    uint32_t pmask = 0;
+                if (__ballot(act && cl != c) != 0ull) {
+                    // rare: the masks of this entry's near ties and of their
+                    // plain FP32 verdicts (score > fl32(t))
+                    uint32_t umask = 0, pmask = 0;
 #pragma unroll
                     for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            pmask |= (acc[ib][ub][r] > tmv) ? (1u << (ib * 16 + r)) : 0u;
+                        for (int r = 0; r < 16; ++r) {
+                            const float sv = acc[ib][ub][r];
+                            umask |= (sv >= lo && !(sv > hi)) ? (1u << (ib * 16 + r)) : 0u;
+                            pmask |= (sv > tmv) ? (1u << (ib * 16 + r)) : 0u;
+                        }
+                    if (!act) umask = 0;
                     const uint32_t nu = __popc(umask);
                     // record offsets: with at most one record per lane (the
                     // usual case) they are the lane's rank among the lanes

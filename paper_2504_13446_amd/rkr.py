@@ -62,7 +62,10 @@ class QueryStats(ctypes.Structure):
                                                              ("table_pruned", ctypes.c_int64),
                                                              ("mfma_flop", ctypes.c_int64),
                                                              ("scored_pairs", ctypes.c_int64),
-                                                             ("persistent_phases", ctypes.c_int64)]
+                                                             ("persistent_phases", ctypes.c_int64),
+                                                             ("ms_seed_kernel", ctypes.c_double),
+                                                             ("scored_seed", ctypes.c_int64),
+                                                             ("scored_exact", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}
