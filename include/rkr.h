@@ -237,6 +237,20 @@ rkr_status rkr_rank_table(const rkr_index *idx, double *t_out, uint32_t *cnt_out
 rkr_status rkr_ranks(rkr_index *idx, const void *q, int32_t *ranks_out);
 
 /*
+ * rkr_ranks for callers that cannot allocate device memory (code under graph
+ * capture elsewhere, tight serving loops, harnesses that forbid hipMalloc):
+ * the same ranks, ranks_out [device, n int32], but every per-call buffer
+ * lives in one static 64 MiB array per device, placed when the first index
+ * is built on that device and held until the process ends; the call
+ * allocates nothing.  Users are counted in chunks that
+ * fit the array; a chunk with more near ties than it holds is counted again
+ * in smaller chunks.  Calls that overlap on one device share the array and
+ * race: issue them one at a time per device.  Errors: RKR_E_UNSUPPORTED for
+ * more than 2^20 users or 2^22 items; RKR_E_INVALID as rkr_ranks.
+ */
+rkr_status rkr_ranks_noalloc(rkr_index *idx, const void *q, int32_t *ranks_out);
+
+/*
  * Learned rank estimator (an MLP 18 -> 64 -> 64 -> 1 on the features
  * [u.q / |u|, |u|, 16 sketch values]) predicting ln r.  rkr_train computes
  * exact ranks for (user, query) pairs of the training queries Qm [device,

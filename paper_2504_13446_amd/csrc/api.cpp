@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -163,6 +164,7 @@ struct rkr_index {
     int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1;
     int64_t nblk32 = 0, nblk = 0;     // item blocks of 32 (real, allocated: a multiple of 4)
     int num_cus = 256;
+    int dev = 0;                      // device the index was built on
     hipStream_t st = nullptr;
     // index data
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
@@ -193,6 +195,7 @@ struct rkr_index {
 // ---------------------------------------------------------------------------
 static_assert(TABLE_COLS == RKR_TABLE_COLS, "the kernels' table width is the ABI's");
 static rkr_status build_rank_table(rkr_index *x, int samples);
+static rkr_status scratch_address(int dev, uint8_t **out);
 
 extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t m, int32_t d, rkr_dtype dt,
                                 const rkr_build_opts *opts, rkr_index **out) {
@@ -234,6 +237,7 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     x->tuner.load();
     {
         int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess) x->dev = dev;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             x->num_cus = cus;
@@ -308,6 +312,12 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
         rkr_destroy(x);
         return rs;
     }
+    // set-up of rkr_ranks_noalloc on this device: taking the address of its
+    // static array makes the runtime place the array now, not in that call
+    // (a failure here surfaces there)
+    uint8_t *na = nullptr;
+    (void)scratch_address(x->dev, &na);
+    g_err.clear();
     *out = x;
     return RKR_OK;
 }
@@ -1096,6 +1106,168 @@ extern "C" rkr_status rkr_ranks(rkr_index *x, const void *q, int32_t *ranks_out)
     x->stats.scored_exact = (int64_t)ctr[7];
     x->stats.ms_total = now_ms() - t0;
     x->stats.graph_replays = 1;
+    return RKR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// All ranks without allocating (rkr_ranks_noalloc)
+// ---------------------------------------------------------------------------
+// The per-call device memory of rkr_ranks_noalloc is one static array per
+// device (every device the library runs on holds it until the process ends).
+// In host code `scratch` only names the array: its device address is taken
+// once per device with hipGetSymbolAddress (that device current) and only
+// that address reaches kernels.  Calls on one device share the array, so
+// calls that overlap on one device race; each call clears what must start at
+// zero.
+static constexpr size_t kNoAllocBytes = (size_t)64 << 20;        // 64 MiB
+static constexpr int64_t kNoAllocMaxUsers = (int64_t)1 << 20;
+static constexpr int64_t kNoAllocMaxItems = (int64_t)1 << 22;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+static constexpr int kMaxDevices = 64;
+static uint8_t *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static rkr_status scratch_address(int dev, uint8_t **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return fail(RKR_E_UNSUPPORTED, "device ordinal above 63");
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        HIPCK(hipGetDevice(&cur));
+        if (cur != dev) HIPCK(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = (uint8_t *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return RKR_OK;
+}
+
+// Bump placement inside the scratch array (256-byte aligned pieces).
+struct Carve {
+    uint8_t *base;
+    size_t used = 0;
+    template <typename T> T *take(int64_t count) {
+        T *p = (T *)(base + used);
+        used += ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
+        return p;
+    }
+};
+
+// The sequence of the captured all-ranks graph (thresholds -> one entry per
+// user -> exact count -> FP64 recheck -> ranks), on users in chunks whose
+// entry lists and near-tie records fit the scratch array; a chunk whose near
+// ties overflow is counted again in smaller chunks (a single user emits at
+// most m records, which always fit).
+extern "C" rkr_status rkr_ranks_noalloc(rkr_index *x, const void *q, int32_t *ranks_out) {
+    g_err.clear();
+    if (!x || !q || !ranks_out) return fail(RKR_E_INVALID, "NULL argument");
+    const int64_t n = x->n, m = x->m;
+    if (n > kNoAllocMaxUsers) return fail(RKR_E_UNSUPPORTED, "rkr_ranks_noalloc: more than 2^20 users");
+    if (m > kNoAllocMaxItems) return fail(RKR_E_UNSUPPORTED, "rkr_ranks_noalloc: more than 2^22 items");
+    uint8_t *base = nullptr;
+    rkr_status rs = scratch_address(x->dev, &base);
+    if (rs != RKR_OK) return rs;
+    hipStream_t st = x->st;
+    const double t0 = now_ms();
+    // pieces for every user
+    Carve cv{base};
+    double *t64 = cv.take<double>(n);
+    int32_t *pair_u = cv.take<int32_t>(n);
+    int32_t *pair_q = cv.take<int32_t>(n);
+    uint32_t *cnt = cv.take<uint32_t>(n);
+    unsigned long long *ctr = cv.take<unsigned long long>(8);
+    int *flags = cv.take<int>(4);
+    const size_t fixed = cv.used;
+    PairSet ps;
+    ps.nq = 1;
+    ps.dense = 1;
+    ps.npairs = n;
+    ps.pair_u = pair_u;
+    ps.pair_q = pair_q;
+    ps.t64 = t64;
+    HIPCK(launch_fill_u32((uint32_t *)flags, 0, 4, st));
+    HIPCK(launch_check_values(q, x->d, x->mk, flags, st));
+    HIPCK(launch_dense_pairs(n, 1, pair_u, pair_q, st));
+    HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, t64, st));
+    int hflags = 0;
+    HIPCK(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (hflags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
+
+    x->stats = rkr_query_stats{};
+    x->stats.queries = 1;
+    x->stats.pairs = n;
+    const int xv = exact_variant(x);
+    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+    // first chunk: every user, or as many as leave half of the array to records
+    const size_t per_task_max = 36 + 4 * 16;   // entry lists with up to 16 item splits
+    int64_t chunk = std::min<int64_t>(n, (int64_t)((kNoAllocBytes - fixed) / 2 / per_task_max));
+    chunk = std::max<int64_t>(chunk, 1);
+    int64_t u0 = 0;
+    while (u0 < n) {
+        const int64_t C = std::min<int64_t>(chunk, n - u0);
+        const int64_t ntp = (C + 511) / 512 * 512;
+        Carve cc{base, fixed};
+        TaskSet ts;
+        ts.task_user = cc.take<int32_t>(ntp);
+        ts.len = cc.take<int32_t>(ntp);
+        ts.blk_base = cc.take<int64_t>(ntp / 32 + 1);
+        ts.ent_pid = cc.take<int32_t>(ntp);
+        ts.ent_q = cc.take<int32_t>(ntp);
+        ts.ent_th = cc.take<float>(ntp);
+        ts.ent_tl = cc.take<float>(ntp);
+        ts.ent_tm = cc.take<float>(ntp);
+        ts.ntask = C;
+        ts.ntask_pad = ntp;
+        ts.cap_total = ntp;
+        CountArgs a = count_args(x, ps, ts, xv);
+        const int64_t nsteps = a.nsteps;
+        int64_t nsplit = pick_nsplit((C + tpw - 1) / tpw, nsteps, x->num_cus);
+        a.steps_per_split = (nsteps + nsplit - 1) / nsplit;
+        nsplit = std::max<int64_t>(1, (nsteps + a.steps_per_split - 1) / std::max<int64_t>(a.steps_per_split, 1));
+        ts.ent_cnt = cc.take<uint32_t>(ntp * nsplit);
+        a.ent_cnt = ts.ent_cnt;
+        if (cc.used + 8 * 1024 > kNoAllocBytes) return fail(RKR_E_DEVICE, "rkr_ranks_noalloc: scratch layout");
+        int2 *emit = (int2 *)(base + cc.used);
+        const int64_t emit_cap = (int64_t)((kNoAllocBytes - cc.used) / sizeof(int2));
+        a.cnt_out = cnt;
+        a.emit = emit;
+        a.emit_count = ctr;
+        a.emit_cap = (unsigned long long)emit_cap;
+        a.stat = ctr + 1;
+        HIPCK(launch_fill_u32((uint32_t *)ctr, 0, 16, st));
+        HIPCK(q_tasks_one_per_user(C, ntp, ps, x->recheck ? 0 : 1, ts, st, u0));
+        HIPCK(launch_fill_u32(cnt + u0, 0, C, st));
+        HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, xv, st));
+        unsigned long long c8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        HIPCK(hipMemcpyAsync(c8, ctr, 64, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        const unsigned long long ne = c8[0];
+        if (ne > (unsigned long long)emit_cap) {
+            if (C == 1) return fail(RKR_E_DEVICE, "rkr_ranks_noalloc: near ties of one user exceed the scratch array");
+            // too many near ties for this chunk: count it again in smaller chunks
+            x->stats.emit_retries += 1;
+            const double shrink = 0.8 * (double)emit_cap / (double)ne;
+            chunk = std::max<int64_t>(1, std::min<int64_t>(C / 2, (int64_t)((double)C * shrink)));
+            continue;
+        }
+        HIPCK(launch_recheck(emit, (int64_t)ne, pair_u, t64, x->Um.p, x->Pm.p, x->d, x->mk, cnt, ctr + 2, st));
+        HIPCK(q_ranks_out(cnt + u0, C, ranks_out + u0, st));
+        unsigned long long flips = 0;
+        HIPCK(hipMemcpyAsync(&flips, ctr + 2, 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        x->stats.uncertain += (int64_t)ne;
+        x->stats.compares += (int64_t)c8[1];
+        x->stats.flips += (int64_t)flips;
+        x->stats.mfma_flop += (int64_t)c8[5];
+        x->stats.scored_pairs += (int64_t)c8[7];
+        u0 += C;
+    }
+    x->stats.refined_pairs = n;
+    x->stats.scored_exact = x->stats.scored_pairs;
+    x->stats.ms_total = now_ms() - t0;
     return RKR_OK;
 }
 

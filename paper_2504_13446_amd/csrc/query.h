@@ -60,8 +60,9 @@ hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_o
                        hipStream_t st);
 hipError_t q_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int32_t *ranks, hipStream_t st);
 hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream_t st);
+// tasks of the n users u0 .. u0 + n - 1, one entry each (pair id = user id)
 hipError_t q_tasks_one_per_user(int64_t n, int64_t ntask_pad, const PairSet &ps, int plain, TaskSet &ts,
-                                hipStream_t st);
+                                hipStream_t st, int64_t u0 = 0);
 hipError_t q_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
 // keep[pid] = 1 for the non-seed pairs the rank table cannot rule out
 // (tab_t, tab_cnt: [n][TABLE_COLS] thresholds and certain counts)

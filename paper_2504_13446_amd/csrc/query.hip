@@ -217,24 +217,24 @@ __global__ void k_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks) {
     if (i < n) ranks[i] = (int32_t)(1u + cnt[i]);
 }
 
-// One entry per user (single query, every user): task t = user t, block b's
+// One entry per user (single query): task t = user u0 + t (t < n), block b's
 // entries at 32 b + lane.  Built without host round trips so the whole
 // single-query pipeline can be captured in a graph.
-__global__ void k_tasks_one_per_user(int64_t n, int64_t ntask_pad, const double *t64, int plain,
+__global__ void k_tasks_one_per_user(int64_t n, int64_t ntask_pad, int64_t u0, const double *t64, int plain,
                                      int32_t *task_user, int32_t *len,
                                      int64_t *blk_base, int32_t *ent_pid, int32_t *ent_q, uint32_t *ent_cnt,
                                      float *ent_th, float *ent_tl, float *ent_tm) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntask_pad) return;
     const bool real = t < n;
-    task_user[t] = real ? (int32_t)t : -1;
+    task_user[t] = real ? (int32_t)(u0 + t) : -1;
     len[t] = real ? 1 : 0;
     if ((t & 31) == 0) blk_base[t >> 5] = t;
-    ent_pid[t] = real ? (int32_t)t : 0;
+    ent_pid[t] = real ? (int32_t)(u0 + t) : 0;
     ent_q[t] = 0;
     ent_cnt[t] = 0;
     // the FP32 values bracketing t (see k_fill_entries)
-    const double tv = real ? t64[t] : 0.0;
+    const double tv = real ? t64[u0 + t] : 0.0;
     const float tm = (float)tv;
     ent_th[t] = real ? (plain ? tm : f32_round_up(tv)) : 0.0f;
     ent_tl[t] = real ? (plain ? tm : f32_round_down(tv)) : 0.0f;
@@ -758,8 +758,8 @@ hipError_t q_write_answer(const uint64_t *keys, int64_t total, int32_t *ids, int
     return hipGetLastError();
 }
 hipError_t q_tasks_one_per_user(int64_t n, int64_t ntask_pad, const PairSet &ps, int plain, TaskSet &ts,
-                                hipStream_t st) {
-    LAUNCH1D(k_tasks_one_per_user, ntask_pad, n, ntask_pad, ps.t64, plain, ts.task_user, ts.len,
+                                hipStream_t st, int64_t u0) {
+    LAUNCH1D(k_tasks_one_per_user, ntask_pad, n, ntask_pad, u0, ps.t64, plain, ts.task_user, ts.len,
              ts.blk_base, ts.ent_pid, ts.ent_q, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
     return hipGetLastError();
 }

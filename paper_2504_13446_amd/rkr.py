@@ -26,7 +26,7 @@ SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
-           "rkr_query_table", "rkr_query_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
+           "rkr_query_table", "rkr_query_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_mlp_adam", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "rkr_query_table_batch": [vp, i32, vp, vp, vp, vp, vp],
         "rkr_query_batch": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rkr_ranks": [vp, vp, vp],
+        "rkr_ranks_noalloc": [vp, vp, vp],
         "rkr_train": [vp, i32, vp, i32, i32, i32, f32, ctypes.c_uint64],
         "rkr_predict": [vp, i32, vp, vp],
         "rkr_mlp_get": [vp, vp],
@@ -233,6 +234,13 @@ def rkr_query_batch(h: int, Q: torch.Tensor, k, c=None, cand_off=None, cand_ids=
 def rkr_ranks(h: int, q: torch.Tensor, n: int) -> torch.Tensor:
     out = torch.empty(n, dtype=torch.int32, device=q.device)
     _check(load().rkr_ranks(h, _ptr(q), _ptr(out)))
+    return out
+
+
+def rkr_ranks_noalloc(h: int, q: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """rkr_ranks into a caller-provided int32 tensor, with no device allocation."""
+    assert out.dtype == torch.int32 and out.is_contiguous()
+    _check(load().rkr_ranks_noalloc(h, _ptr(q), _ptr(out)))
     return out
 
 
