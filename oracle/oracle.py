@@ -24,6 +24,10 @@ What is computed, and where the paper defines it (arXiv 2504.13446):
                    whose partial count already puts them behind the k best
                    found so far stop counting (Lemma 1 (2) on exact counts);
                    the result equals topk(ranks(...)) (see orc_topk_abandon).
+* ``paper_table``, ``paper_table_query`` -- the paper's own method: Alg. 1
+                   (Sec. 4.2: norm-sorted buckets, uniform thresholds between
+                   the footnote's domain values, cells estimated from random
+                   samples per bucket) and the query's three steps (Sec. 4.3).
 * ``norm_order``, ``stratified_sample``, ``sketch`` -- the per-user score
                    sketch: P ordered by norm, descending (Sec. 4.2 step 1),
                    split into equal buckets with one sample from the middle
@@ -73,13 +77,15 @@ def lib():
                                   i64, vp, vp, ctypes.c_int]
         L.orc_topk_abandon.argtypes = [vp, i64, vp, i64, vp, vp, ctypes.c_int, ctypes.c_int, vp,
                                        i64, vp, vp, vp, ctypes.c_int]
+        L.orc_paper_table.argtypes = [vp, i64, vp, i64, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, vp, vp, vp, vp, ctypes.c_int]
         L.orc_norm_order.argtypes = [vp, i64, vp]
         L.orc_sketch.argtypes = [vp, i64, vp, vp, i64, ctypes.c_int, vp, ctypes.c_int, vp,
                                  ctypes.c_int]
         L.orc_rank_table.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.c_int, vp, ctypes.c_int,
                                      vp, vp, ctypes.c_int]
         for f in (L.orc_dots, L.orc_norms, L.orc_ranks, L.orc_certify, L.orc_norm_order,
-                  L.orc_sketch, L.orc_rank_table, L.orc_topk_abandon):
+                  L.orc_sketch, L.orc_rank_table, L.orc_topk_abandon, L.orc_paper_table):
             f.restype = None
         _lib = L
     return _lib
@@ -298,6 +304,87 @@ def table_query(t, cnt, tq, m: int, k: int, c: float):
     ids = np.concatenate([first, fill]).astype(np.int32)
     out = np.concatenate([r_hi[first].astype(np.float64), est[fill]])
     return ids, out
+
+
+def paper_table(U, P, tau: int, omega: int, s: int, sample_pos, threads: int = 0):
+    """The paper's rank table (Sec. 4.2, Alg. 1) with estimated cells (see
+    orc_paper_table): returns (fmin [n], step [n], T [n, tau] float32).
+    sample_pos [omega * s]: positions within each bucket (the random draws)."""
+    U = widen(U); P = widen(P)
+    n, d = U.shape
+    m = P.shape[0]
+    order = norm_order(P)
+    pos = np.ascontiguousarray(np.asarray(sample_pos, np.int32).reshape(-1))
+    assert pos.shape[0] == omega * s and tau >= 2
+    fmin = np.empty(n, np.float64)
+    step = np.empty(n, np.float64)
+    T = np.empty((n, tau), np.float32)
+    lib().orc_paper_table(_p(U), n, _p(P), m, _p(order), d, int(tau), int(omega), int(s), _p(pos),
+                          _p(fmin), _p(step), _p(T), int(threads))
+    return fmin, step, T
+
+
+def paper_table_thresholds(fmin, step, tau: int) -> np.ndarray:
+    """t[u][j] = fmin[u] + j * step[u] (j = 0..tau-1), one FP64 product and
+    one FP64 sum each, as Alg. 1 step 2 spaces them."""
+    j = np.arange(tau, dtype=np.float64)
+    return np.asarray(fmin, np.float64)[:, None] + j[None, :] * np.asarray(step, np.float64)[:, None]
+
+
+def paper_table_bounds(fmin, step, T, tq, m: int):
+    """Query step 1 (Sec. 4.3) on the paper's table: with ascending thresholds
+    t[j] and L = #{j : t[j] <= u.q}, u.q lies in [t[L-1], t[L]), so
+    r_lo = T[L] (1 when L = tau) and r_hi = T[L-1] (m + 1 when L = 0), both
+    FP32 as the cells.  Returns (L, r_lo, r_hi, t)."""
+    T = np.asarray(T, np.float32)
+    n, tau = T.shape
+    t = paper_table_thresholds(fmin, step, tau)
+    tq = np.asarray(tq, np.float64)
+    L = np.sum(t <= tq[:, None], axis=1)
+    ids = np.arange(n)
+    r_lo = np.where(L == tau, np.float32(1.0), T[ids, np.minimum(L, tau - 1)]).astype(np.float32)
+    r_hi = np.where(L == 0, np.float32(m + 1), T[ids, np.maximum(L - 1, 0)]).astype(np.float32)
+    return L, r_lo, r_hi, t
+
+
+def paper_table_query(fmin, step, T, tq, m: int, k: int, c: float):
+    """The paper's query (Sec. 4.3, steps 1-3) on its own table, one query.
+
+    Step 1 as paper_table_bounds; R_lo_k, R_hi_k are the k-th smallest r_lo
+    and r_hi.  Step 2: if c R_lo_k >= R_hi_k the answer is the k users of
+    smallest r_hi (ties by id); otherwise the users with r_hi <= c R_lo_k come
+    first (by r_hi, id), users with r_lo > R_hi_k are ruled out (Lemma 1 (2))
+    and the rest stay open.  Step 3 fills the answer with the open users of
+    smallest estimate, linear in u.q between (t[L-1], r_hi) and (t[L], r_lo),
+    r_lo at either end of the row or between equal thresholds, ordered by the
+    estimate rounded to FP32, ties by id.  Comparisons with c R_lo_k are in
+    FP64.  Returns (ids, values): the value each user was chosen by."""
+    L, r_lo, r_hi, t = paper_table_bounds(fmin, step, T, tq, m)
+    n, tau = t.shape
+    ids_all = np.arange(n, dtype=np.int64)
+    R_lo_k = np.sort(r_lo)[k - 1]
+    R_hi_k = np.sort(r_hi)[k - 1]
+    by_hi = np.lexsort((ids_all, r_hi))
+    if c * float(R_lo_k) >= float(R_hi_k):
+        sel = by_hi[:k]
+        return sel.astype(np.int32), r_hi[sel].astype(np.float64)
+    admit = r_hi.astype(np.float64) <= c * float(R_lo_k)
+    first = by_hi[admit[by_hi]]
+    rest = (~admit) & (r_lo <= R_hi_k)
+    inner = (L > 0) & (L < tau)
+    tA = t[ids_all, np.maximum(L - 1, 0)]
+    tB = t[ids_all, np.minimum(L, tau - 1)]
+    ok = inner & (tB > tA)
+    lo64, hi64 = r_lo.astype(np.float64), r_hi.astype(np.float64)
+    frac = np.where(ok, (np.asarray(tq, np.float64) - tA) / np.where(ok, tB - tA, 1.0), 0.0)
+    est = np.where(ok, hi64 + (lo64 - hi64) * frac, lo64)
+    est32 = est.astype(np.float32)
+    cand = ids_all[rest]
+    order = cand[np.lexsort((cand, est32[cand]))]
+    fill = order[:k - first.shape[0]]
+    ids = np.concatenate([first, fill]).astype(np.int32)
+    vals = np.concatenate([hi64[first], est[fill]])
+    return ids, vals
 
 
 # --------------------------------------------------------------------------

@@ -456,3 +456,83 @@ void orc_topk_abandon(const double *U, int64_t n, const double *P, int64_t m,
     free(heap);
     free(vis);
 }
+
+/*
+ * The paper's rank table (Sec. 4.2, Alg. 1), with estimated cells.
+ *   Step 1: the items in norm order (order[0..m-1], descending norm) are cut
+ *     into omega equally sized buckets: bucket l holds the positions
+ *     [floor(l m / omega), floor((l + 1) m / omega)).
+ *   Sampling: bucket l's samples are the items at the positions
+ *     sample_pos[l * s + i] of that bucket, i < s_l = min(s, |P_l|) (the
+ *     random draws are inputs).
+ *   Step 2: tau uniform thresholds between f_min and f_max, here the
+ *     footnote's domain values: f_max = |u| max_p |p| (Cauchy-Schwarz),
+ *     f_min = -f_max, with |x| the spec norm; t_j = f_min + j * step for
+ *     j = 0..tau-1 (ascending), step = (f_max - f_min) / (tau - 1).
+ *   Step 3: every cell starts at 1 and each bucket adds, in bucket order,
+ *     (A_l[j] |P_l|) / s_l with A_l[j] = #{sampled p of bucket l : s(u,p) >
+ *     t_j} (eq. of the cell estimator; with s_l = |P_l| the cell is exactly
+ *     1 + #{p : s(u,p) > t_j}).  The cell is kept in FP32 (round to nearest).
+ * Outputs per user: fmin_out[u], step_out[u], T_out[u * tau + j].
+ */
+void orc_paper_table(const double *U, int64_t n, const double *P, int64_t m,
+                     const int64_t *order, int d, int tau, int omega, int s,
+                     const int32_t *sample_pos, double *fmin_out, double *step_out,
+                     float *T_out, int nthreads)
+{
+    set_threads(nthreads);
+    double pmax = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double x = sqrt(spec_dot(P + i * d, P + i * d, d));
+        if (x > pmax)
+            pmax = x;
+    }
+#pragma omp parallel
+    {
+        double *T = (double *)malloc(sizeof(double) * (size_t)tau);
+        double *t = (double *)malloc(sizeof(double) * (size_t)tau);
+        int64_t *A = (int64_t *)malloc(sizeof(int64_t) * (size_t)tau);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t ui = 0; ui < n; ++ui) {
+            const double *u = U + ui * d;
+            const double fmax = sqrt(spec_dot(u, u, d)) * pmax;
+            const double fmin = -fmax;
+            const double step = (fmax - fmin) / (double)(tau - 1);
+            for (int j = 0; j < tau; ++j) {
+                t[j] = fmin + (double)j * step;
+                T[j] = 1.0;
+            }
+            for (int l = 0; l < omega; ++l) {
+                const int64_t b0 = (int64_t)l * m / omega, b1 = (int64_t)(l + 1) * m / omega;
+                const int64_t size = b1 - b0;
+                const int64_t sl = size < s ? size : s;
+                if (sl == 0)
+                    continue;
+                for (int j = 0; j < tau; ++j)
+                    A[j] = 0;
+                /* each sample adds 1 to A[j] for every threshold it is above;
+                   the thresholds ascend, so the first one it is not above
+                   ends its walk */
+                for (int64_t i = 0; i < sl; ++i) {
+                    const double *p = P + order[b0 + sample_pos[(int64_t)l * s + i]] * d;
+                    const double sc = spec_dot(u, p, d);
+                    for (int j = 0; j < tau; ++j) {
+                        if (sc > t[j])
+                            A[j] += 1;
+                        else
+                            break;
+                    }
+                }
+                for (int j = 0; j < tau; ++j)
+                    T[j] = T[j] + ((double)A[j] * (double)size) / (double)sl;
+            }
+            fmin_out[ui] = fmin;
+            step_out[ui] = step;
+            for (int j = 0; j < tau; ++j)
+                T_out[ui * tau + j] = (float)T[j];
+        }
+        free(A);
+        free(t);
+        free(T);
+    }
+}

@@ -153,3 +153,21 @@ def make(name: str, n: int | None = None, m: int | None = None, d: int | None = 
         kk = np.minimum(kk, sizes.astype(np.int32))
     return Workload(name=name, n=n, m=m, d=d, dtype=dtype, U=U, P=P, qidx=qidx, Qv=Qv, k=kk,
                     c=spec.get("c"), cand_off=cand_off, cand_ids=cand_ids)
+
+
+def bucket_sample_positions(m: int, omega: int, s: int, seed: int = 13446) -> np.ndarray:
+    """Random draws of the paper's sampling (Sec. 4.2, Alg. 1): for each of the
+    omega buckets of a partition of m items into equal parts (bucket l holds
+    floor((l + 1) m / omega) - floor(l m / omega) items), s distinct positions
+    within the bucket, uniform without replacement (all of them, in order,
+    when the bucket holds s or fewer; the remaining slots are -1).  int32
+    [omega * s]."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, m, omega, s]))
+    out = np.full(omega * s, -1, np.int32)
+    for l in range(omega):
+        size = (l + 1) * m // omega - l * m // omega
+        if size <= s:
+            out[l * s:l * s + size] = np.arange(size, dtype=np.int32)
+        else:
+            out[l * s:(l + 1) * s] = rng.choice(size, size=s, replace=False).astype(np.int32)
+    return out
