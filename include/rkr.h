@@ -202,6 +202,58 @@ rkr_status rkr_query_table_batch(rkr_index *idx, int32_t nq, const void *Qm, con
                                  const double *c, int32_t *ids_out, double *est_out);
 
 /*
+ * The paper's own rank table (Sec. 4.2, Alg. 1), with estimated cells:
+ *   step 1: the items in norm order (descending, ties by id) are cut into
+ *     omega equally sized buckets; bucket l holds the positions
+ *     [floor(l m / omega), floor((l + 1) m / omega)) of that order;
+ *   sampling: bucket l's samples are at the positions sample_pos[l * s + i]
+ *     of the bucket, i < s_l = min(s, |P_l|) [host, omega * s int32; the
+ *     random draws are the caller's; slots past s_l are ignored];
+ *   step 2: tau thresholds spaced uniformly between f_min and f_max, with
+ *     the paper's footnote's domain values f_max = |u| max_p |p| (Cauchy-
+ *     Schwarz) and f_min = -f_max: t_j = f_min + j (f_max - f_min) / (tau - 1),
+ *     j = 0 .. tau - 1, ascending (|x| is the FP64 spec norm);
+ *   step 3: cell T_j = 1 + sum over buckets, in order, of
+ *     (A_l[j] |P_l|) / s_l with A_l[j] = #{sampled p of bucket l : u.p > t_j}
+ *     (the cell estimator of Sec. 4.2), in FP64, stored in FP32.
+ * The table lives in the index (8 n bytes of f_min, 8 n of step, 4 n tau of
+ * cells) and replaces any earlier one.  Errors: RKR_E_INVALID for tau < 2,
+ * omega < 1 or s < 1, a position outside its bucket or repeated within it;
+ * RKR_E_UNSUPPORTED for tau > 2047 or omega * s > 2^22.
+ */
+rkr_status rkr_paper_table_build(rkr_index *idx, int32_t tau, int32_t omega, int32_t s,
+                                 const int32_t *sample_pos);
+
+/*
+ * The paper's table: fmin_out [device, n double] (f_min per user),
+ * step_out [device, n double] (threshold spacing), cells_out [device,
+ * n x tau float].  RKR_E_STATE without one.
+ */
+rkr_status rkr_paper_table(const rkr_index *idx, double *fmin_out, double *step_out, float *cells_out);
+
+/*
+ * The paper's query (Sec. 4.3, steps 1-3) on its own table, for nq queries
+ * Qm [device, nq x d], k[nq] and c[nq] [host]:
+ *   step 1: with L = #{j : t_j <= u.q}, r_lo = T_L (1 when L = tau) and
+ *     r_hi = T_{L-1} (m + 1 when L = 0), FP32; R_lo_k, R_hi_k the k-th
+ *     smallest of each;
+ *   step 2: if c R_lo_k >= R_hi_k the answer is the k users of smallest r_hi
+ *     (ties by id); otherwise the users with r_hi <= c R_lo_k come first (by
+ *     r_hi, id), users with r_lo > R_hi_k are ruled out (Lemma 1 (2)) and
+ *     step 3 fills the answer with the others of smallest estimate, linear
+ *     in u.q between (t_{L-1}, r_hi) and (t_L, r_lo) (r_lo at either end of
+ *     the row), ordered by the estimate rounded to FP32, ties by id.
+ * Query i's answer is at offset k[0] + ... + k[i-1] of ids_out [device,
+ * int32] and val_out [device, double] (the bound or estimate each user was
+ * chosen by).  An estimate: Def. 3 is not guaranteed.  Errors as
+ * rkr_query_table_batch, RKR_E_STATE without a paper table.
+ */
+rkr_status rkr_query_paper_table_batch(rkr_index *idx, int32_t nq, const void *Qm, const int32_t *k,
+                                       const double *c, int32_t *ids_out, double *val_out);
+rkr_status rkr_query_paper_table(rkr_index *idx, const void *q, int32_t k, double c, int32_t *ids_out,
+                                 double *val_out);
+
+/*
  * Batch of nq queries Qm [device, nq x d] sharing one pass over U.P^T.
  *   k        [host, nq]      answer size per query
  *   c        [host, nq]      NULL: exact answers (Def. 2); else c[i] >= 1

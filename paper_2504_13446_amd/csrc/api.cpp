@@ -42,6 +42,7 @@
 #include "query.h"
 #include "rkr.h"
 #include "mlp.h"
+#include "paper_table.h"
 
 using namespace rkr;
 
@@ -180,6 +181,11 @@ struct rkr_index {
     // round-ups, and certain counts over all of P
     DBuf tab_t, tab_th, tab_cnt;
     bool has_table = false;
+    // the paper's own rank table (Alg. 1, Sec. 4.2): per user f_min and the
+    // threshold step (FP64), and [n][ptab_tau] estimated cells (FP32)
+    DBuf ptab_fmin, ptab_step, ptab_cells;
+    int ptab_tau = 0;
+    bool has_ptab = false;
     int64_t emit_cap = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     rkr_query_opts qo{};
@@ -325,7 +331,7 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
 extern "C" void rkr_destroy(rkr_index *x) {
     if (!x) return;
     (void)hipStreamSynchronize(x->st);
-    DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt,
+    DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt, &x->ptab_fmin, &x->ptab_step, &x->ptab_cells,
                     &x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
                     &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
                     &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
@@ -1274,11 +1280,16 @@ extern "C" rkr_status rkr_ranks_noalloc(rkr_index *x, const void *q, int32_t *ra
 // ---------------------------------------------------------------------------
 // the paper's table query (Sec. 4.3, steps 1-3) on the index's rank table
 // ---------------------------------------------------------------------------
-extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k,
-                                            const double *c, int32_t *ids_out, double *est_out) {
+// The query of Sec. 4.3 on a rank table: the exact-cell table built with the
+// index (paper = false) or the paper's estimated table of Alg. 1 (paper =
+// true, whose bounds are FP32 values: the keys carry their order keys).
+static rkr_status table_query_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k, const double *c,
+                                    int32_t *ids_out, double *est_out, bool paper) {
     g_err.clear();
     if (!x || !Qm || !k || !c || !ids_out || !est_out) return fail(RKR_E_INVALID, "NULL argument");
-    if (!x->has_table) return fail(RKR_E_STATE, "index built without a rank table");
+    if (!paper && !x->has_table) return fail(RKR_E_STATE, "index built without a rank table");
+    if (paper && !x->has_ptab) return fail(RKR_E_STATE, "no paper rank table (rkr_paper_table_build)");
+    const int fk = paper ? 1 : 0;
     if (nq < 1 || nq > 65535) return fail(RKR_E_INVALID, "nq must be in [1, 65535]");
     const int64_t n = x->n;
     if (n * (int64_t)nq >= ((int64_t)1 << 31)) return fail(RKR_E_UNSUPPORTED, "n * nq must stay below 2^31");
@@ -1323,15 +1334,19 @@ extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(Qm, (int64_t)nq * x->d, x->mk, x->flags.as<int>(), st));
     HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), st));
-    HIPCK(q_tqb_bounds(n, nq, x->m, x->t64.as<double>(), x->tab_t.as<double>(), x->tab_cnt.as<uint32_t>(), key_lo,
-                       key_hi, est, st));
+    if (paper)
+        HIPCK(launch_ptq_bounds(n, nq, x->m, x->ptab_tau, x->t64.as<double>(), x->ptab_fmin.as<double>(),
+                                x->ptab_step.as<double>(), x->ptab_cells.as<float>(), key_lo, key_hi, est, st));
+    else
+        HIPCK(q_tqb_bounds(n, nq, x->m, x->t64.as<double>(), x->tab_t.as<double>(), x->tab_cnt.as<uint32_t>(),
+                           key_lo, key_hi, est, st));
     // R_lo_k, R_hi_k per query and the case of step 2
     HIPCK(launch_select(key_lo, d_seg, d_k, nq, d_off, sel_lo, st));
     HIPCK(launch_select(key_hi, d_seg, d_k, nq, d_off, sel_hi, st));
-    HIPCK(q_tqb_kth(nq, d_k, d_c, sel_lo, sel_hi, d_off, d_Rlo, d_Rhi, d_first, st));
+    HIPCK(q_tqb_kth(nq, d_k, d_c, sel_lo, sel_hi, d_off, d_Rlo, d_Rhi, d_first, st, fk));
     // step 2, second case: admitted users and the users left open
     HIPCK(launch_fill_u32((uint32_t *)d_nadm, 0, 2 * (int64_t)nq, st));
-    HIPCK(q_tqb_classify(n, nq, d_c, d_Rlo, d_Rhi, d_first, key_lo, key_hi, est, key_c, key_t, d_nadm, st));
+    HIPCK(q_tqb_classify(n, nq, d_c, d_Rlo, d_Rhi, d_first, key_lo, key_hi, est, key_c, key_t, d_nadm, st, fk));
     std::vector<unsigned long long> nadm(nq);
     std::vector<int32_t> first(nq), nc(nq), nt(nq);
     int flags = 0;
@@ -1358,16 +1373,119 @@ extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void
     HIPCK(launch_select(key_c, d_seg, d_nc, nq, d_offc, sel_c, st));
     HIPCK(launch_select(key_t, d_seg, d_nt, nq, d_offt, sel_t, st));
     HIPCK(q_tqb_answer(nq, n, total, d_off, d_first, d_off, sel_hi, d_nc, d_offc, sel_c, d_offt, sel_t, est, ids_out,
-                       est_out, st));
+                       est_out, st, fk));
     HIPCK(hipStreamSynchronize(st));
     x->stats.survivors = admitted;
     x->stats.ms_total = now_ms() - t0;
     return RKR_OK;
 }
 
+extern "C" rkr_status rkr_query_table_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k,
+                                            const double *c, int32_t *ids_out, double *est_out) {
+    return table_query_batch(x, nq, Qm, k, c, ids_out, est_out, false);
+}
+
 extern "C" rkr_status rkr_query_table(rkr_index *x, const void *q, int32_t k, double c, int32_t *ids_out,
                                       double *est_out) {
     return rkr_query_table_batch(x, 1, q, &k, &c, ids_out, est_out);
+}
+
+// ---------------------------------------------------------------------------
+// the paper's own rank table (Alg. 1, Sec. 4.2) and its query (Sec. 4.3)
+// ---------------------------------------------------------------------------
+extern "C" rkr_status rkr_paper_table_build(rkr_index *x, int32_t tau, int32_t omega, int32_t s,
+                                            const int32_t *sample_pos) {
+    g_err.clear();
+    if (!x || !sample_pos) return fail(RKR_E_INVALID, "NULL argument");
+    if (tau < 2) return fail(RKR_E_INVALID, "tau must be at least 2");
+    if (tau > paper_table_tau_max())
+        return fail(RKR_E_UNSUPPORTED, "tau above " + std::to_string(paper_table_tau_max()));
+    if (omega < 1 || s < 1) return fail(RKR_E_INVALID, "omega and s must be positive");
+    if ((int64_t)omega * s > ((int64_t)1 << 22)) return fail(RKR_E_UNSUPPORTED, "omega * s above 2^22");
+    const int64_t n = x->n, m = x->m;
+    const int d = x->d;
+    hipStream_t st = x->st;
+    // buckets of the norm-sorted items and the positions of their samples
+    std::vector<int32_t> soff(omega + 1, 0), idx;
+    std::vector<int64_t> bsize(omega, 0);
+    for (int l = 0; l < omega; ++l) {
+        const int64_t b0 = (int64_t)l * m / omega, b1 = (int64_t)(l + 1) * m / omega;
+        const int64_t size = b1 - b0, sl = std::min<int64_t>(s, size);
+        bsize[l] = size;
+        std::vector<int32_t> seen(sample_pos + (int64_t)l * s, sample_pos + (int64_t)l * s + sl);
+        for (int32_t v : seen)
+            if (v < 0 || v >= size)
+                return fail(RKR_E_INVALID, "sample position out of its bucket (bucket " + std::to_string(l) + ")");
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            return fail(RKR_E_INVALID, "sample positions repeat within bucket " + std::to_string(l));
+        for (int64_t i = 0; i < sl; ++i) idx.push_back((int32_t)(b0 + sample_pos[(int64_t)l * s + i]));
+        soff[l + 1] = soff[l] + (int32_t)sl;
+    }
+    const int ns = soff[omega];
+    const int mes = x->mk == MK_BF16 ? 2 : 4;
+    x->has_ptab = false;
+    x->sc.reset();
+    HIPCK(x->ptab_fmin.ensure(n * 8));
+    HIPCK(x->ptab_step.ensure(n * 8));
+    HIPCK(x->ptab_cells.ensure(n * (int64_t)tau * 4));
+    double *unorm = (double *)x->sc.take(n * 8);
+    double *pmax = (double *)x->sc.take(8);
+    int32_t *d_soff = (int32_t *)x->sc.take((omega + 1) * 4);
+    int64_t *d_bsize = (int64_t *)x->sc.take(omega * 8);
+    int32_t *d_idx = (int32_t *)x->sc.take(std::max(ns, 1) * 4);
+    void *Sm = x->sc.take((int64_t)std::max(ns, 1) * d * mes);
+    // sample scores of a chunk of users: at most 2^28 doubles
+    const int64_t chunk = std::max<int64_t>(64, (((int64_t)1 << 28) / std::max(ns, 1)) / 64 * 64);
+    const int64_t cu = std::min<int64_t>(n, chunk);
+    double *S = (double *)x->sc.take(cu * std::max(ns, 1) * 8);
+    if (!unorm || !pmax || !d_soff || !d_bsize || !d_idx || !Sm || !S)
+        return fail(RKR_E_NOMEM, "out of device memory (paper rank table)");
+    HIPCK(hipMemcpyAsync(d_soff, soff.data(), (omega + 1) * 4, hipMemcpyHostToDevice, st));
+    HIPCK(hipMemcpyAsync(d_bsize, bsize.data(), omega * 8, hipMemcpyHostToDevice, st));
+    if (ns > 0) {
+        HIPCK(hipMemcpyAsync(d_idx, idx.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+        HIPCK(launch_gather_rows(x->Pm.p, d_idx, ns, d, x->mk, Sm, st));
+    }
+    HIPCK(launch_spec_norm(x->Um.p, n, d, x->mk, unorm, st));
+    // the items are in norm order: the first has the largest spec norm
+    if (m > 0)
+        HIPCK(launch_spec_norm(x->Pm.p, 1, d, x->mk, pmax, st));
+    else
+        HIPCK(launch_fill_u32((uint32_t *)pmax, 0, 2, st));
+    for (int64_t u0 = 0; u0 < n; u0 += cu) {
+        const int64_t nu = std::min<int64_t>(cu, n - u0);
+        if (ns > 0)
+            HIPCK(launch_thresh_dense((const uint8_t *)x->Um.p + u0 * d * mes, nu, Sm, ns, d, x->mk, S, st));
+        HIPCK(launch_ptab_cells(u0, nu, S, ns, omega, d_soff, d_bsize, tau, unorm, pmax, x->ptab_fmin.as<double>(),
+                                x->ptab_step.as<double>(), x->ptab_cells.as<float>(), st));
+    }
+    HIPCK(hipStreamSynchronize(st));
+    x->sc.reset();
+    x->ptab_tau = tau;
+    x->has_ptab = true;
+    return RKR_OK;
+}
+
+extern "C" rkr_status rkr_paper_table(const rkr_index *x, double *fmin_out, double *step_out, float *cells_out) {
+    g_err.clear();
+    if (!x || !fmin_out || !step_out || !cells_out) return fail(RKR_E_INVALID, "NULL argument");
+    if (!x->has_ptab) return fail(RKR_E_STATE, "no paper rank table (rkr_paper_table_build)");
+    HIPCK(hipMemcpyAsync(fmin_out, x->ptab_fmin.p, x->n * 8, hipMemcpyDeviceToDevice, x->st));
+    HIPCK(hipMemcpyAsync(step_out, x->ptab_step.p, x->n * 8, hipMemcpyDeviceToDevice, x->st));
+    HIPCK(hipMemcpyAsync(cells_out, x->ptab_cells.p, x->n * (int64_t)x->ptab_tau * 4, hipMemcpyDeviceToDevice, x->st));
+    HIPCK(hipStreamSynchronize(x->st));
+    return RKR_OK;
+}
+
+extern "C" rkr_status rkr_query_paper_table_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k,
+                                                  const double *c, int32_t *ids_out, double *val_out) {
+    return table_query_batch(x, nq, Qm, k, c, ids_out, val_out, true);
+}
+
+extern "C" rkr_status rkr_query_paper_table(rkr_index *x, const void *q, int32_t k, double c, int32_t *ids_out,
+                                            double *val_out) {
+    return rkr_query_paper_table_batch(x, 1, q, &k, &c, ids_out, val_out);
 }
 
 // ---------------------------------------------------------------------------

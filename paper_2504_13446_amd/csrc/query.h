@@ -71,17 +71,20 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st);
 // the paper's table query (Sec. 4.3) for a dense batch of nq queries (pairs
 // u * nq + q; keys query-major): brackets and estimates, each query's R_lo_k,
-// R_hi_k and case, the step-2 classification, the answer assembly
+// R_hi_k and case, the step-2 classification, the answer assembly.  Keys
+// carry an integer rank in their top 32 bits, or with fk = 1 the order key
+// of an FP32 bound (the paper's estimated cells).
 hipError_t q_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64, const double *tab_t, const uint32_t *tab_cnt,
                         uint64_t *key_lo, uint64_t *key_hi, double *est, hipStream_t st);
 hipError_t q_tqb_kth(int nq, const int32_t *k, const double *c, const uint64_t *sel_lo, const uint64_t *sel_hi,
-                     const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case, hipStream_t st);
+                     const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case, hipStream_t st,
+                     int fk = 0);
 hipError_t q_tqb_classify(int64_t n, int nq, const double *c, const uint32_t *R_lo, const uint32_t *R_hi,
                           const int32_t *first_case, const uint64_t *key_lo, const uint64_t *key_hi, const double *est,
-                          uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm, hipStream_t st);
+                          uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm, hipStream_t st, int fk = 0);
 hipError_t q_tqb_answer(int nq, int64_t n, int64_t total, const int64_t *off, const int32_t *first_case,
                         const int64_t *sel_off, const uint64_t *sel_hi, const int32_t *nc, const int64_t *off_c,
                         const uint64_t *sel_c, const int64_t *off_t, const uint64_t *sel_t, const double *est,
-                        int32_t *ids, double *est_out, hipStream_t st);
+                        int32_t *ids, double *est_out, hipStream_t st, int fk = 0);
 
 }  // namespace rkr

@@ -502,17 +502,25 @@ __global__ __launch_bounds__(256) void k_tqb_bounds(int64_t n, int nq, int64_t m
     }
 }
 
+// The bound a key's top 32 bits carry: an integer rank (the exact-cell table)
+// or, with fk, the order key of an FP32 bound (the paper's estimated cells).
+__device__ inline double key_bound(uint32_t top, int fk) {
+    if (!fk) return (double)top;
+    const uint32_t b = (top & 0x80000000u) ? (top & 0x7FFFFFFFu) : ~top;
+    return (double)__uint_as_float(b);
+}
+
 // Per query: R_lo_k, R_hi_k from the k smallest keys of each kind, and
 // which case of step 2 applies (1: c R_lo_k >= R_hi_k).
 __global__ void k_tqb_kth(int nq, const int32_t *k, const double *c, const uint64_t *sel_lo, const uint64_t *sel_hi,
-                          const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case) {
+                          const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case, int fk) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     const int64_t i = sel_off[q] + k[q] - 1;
     const uint32_t lo = (uint32_t)(sel_lo[i] >> 32), hi = (uint32_t)(sel_hi[i] >> 32);
     R_lo[q] = lo;
     R_hi[q] = hi;
-    first_case[q] = c[q] * (double)lo >= (double)hi ? 1 : 0;
+    first_case[q] = c[q] * key_bound(lo, fk) >= key_bound(hi, fk) ? 1 : 0;
 }
 
 // Step 2 when c R_lo_k < R_hi_k, per (query, user): the admitted users
@@ -522,7 +530,8 @@ __global__ void k_tqb_kth(int nq, const int32_t *k, const double *c, const uint6
 // the query's admitted users.  Queries in the first case get no keys.
 __global__ void k_tqb_classify(int64_t n, const double *c, const uint32_t *R_lo, const uint32_t *R_hi,
                                const int32_t *first_case, const uint64_t *key_lo, const uint64_t *key_hi,
-                               const double *est, uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm) {
+                               const double *est, uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm,
+                               int fk) {
     const int q = blockIdx.y;
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool admit = false;
@@ -532,7 +541,7 @@ __global__ void k_tqb_classify(int64_t n, const double *c, const uint32_t *R_lo,
         const uint64_t kh = key_hi[j];
         if (!first_case[q]) {
             const uint32_t rhi = (uint32_t)(kh >> 32), rlo = (uint32_t)(key_lo[j] >> 32);
-            admit = (double)rhi <= c[q] * (double)R_lo[q];
+            admit = key_bound(rhi, fk) <= c[q] * key_bound(R_lo[q], fk);
             open = !admit && rlo <= R_hi[q];
         }
         key_c[j] = admit ? kh : ~0ull;
@@ -548,7 +557,7 @@ __global__ void k_tqb_classify(int64_t n, const double *c, const uint32_t *R_lo,
 __global__ void k_tqb_answer(int nq, int64_t n, const int64_t *off, const int32_t *first_case, const int64_t *sel_off,
                              const uint64_t *sel_hi, const int32_t *nc, const int64_t *off_c, const uint64_t *sel_c,
                              const int64_t *off_t, const uint64_t *sel_t, const double *est, int32_t *ids,
-                             double *est_out) {
+                             double *est_out, int fk) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= off[nq]) return;
     const int q = seg_of(off, nq, j);
@@ -557,10 +566,10 @@ __global__ void k_tqb_answer(int nq, int64_t n, const int64_t *off, const int32_
     double e;
     if (first_case[q]) {
         key = sel_hi[sel_off[q] + i];
-        e = (double)(uint32_t)(key >> 32);
+        e = key_bound((uint32_t)(key >> 32), fk);
     } else if (i < nc[q]) {
         key = sel_c[off_c[q] + i];
-        e = (double)(uint32_t)(key >> 32);
+        e = key_bound((uint32_t)(key >> 32), fk);
     } else {
         key = sel_t[off_t[q] + i - nc[q]];
         e = est[(int64_t)q * n + (int64_t)(key & 0xFFFFFFFFu)];
@@ -807,24 +816,25 @@ hipError_t q_tqb_bounds(int64_t n, int nq, int64_t m, const double *t64, const d
     return hipGetLastError();
 }
 hipError_t q_tqb_kth(int nq, const int32_t *k, const double *c, const uint64_t *sel_lo, const uint64_t *sel_hi,
-                     const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case, hipStream_t st) {
-    LAUNCH1D(k_tqb_kth, nq, nq, k, c, sel_lo, sel_hi, sel_off, R_lo, R_hi, first_case);
+                     const int64_t *sel_off, uint32_t *R_lo, uint32_t *R_hi, int32_t *first_case, hipStream_t st,
+                     int fk) {
+    LAUNCH1D(k_tqb_kth, nq, nq, k, c, sel_lo, sel_hi, sel_off, R_lo, R_hi, first_case, fk);
     return hipGetLastError();
 }
 hipError_t q_tqb_classify(int64_t n, int nq, const double *c, const uint32_t *R_lo, const uint32_t *R_hi,
                           const int32_t *first_case, const uint64_t *key_lo, const uint64_t *key_hi, const double *est,
-                          uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm, hipStream_t st) {
+                          uint64_t *key_c, uint64_t *key_t, unsigned long long *nadm, hipStream_t st, int fk) {
     if (n <= 0 || nq <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tqb_classify, dim3((unsigned)((n + 255) / 256), (unsigned)nq), dim3(256), 0, st, n, c, R_lo,
-                       R_hi, first_case, key_lo, key_hi, est, key_c, key_t, nadm);
+                       R_hi, first_case, key_lo, key_hi, est, key_c, key_t, nadm, fk);
     return hipGetLastError();
 }
 hipError_t q_tqb_answer(int nq, int64_t n, int64_t total, const int64_t *off, const int32_t *first_case,
                         const int64_t *sel_off, const uint64_t *sel_hi, const int32_t *nc, const int64_t *off_c,
                         const uint64_t *sel_c, const int64_t *off_t, const uint64_t *sel_t, const double *est,
-                        int32_t *ids, double *est_out, hipStream_t st) {
+                        int32_t *ids, double *est_out, hipStream_t st, int fk) {
     LAUNCH1D(k_tqb_answer, total, nq, n, off, first_case, sel_off, sel_hi, nc, off_c, sel_c, off_t, sel_t, est, ids,
-             est_out);
+             est_out, fk);
     return hipGetLastError();
 }
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st) {

@@ -26,7 +26,8 @@ SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
-           "rkr_query_table", "rkr_query_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
+           "rkr_query_table", "rkr_query_table_batch", "rkr_paper_table_build", "rkr_paper_table",
+           "rkr_query_paper_table", "rkr_query_paper_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_mlp_adam", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
@@ -92,6 +93,10 @@ def load(path: str = LIB_PATH):
         "rkr_query_approx": [vp, vp, i32, f64, vp, vp],
         "rkr_query_table": [vp, vp, i32, f64, vp, vp],
         "rkr_query_table_batch": [vp, i32, vp, vp, vp, vp, vp],
+        "rkr_paper_table_build": [vp, i32, i32, i32, vp],
+        "rkr_paper_table": [vp, vp, vp, vp],
+        "rkr_query_paper_table": [vp, vp, i32, f64, vp, vp],
+        "rkr_query_paper_table_batch": [vp, i32, vp, vp, vp, vp, vp],
         "rkr_query_batch": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rkr_ranks": [vp, vp, vp],
         "rkr_ranks_noalloc": [vp, vp, vp],
@@ -208,6 +213,44 @@ def rkr_query_table_batch(h: int, Q: torch.Tensor, k, c):
     est = torch.empty(int(off[-1]), dtype=torch.float64, device=Q.device)
     _check(load().rkr_query_table_batch(h, nq, _ptr(Q), kk.ctypes.data, cc.ctypes.data, _ptr(ids), _ptr(est)))
     return ids, est, off
+
+
+def rkr_paper_table_build(h: int, tau: int, omega: int, s: int, sample_pos) -> None:
+    """The paper's rank table (Alg. 1) in the index; sample_pos [omega * s]
+    int32 positions within the buckets (host)."""
+    pos = np.ascontiguousarray(np.asarray(sample_pos, np.int32).reshape(-1))
+    assert pos.size == omega * s
+    _check(load().rkr_paper_table_build(h, int(tau), int(omega), int(s), pos.ctypes.data))
+
+
+def rkr_paper_table(h: int, n: int, tau: int, device="cuda"):
+    """(f_min [n] float64, step [n] float64, cells [n, tau] float32) on the device."""
+    fmin = torch.empty(n, dtype=torch.float64, device=device)
+    step = torch.empty(n, dtype=torch.float64, device=device)
+    cells = torch.empty((n, tau), dtype=torch.float32, device=device)
+    _check(load().rkr_paper_table(h, _ptr(fmin), _ptr(step), _ptr(cells)))
+    return fmin, step, cells
+
+
+def rkr_query_paper_table_batch(h: int, Q: torch.Tensor, k, c):
+    """The paper's query on its own table for nq queries: (ids int32, values
+    float64) on the device, concatenated by query, and the host offsets."""
+    nq = int(Q.shape[0])
+    kk = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    cc = np.ascontiguousarray(np.broadcast_to(np.asarray(c, np.float64), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(kk)
+    ids = torch.empty(int(off[-1]), dtype=torch.int32, device=Q.device)
+    val = torch.empty(int(off[-1]), dtype=torch.float64, device=Q.device)
+    _check(load().rkr_query_paper_table_batch(h, nq, _ptr(Q), kk.ctypes.data, cc.ctypes.data, _ptr(ids), _ptr(val)))
+    return ids, val, off
+
+
+def rkr_query_paper_table(h: int, q: torch.Tensor, k: int, c: float):
+    ids = torch.empty(k, dtype=torch.int32, device=q.device)
+    val = torch.empty(k, dtype=torch.float64, device=q.device)
+    _check(load().rkr_query_paper_table(h, _ptr(q), int(k), float(c), _ptr(ids), _ptr(val)))
+    return ids, val
 
 
 def rkr_query_batch(h: int, Q: torch.Tensor, k, c=None, cand_off=None, cand_ids=None):
@@ -337,6 +380,19 @@ class Index:
 
     def query_table_batch(self, Q, k, c):
         return rkr_query_table_batch(self.h, Q, k, c)
+
+    def paper_table_build(self, tau, omega, s, sample_pos):
+        rkr_paper_table_build(self.h, tau, omega, s, sample_pos)
+        self.paper_tau = int(tau)
+
+    def paper_table(self):
+        return rkr_paper_table(self.h, self.n, self.paper_tau)
+
+    def query_paper_table(self, q, k, c):
+        return rkr_query_paper_table(self.h, q, k, c)
+
+    def query_paper_table_batch(self, Q, k, c):
+        return rkr_query_paper_table_batch(self.h, Q, k, c)
 
     def query_batch(self, Q, k, c=None, cand_off=None, cand_ids=None):
         return rkr_query_batch(self.h, Q, k, c, cand_off, cand_ids)
