@@ -104,7 +104,11 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--nq", type=int, default=None)
-    ap.add_argument("--score", default="bf16", choices=["bf16", "fp8", "f32"])
+    ap.add_argument("--score", default=None, choices=["bf16", "fp8", "f32"],
+                    help="score precision (default: fp8 for the uneven workload, else bf16)")
+    ap.add_argument("--mode", default=None, choices=["exact", "approx"],
+                    help="exact (Def. 2) or approximate (Def. 3, the workload's c); default: approximate "
+                         "for the workloads that name a c (uneven, learned), else exact")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-approx", action="store_true", help="skip the c = 1.5 approximate line")
@@ -141,10 +145,21 @@ def main() -> int:
     log("generating workload %s" % args.workload)
     w = W.make(args.workload, n=args.n, m=args.m, nq=args.nq)
     n, m, d, nq = w.n, w.m, w.d, w.nq
+    if args.score is None:
+        args.score = "fp8" if w.name == "uneven" else "bf16"
+    mode = args.mode or ("approx" if w.c is not None else "exact")
+    cvec = np.full(nq, w.c if w.c is not None else 1.5) if mode == "approx" else None
     log("n=%d m=%d d=%d nq=%d dtype=%s" % (n, m, d, nq, w.dtype))
     U = rkr.to_device(w.U, w.dtype)
     P = rkr.to_device(w.P, w.dtype)
     Q = rkr.to_device(w.Qv, w.dtype)
+    # candidate lists of the uneven workload (one CSR list per query)
+    cand = {}
+    if w.cand_off is not None:
+        cand = {"cand_off": w.cand_off, "cand_ids": torch.from_numpy(w.cand_ids).cuda()}
+
+    def run(index, c=cvec):
+        return index.query_batch(Q, w.k, c=c, **cand)
     torch.cuda.synchronize()
     t = time.time()
     idx = rkr.Index(U, P, score=args.score, rank_table=args.rank_table)
@@ -154,13 +169,13 @@ def main() -> int:
     idx.configure(seed_mult=args.seed_mult)
 
     for i in range(args.warmup):
-        idx.query_batch(Q, w.k)
+        run(idx)
         log("warmup %d: %s" % (i, _brief(idx.stats())))
     torch.cuda.synchronize()
     per = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ids, rk, off = idx.query_batch(Q, w.k)
+        ids, rk, off = run(idx)
         per.append(idx.stats())
         log("step %d: %s" % (i, _brief(per[-1])))
     torch.cuda.synchronize()
@@ -204,7 +219,10 @@ def main() -> int:
         "dtype": args.score,
         "data": "synthetic",
         "config": {"workload": w.name, "n_users": n, "m_items": m, "d": d, "queries": nq,
-                   "k": int(w.k[0]), "masters": w.dtype, "score": args.score, "mode": "exact",
+                   "k": int(w.k[0]) if np.all(w.k == w.k[0]) else sorted(set(int(v) for v in w.k)),
+                   "masters": w.dtype, "score": args.score,
+                   "mode": mode if mode == "exact" else "approx c=%g" % cvec[0],
+                   "candidate_pairs": int(w.cand_off[-1]) if w.cand_off is not None else None,
                    "rank_table_samples": args.rank_table,
                    "generator": "iid N(0,I) directions x LogNormal(0,0.5) norms, seeded"},
         # rank comparisons per second: the n * m * Q the definition asks for
@@ -244,7 +262,27 @@ def main() -> int:
                          "frac": round(cmp_rate / ALU_PEAK_TOPS, 5), "compares_per_step": cmp}},
     }
 
-    if not args.no_approx:
+    if mode == "approx":
+        # the same workload answered exactly: its time, and the Sec. 5 quality
+        # of the approximate answers against it (the returned ranks are exact
+        # for every returned user)
+        run(idx, c=None)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ids_e, rk_e, off_e = run(idx, c=None)
+        torch.cuda.synchronize()
+        ms_e = (time.perf_counter() - t) * 1e3
+        se = idx.stats()
+        out["exact_same_workload"] = {"ms_per_step": round(ms_e, 2), "queries_per_s": round(nq / (ms_e / 1e3), 2),
+                                      "near_ties_rechecked": int(se["uncertain"]),
+                                      "recheck_fraction_of_compares": round(se["uncertain"] / max(se["compares"], 1), 6)}
+        out["approx_quality"] = quality(rk_np, off, rk_e.cpu().numpy(), off_e, cvec[0])
+        out["approx_quality"].update({"near_ties_rechecked": int(st["uncertain"]),
+                                      "recheck_fraction_of_compares": round(st["uncertain"] / max(st["compares"], 1), 6),
+                                      "queries_settled_without_refine": int(st["approx_settled"])})
+        log("exact on the same workload: %.1f ms; approximate quality %s" % (ms_e, out["approx_quality"]))
+
+    if not args.no_approx and mode == "exact" and not cand:
         out["approx_c1_5"] = approx_line(idx, Q, w, ids_np, rk_np, off)
 
     if args.rank_table > 0 and not args.no_table_compare:
@@ -252,11 +290,11 @@ def main() -> int:
         # every non-seed pair); warm-up lets the tuner settle on its own key
         idx.configure(no_table=True, seed_mult=args.seed_mult)
         for _ in range(6):
-            idx.query_batch(Q, w.k)
+            run(idx)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(2):
-            ids_nt, rk_nt, _ = idx.query_batch(Q, w.k)
+            ids_nt, rk_nt, _ = run(idx)
         torch.cuda.synchronize()
         ms_nt = (time.perf_counter() - t) * 1e3 / 2
         same = bool(np.array_equal(ids_nt.cpu().numpy(), ids_np) and np.array_equal(rk_nt.cpu().numpy(), rk_np))
@@ -268,7 +306,7 @@ def main() -> int:
         idx.configure(no_table=False, seed_mult=args.seed_mult)
         log("without the rank table: %.1f ms/step (same answers: %s)" % (ms_nt, same))
 
-    if not args.no_table_query:
+    if not args.no_table_query and mode == "exact" and not cand:
         ks = np.atleast_1d(w.k).astype(np.int32)
         if args.rank_table > 0:
             # the query of Sec. 4.3 on the index's exact-cell table
@@ -290,11 +328,11 @@ def main() -> int:
         b32 = (time.time() - t) * 1e3
         idx32.configure(seed_mult=args.seed_mult)
         for _ in range(2):
-            idx32.query_batch(Q, w.k)
+            run(idx32)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(3):
-            ids32, rk32, _ = idx32.query_batch(Q, w.k)
+            ids32, rk32, _ = run(idx32)
         torch.cuda.synchronize()
         ms32 = (time.perf_counter() - t) * 1e3 / 3
         s32 = idx32.stats()
@@ -310,10 +348,10 @@ def main() -> int:
             # the same pair without the rank table (the screen scans every pair)
             idx32.configure(no_table=True, seed_mult=args.seed_mult)
             for _ in range(2):
-                idx32.query_batch(Q, w.k)
+                run(idx32)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            idx32.query_batch(Q, w.k)
+            run(idx32)
             torch.cuda.synchronize()
             ms32nt = (time.perf_counter() - t) * 1e3
             out["fp32_plain"]["without_rank_table_ms_per_step"] = round(ms32nt, 2)
@@ -329,6 +367,21 @@ def main() -> int:
     print(json.dumps(out))
     sys.stdout.flush()
     return 0
+
+
+def quality(rk_c, off_c, rk_x, off_x, c: float) -> dict:
+    """The Sec. 5 criteria of approximate answers (true ranks rk_c) against the
+    exact ones (rk_x), per query in rank order, averaged: accuracy, overall
+    ratio, and Def. 3 violations."""
+    acc, ratio, viol = [], [], 0
+    for i in range(len(off_c) - 1):
+        a = np.sort(rk_c[off_c[i]:off_c[i + 1]].astype(np.float64))
+        b = np.sort(rk_x[off_x[i]:off_x[i + 1]].astype(np.float64))
+        viol += int(np.sum(a > c * b))
+        acc.append(float(np.mean(a <= c * b)))
+        ratio.append(float(np.mean(a / b)))
+    return {"c": float(c), "accuracy": round(float(np.mean(acc)), 5), "overall_ratio": round(float(np.mean(ratio)), 5),
+            "def3_violations": int(viol)}
 
 
 def approx_line(idx, Q, w, ids_ex, rk_ex, off, c: float = 1.5) -> dict:

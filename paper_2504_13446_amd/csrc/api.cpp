@@ -426,6 +426,15 @@ static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus) {
 // tile; FP32 scores have one tile, v0 = 1 x 1).
 static int exact_variant(const rkr_index *x) { return x->sk == SK_F32 ? 0 : 2; }
 
+// Live entries per lane from which the screen counts by histogram (bucketed
+// counting) instead of comparing codes one entry at a time (RKR_SCREEN_HIST
+// overrides it; 0: never).  Both count lower bounds of the certain counts.
+static int screen_hist_min() {
+    const char *v = getenv("RKR_SCREEN_HIST");
+    if (v && *v) return std::max(0, atoi(v));
+    return 12;
+}
+
 static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int variant) {
     CountArgs a{};
     const int nib = nib_of(x->sk, x->nks, variant);
@@ -461,6 +470,7 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int va
     a.emit_cap = (unsigned long long)x->emit_cap;
     a.stat = x->ctr.as<unsigned long long>() + 1;
     a.plain = x->recheck ? 0 : 1;
+    a.hist_min = screen_hist_min();
     return a;
 }
 

@@ -50,6 +50,19 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 // this many live entries (below it, quantising costs more than it saves).
 constexpr int SWAR_MIN_ENTRIES = 4;
 
+// Bucketed counting for screens with many live entries per user: the step's
+// codes of a user (both lanes of its pair) go into a 128-bin LDS histogram,
+// turned into suffix sums, so an entry's count of codes above its
+// threshold's code is one byte read instead of a compare over every code.
+// 128 one-byte bins per user (a byte never overflows: at most 128 codes per
+// pair), at a stride of 33 words so that the 32 users of a wave that update
+// the same bin do so in different LDS banks.
+constexpr int HIST_STRIDE = 132;
+template <int MODE, int NUB>
+constexpr int hist_bytes() {
+    return MODE == CM_SCREEN ? WAVES_PER_WG * NUB * USER_BLOCK * HIST_STRIDE : 0;
+}
+
 template <int SK> struct FragT;
 template <> struct FragT<SK_BF16> { using T = i32x4; };
 template <> struct FragT<SK_F32> { using T = float; };
@@ -241,13 +254,13 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     // counted; a step's first group is requested before its scores are
     // computed, so the matrix-core work hides that latency.
     //
-    // The loop over entries is branch-free per lane: it runs nit (the wave's
-    // longest list, uniform) iterations; every lane loads slot i and stores to
-    // slot (alive ? w : i).  Slots below nit exist for every lane of the
-    // block (a block's lists were laid out for its longest initial list), a
-    // lane past its own list or whose pair just died only rewrites its own
-    // slot i >= w, which later compaction overwrites in program order, and the
-    // two lanes of a pair write identical values.
+    // The loop over entries runs nit (the wave's longest list, uniform)
+    // iterations; every lane loads slot i (slots below nit exist for every
+    // lane of the block: a block's lists were laid out for its longest initial
+    // list).  A live entry is written back only if it moves down to slot w < i
+    // (all fields) or stays and its budget changed (the budget); a dead entry,
+    // or a lane past its own list, writes nothing, since the list ends at w.
+    // The two lanes of a pair write identical values.
     constexpr int ED = 4;
     int g0_pid[NUB][ED], g0_rem[NUB][ED];
     float g0_th[NUB][ED];
@@ -279,7 +292,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     // step: count(hi) returns the lane's number of scores certainly above hi
     // (a lower bound of the exact count); entries whose remaining budget turns
     // negative are dropped, the others are compacted to the front.
-    auto screen_entries = [&](int ub, float eps, auto count) {
+    auto screen_entries = [&](int ub, float eps, auto count, bool paired) {
         int w = 0;
         const int mylen = len[ub];
         const int lim = nit[ub];
@@ -309,14 +322,24 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                     const bool act = i < mylen;
                     const float hb = f32_next_up(th_c[k] + eps);
                     const float hi = a.plain ? th_c[k] : hb;
-                    const uint32_t c = pair_sum(count(hi));
+                    // paired: count gives the pair's total, else the lane's
+                    const uint32_t c = paired ? count(hi) : pair_sum(count(hi));
                     // remaining budget: the pair dies when more than bound - 1 items are certainly above
                     const int rem = rem_c[k] - (int)c;
                     const bool alive = act && rem >= 0;
-                    const uint32_t ow = ebyte[ub] + (uint32_t)(alive ? w : i) * 128u;
-                    st_u32(a.ent_cnt, ow, (uint32_t)rem);
-                    st_u32(a.ent_pid, ow, (uint32_t)pid_c[k]);
-                    st_u32(a.ent_th, ow, __float_as_uint(th_c[k]));
+                    // only what changes is written: an entry that moves down
+                    // to slot w, or the budget of one that stays; slots from w
+                    // on are past the list and never read
+                    if (alive) {
+                        const uint32_t ow = ebyte[ub] + (uint32_t)w * 128u;
+                        if (w != i) {
+                            st_u32(a.ent_cnt, ow, (uint32_t)rem);
+                            st_u32(a.ent_pid, ow, (uint32_t)pid_c[k]);
+                            st_u32(a.ent_th, ow, __float_as_uint(th_c[k]));
+                        } else if (c != 0) {
+                            st_u32(a.ent_cnt, ow, (uint32_t)rem);
+                        }
+                    }
                     w += alive ? 1 : 0;
                 }
             }
@@ -409,8 +432,66 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     constexpr int QW = NIB * 4;
     uint32_t qd_p[NUB][QW];
     float mn_p[NUB], sc_p[NUB], eps_p[NUB];
+    bool hist_p[NUB];
+#pragma unroll
+    for (int ub = 0; ub < NUB; ++ub) hist_p[ub] = false;
     bool have_prev = false;
     const bool late = MODE == CM_SCREEN && wave >= WAVES_PER_WG / 2;
+    // this lane pair's histogram of user block ub (screening only)
+    uint8_t *const hist_lds = lds + NBUF * STAGE + record_bytes<MODE>();
+    auto hist_of = [&](int ub) { return hist_lds + ((wave * NUB + ub) * USER_BLOCK + l32) * HIST_STRIDE; };
+    // The pair's codes into the histogram (bin b = code - 128), then in place
+    // the suffix counts SS[b] = #{codes of the pair with bin > b}.  Only this
+    // wave touches its histograms and its LDS operations run in order, so a
+    // wavefront fence (no workgroup barrier) orders the phases.
+    auto build_hist = [&](int ub, const uint32_t *qd) {
+        uint32_t *hw = (uint32_t *)hist_of(ub);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) hw[half * 16 + k] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int j = 0; j < QW; ++j)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t bin = ((qd[j] >> (8 * b)) & 0xFFu) - 128u;
+                __hip_atomic_fetch_add(hw + (bin >> 2), 1u << (8 * (bin & 3u)), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // each lane of the pair turns its half (16 words, 64 bins) into suffix
+        // counts; the lower half adds the upper half's total
+        uint32_t x[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = hw[half * 16 + k];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tot += (x[k] * 0x01010101u) >> 24;
+        // the swap hands each lane its partner's total in one of the two
+        // results and keeps its own in the other: their sum minus its own is
+        // the partner's
+        auto sw = __builtin_amdgcn_permlane32_swap(tot, tot, false, false);
+        uint32_t carry = half == 0 ? sw[0] + sw[1] - tot : 0u;
+#pragma unroll
+        for (int k = 15; k >= 0; --k) {
+            // byte j of t: the bins above j within the word
+            uint32_t t = x[k] >> 8;
+            t += t >> 8;
+            t += t >> 16;
+            const uint32_t wsum = (x[k] * 0x01010101u) >> 24;
+            x[k] = t + carry * 0x01010101u;
+            carry += wsum;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) hw[half * 16 + k] = x[k];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    // the pair's count of codes above F(hi): the same number code_count and
+    // a sum over the pair give
+    auto hist_count = [&](int ub, float mn, float sc, float hi) -> uint32_t {
+        const float v = __builtin_amdgcn_fmed3f(fmaf(hi - mn, sc, 128.0f), 128.0f, 255.0f);
+        const uint32_t g = __builtin_amdgcn_cvt_pk_u8_f32(v, 0, 0u) & 0xFFu;
+        return (uint32_t)hist_of(ub)[g - 128u];
+    };
     // the code compare against threshold hi (see the compare section)
     auto code_count = [](const uint32_t *qd, float mn, float sc, float hi) -> uint32_t {
         const float v = __builtin_amdgcn_fmed3f(fmaf(hi - mn, sc, 128.0f), 128.0f, 255.0f);
@@ -450,8 +531,14 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         if constexpr (MODE == CM_SCREEN) {
             if (late && have_prev) {
 #pragma unroll
-                for (int ub = 0; ub < NUB; ++ub)
-                    screen_entries(ub, eps_p[ub], [&](float hi) { return code_count(qd_p[ub], mn_p[ub], sc_p[ub], hi); });
+                for (int ub = 0; ub < NUB; ++ub) {
+                    if (hist_p[ub])
+                        screen_entries(ub, eps_p[ub], [&](float hi) { return hist_count(ub, mn_p[ub], sc_p[ub], hi); },
+                                       true);
+                    else
+                        screen_entries(ub, eps_p[ub],
+                                       [&](float hi) { return code_count(qd_p[ub], mn_p[ub], sc_p[ub], hi); }, false);
+                }
             }
         }
 
@@ -527,12 +614,25 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         // code(s) > F(hi) implies s > hi.  Four codes share a dword, so one
         // subtract, mask and bit count compare four scores with an entry.
         //   F(x) = cvt_u8(med3(fma(x - mn, sc, 128), 128, 255)),  sc = 126 / (mx - mn)
+        // with [mn, mx] the range of the lane's scores in the step (of both
+        // lanes of the pair for bucketed counting)
         // For a score x in [mn, mx], (x - mn) * sc <= 126 (1 + 2^-22), so the fma
         // lies in [128, 254.01] (med3 is the identity there): every code byte keeps
         // its top bit.  A flat or tiny range gives sc = 0: all codes 128, nothing
         // counted (still a lower bound).  Past-the-end items (a partial last step)
         // take the code of mn, 128, which is never counted either.
-        auto quantize = [&](int ub, bool full, uint32_t *qd, float &mn_o, float &sc_o) {
+        // With pair, the range is the user's over both lanes of its pair, so
+        // the two lanes code with one map (the pair's histogram merges their
+        // codes); the per-entry code compare keeps each lane's own, finer range.
+        auto pair_min_max = [](float &mn, float &mx) {
+            // each lane gets its partner's value in one of the two results
+            // and keeps its own in the other
+            auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(mn), __float_as_uint(mn), false, false);
+            auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(mx), __float_as_uint(mx), false, false);
+            mn = fminf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+            mx = fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+        };
+        auto quantize = [&](int ub, bool full, uint32_t *qd, float &mn_o, float &sc_o, bool pair) {
             float mn, mx;
             if (full) {
                 mn = acc[0][ub][0];
@@ -544,6 +644,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                         mn = fminf(mn, acc[ib][ub][r]);
                         mx = fmaxf(mx, acc[ib][ub][r]);
                     }
+                if (pair) pair_min_max(mn, mx);
             } else {
                 mn = __builtin_inff();
                 mx = -__builtin_inff();
@@ -557,6 +658,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                             mx = fmaxf(mx, v);
                         }
                     }
+                if (pair) pair_min_max(mn, mx);
                 if (!(mn <= mx)) mn = mx = 0.0f;
 #pragma unroll
                 for (int ib = 0; ib < NIB; ++ib)
@@ -585,14 +687,23 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             const float eps = f32_round_up(E * (1.0 + 1e-9));
             if constexpr (MODE == CM_SCREEN) {
                 const bool full = item0 + NIB * 32 <= a.m;
+                const bool many = a.hist_min > 0 && __ballot(len[ub] >= a.hist_min) != 0ull;
                 if (late) {
-                    quantize(ub, full, qd_p[ub], mn_p[ub], sc_p[ub]);
+                    quantize(ub, full, qd_p[ub], mn_p[ub], sc_p[ub], many);
                     eps_p[ub] = eps;
+                    hist_p[ub] = many;
+                    if (many) build_hist(ub, qd_p[ub]);
+                } else if (full && many) {
+                    uint32_t qd[QW];
+                    float mn, sc;
+                    quantize(ub, true, qd, mn, sc, true);
+                    build_hist(ub, qd);
+                    screen_entries(ub, eps, [&](float hi) { return hist_count(ub, mn, sc, hi); }, true);
                 } else if (full && __ballot(len[ub] >= SWAR_MIN_ENTRIES) != 0ull) {
                     uint32_t qd[QW];
                     float mn, sc;
-                    quantize(ub, true, qd, mn, sc);
-                    screen_entries(ub, eps, [&](float hi) { return code_count(qd, mn, sc, hi); });
+                    quantize(ub, true, qd, mn, sc, false);
+                    screen_entries(ub, eps, [&](float hi) { return code_count(qd, mn, sc, hi); }, false);
                 } else {
                     screen_entries(ub, eps, [&](float hi) -> uint32_t {
                         uint32_t c = 0;
@@ -601,7 +712,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
 #pragma unroll
                             for (int r = 0; r < 16; ++r) c += (acc[ib][ub][r] > hi) ? 1u : 0u;
                         return c;
-                    });
+                    }, false);
                 }
                 continue;
             }
@@ -764,7 +875,12 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
 #pragma unroll
             for (int ub = 0; ub < NUB; ++ub) {
                 fetch_first(ub);
-                screen_entries(ub, eps_p[ub], [&](float hi) { return code_count(qd_p[ub], mn_p[ub], sc_p[ub], hi); });
+                if (hist_p[ub])
+                    screen_entries(ub, eps_p[ub], [&](float hi) { return hist_count(ub, mn_p[ub], sc_p[ub], hi); },
+                                   true);
+                else
+                    screen_entries(ub, eps_p[ub], [&](float hi) { return code_count(qd_p[ub], mn_p[ub], sc_p[ub], hi); },
+                                   false);
             }
         }
     }
@@ -851,7 +967,7 @@ static hipError_t launch_one(const CountArgs &a, int nsplit, hipStream_t st) {
     constexpr int TASKS_PER_WG = WAVES_PER_WG * NUB * USER_BLOCK;
     constexpr int STEP_BYTES_MAX = NIB * NKS * 64 * frag_fb(SK);
     constexpr int STAGE = STEP_BYTES_MAX + 32;
-    const size_t lds = (size_t)stage_buffers<MODE>(STAGE) * STAGE + record_bytes<MODE>();
+    const size_t lds = (size_t)stage_buffers<MODE>(STAGE) * STAGE + record_bytes<MODE>() + hist_bytes<MODE, NUB>();
     if (a.nks != NKS) return hipErrorInvalidValue;   // layouts are padded to a supported k-step count
     const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
     if (ntiles == 0) return hipSuccess;

@@ -104,6 +104,8 @@ struct CountArgs {
     unsigned long long *stat;     // [0]: executed compares, [2]: compare lane slots, [4]: matrix-core flop,
                                   // [6]: (user, item) scores of users with a live pair
     int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
+    int hist_min;                 // screening: bucketed counting once some lane of a wave holds
+                                  // this many live entries (0: never)
     // persistent launch: workgroups take tiles from *tile_counter (zeroed before
     // the launch) until it passes ntiles; null = one workgroup per tile
     unsigned long long *tile_counter;

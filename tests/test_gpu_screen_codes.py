@@ -142,3 +142,26 @@ def _ranks_cached(w):
     if key not in _RANKS:
         _RANKS[key] = O.ranks(w.U, w.P, w.Qv)
     return _RANKS[key]
+
+
+@pytest.mark.parametrize("score", ["bf16", "fp8", "f32"])
+def test_bucketed_counting_answers_equal_the_oracle(score, monkeypatch):
+    """Bucketed counting (a histogram of a step's codes per user over both
+    lanes of its pair, then one lookup per pair) must keep the counts lower
+    bounds of the certain counts: with 64 queries and no rank table every lane
+    starts with 64 live pairs, so the screen takes the histogram path; the
+    answers, with it forced on and switched off, equal the oracle's."""
+    from paper_2504_13446_amd import workloads as W
+    w = W.make("small", n=6_000, m=5_000, d=40, nq=64, k=10)
+    R = O.ranks(w.U, w.P, w.Qv)
+    for hist in ("12", "0"):
+        monkeypatch.setenv("RKR_SCREEN_HIST", hist)
+        monkeypatch.setenv("RKR_AUTOTUNE_CACHE", "off")
+        idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score=score)
+        ids, rk, off = idx.query_batch(_dev(w.Qv, "f32"), w.k)
+        idx.close()
+        ids, rk = ids.cpu().numpy(), rk.cpu().numpy()
+        for i in range(w.nq):
+            wi, wr = O.topk(R[i], int(w.k[i]))
+            assert np.array_equal(ids[off[i]:off[i + 1]], wi), (hist, i)
+            assert np.array_equal(rk[off[i]:off[i + 1]], wr), (hist, i)
