@@ -115,6 +115,12 @@ def main() -> int:
     ap.add_argument("--no-single", action="store_true", help="skip the single-query all-ranks line")
     ap.add_argument("--rank-table", type=int, default=4096,
                     help="sample items for the index's rank table (0: no table)")
+    ap.add_argument("--train-queries", type=int, default=1114,
+                    help="learned workload: training queries (disjoint from the test queries)")
+    ap.add_argument("--train-pairs", type=int, default=9766,
+                    help="learned workload: (user, query) pairs per training query (half best by u.q/|u|, "
+                         "half spread; 1,114 x 9,766 gives 10.0M triples)")
+    ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--seed-mult", type=int, default=0,
                     help="seeds per query, in units of k (0: the library's default)")
     ap.add_argument("--no-table-query", action="store_true", help="skip the paper's table query line")
@@ -162,11 +168,28 @@ def main() -> int:
         return index.query_batch(Q, w.k, c=c, **cand)
     torch.cuda.synchronize()
     t = time.time()
-    idx = rkr.Index(U, P, score=args.score, rank_table=args.rank_table)
+    learned = w.name == "learned"
+    idx = rkr.Index(U, P, score=args.score, rank_table=args.rank_table, sketch_samples=4096 if learned else 0)
     torch.cuda.synchronize()
     build_ms = (time.time() - t) * 1e3
     log("index built in %.0f ms" % build_ms)
     idx.configure(seed_mult=args.seed_mult)
+    train_info = None
+    if learned:
+        # the rank estimator, trained on exact ranks of training queries that
+        # are not test queries; the test batch then orders its seeds by it
+        Qtr = rkr.to_device(W.extra_queries(w, args.train_queries), w.dtype)
+        torch.cuda.synchronize()
+        t = time.time()
+        idx.train(Qtr, pairs_per_query=args.train_pairs, epochs=args.train_epochs, batch=4096, lr=1e-3, seed=5)
+        torch.cuda.synchronize()
+        s_tr = idx.stats()
+        train_info = {"training_queries": int(Qtr.shape[0]), "triples": int(s_tr["pairs"]),
+                      "epochs": args.train_epochs, "final_mse_ln_rank": round(float(s_tr["mlp_loss"]), 5),
+                      "ms": round((time.time() - t) * 1e3, 1)}
+        log("estimator trained: %s" % train_info)
+        del Qtr
+        idx.configure(seed_mult=args.seed_mult, use_estimator=True)
 
     for i in range(args.warmup):
         run(idx)
@@ -261,6 +284,9 @@ def main() -> int:
             "alu_view": {"achieved": round(cmp_rate, 4), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                          "frac": round(cmp_rate / ALU_PEAK_TOPS, 5), "compares_per_step": cmp}},
     }
+
+    if train_info is not None:
+        out["estimator"] = learned_line(idx, run, w, train_info, cvec, rk_np, off, ms_step)
 
     if mode == "approx":
         # the same workload answered exactly: its time, and the Sec. 5 quality
@@ -367,6 +393,54 @@ def main() -> int:
     print(json.dumps(out))
     sys.stdout.flush()
     return 0
+
+
+def learned_line(idx, run, w, train_info, cvec, rk_main, off_main, ms_main) -> dict:
+    """The learned workload: what the trained estimator buys.  Exact answers
+    with seeds ordered by the estimator and by the rank-table heuristic
+    (u.q/|u|) must be identical; the work each needed is compared (seed pairs
+    counted, pairs left after the screen, executed compares, scored pairs,
+    time).  The approximate batch (c) of the main line against the same
+    batch without the estimator.  And pruning: the answer taken from the 2k
+    users per query of best predicted rank (estimator) or best u.q/|u|,
+    counted exactly, with no verifying screen (Def. 3 not guaranteed): the
+    Sec. 5 criteria, Def. 3 violations and recall of the exact top-k."""
+    import torch
+
+    def timed(c, use_est, prune=0, reps=2):
+        idx.configure(use_estimator=use_est, prune_mult=prune)
+        run(idx, c=c)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            ids, rk, off = run(idx, c=c)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        st = idx.stats()
+        work = {k: int(st[k]) for k in ("seed_pairs", "survivors", "refined_pairs", "compares", "scored_pairs",
+                                        "uncertain")}
+        return ids.cpu().numpy(), rk.cpu().numpy(), off, round(ms, 2), work
+
+    res = {"training": train_info}
+    ie, re_, oe, ms_e, work_e = timed(None, True)
+    ih, rh, oh, ms_h, work_h = timed(None, False)
+    res["exact"] = {"identical_answers": bool(np.array_equal(ie, ih) and np.array_equal(re_, rh)),
+                    "with_estimator": {"ms_per_step": ms_e, **work_e},
+                    "rank_table_heuristic": {"ms_per_step": ms_h, **work_h}}
+    _, ra, oa, ms_a, work_a = timed(cvec, False)
+    res["approx_without_estimator"] = {"ms_per_step": ms_a, **work_a,
+                                       "quality": quality(ra, oa, re_, oe, cvec[0])}
+    res["approx_with_estimator"] = {"ms_per_step": round(ms_main, 2),
+                                    "quality": quality(rk_main, off_main, re_, oe, cvec[0])}
+    for name, use in (("pruned_estimator", True), ("pruned_heuristic", False)):
+        ip, rp, op, ms_p, work_p = timed(cvec, use, prune=2)
+        rec = [len(set(ip[op[i]:op[i + 1]].tolist()) & set(ie[oe[i]:oe[i + 1]].tolist())) / float(oe[i + 1] - oe[i])
+               for i in range(w.nq)]
+        res[name] = {"candidates_per_query": "2k", "ms_per_step": ms_p, **work_p,
+                     "quality": quality(rp, op, re_, oe, cvec[0]), "recall_of_exact_top_k": round(float(np.mean(rec)), 4)}
+    idx.configure(use_estimator=True, prune_mult=0)
+    log("estimator line: %s" % json.dumps(res))
+    return res
 
 
 def quality(rk_c, off_c, rk_x, off_x, c: float) -> dict:

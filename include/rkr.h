@@ -87,7 +87,7 @@ typedef struct {
     int32_t seed_mult;      /* seeds per query = seed_mult * k (default: 1 with a rank   */
                             /* table in use, else 2)                                     */
     int32_t use_estimator;  /* 1: order seeds by the trained estimator (needs rkr_train) */
-    int32_t approx_refine;  /* approximate mode: max refine rounds (default 4)           */
+    int32_t reserved0;      /* must be 0                                                 */
     int32_t prune_mult;     /* approximate mode only: answer from the prune_mult * k     */
                             /* users per query of best predicted rank (estimator) or     */
                             /* best u.q/|u| (no estimator), without the verifying screen */

@@ -239,7 +239,6 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
     x->mk = dt == RKR_BF16 ? MK_BF16 : MK_F32;
     x->st = st;
     x->qo.seed_mult = 0;   // chosen per call (see run_batch)
-    x->qo.approx_refine = 4;
     x->tuner.load();
     {
         int dev = 0, cus = 0;
@@ -353,10 +352,10 @@ extern "C" void rkr_destroy(rkr_index *x) {
 extern "C" rkr_status rkr_configure(rkr_index *x, const rkr_query_opts *o) {
     g_err.clear();
     if (!x || !o) return fail(RKR_E_INVALID, "NULL argument");
-    if (o->seed_mult < 0 || o->approx_refine < 0 || o->prune_mult < 0) return fail(RKR_E_INVALID, "negative option");
+    if (o->seed_mult < 0 || o->prune_mult < 0) return fail(RKR_E_INVALID, "negative option");
+    if (o->reserved0 != 0) return fail(RKR_E_INVALID, "reserved0 must be 0");
     if (o->use_estimator && !x->est.trained) return fail(RKR_E_STATE, "estimator not trained");
     rkr_query_opts q = *o;
-    if (q.approx_refine == 0) q.approx_refine = 4;
     x->qo = q;
     return RKR_OK;
 }

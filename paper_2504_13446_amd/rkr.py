@@ -46,7 +46,7 @@ class BuildOpts(ctypes.Structure):
 
 class QueryOpts(ctypes.Structure):
     _fields_ = [("seed_mult", ctypes.c_int32), ("use_estimator", ctypes.c_int32),
-                ("approx_refine", ctypes.c_int32), ("prune_mult", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("prune_mult", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("no_table", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
@@ -172,9 +172,9 @@ def rkr_destroy(h: int) -> None:
         load().rkr_destroy(h)
 
 
-def rkr_configure(h: int, seed_mult: int = 0, use_estimator: bool = False, approx_refine: int = 0,
+def rkr_configure(h: int, seed_mult: int = 0, use_estimator: bool = False,
                   prune_mult: int = 0, graph: bool = False, no_table: bool = False) -> None:
-    o = QueryOpts(int(seed_mult), 1 if use_estimator else 0, int(approx_refine), int(prune_mult),
+    o = QueryOpts(int(seed_mult), 1 if use_estimator else 0, 0, int(prune_mult),
                   1 if graph else 0, 1 if no_table else 0)
     _check(load().rkr_configure(h, ctypes.byref(o)))
 

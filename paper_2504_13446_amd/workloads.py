@@ -171,3 +171,13 @@ def bucket_sample_positions(m: int, omega: int, s: int, seed: int = 13446) -> np
         else:
             out[l * s:(l + 1) * s] = rng.choice(size, size=s, replace=False).astype(np.int32)
     return out
+
+
+def extra_queries(w: Workload, nq: int, seed: int = 1) -> np.ndarray:
+    """nq more query vectors: rows of P drawn uniformly without replacement
+    from the rows that are not w's queries (e.g. training queries for the
+    rank estimator, disjoint from the test queries).  Master dtype [nq][d]."""
+    rng = np.random.default_rng(np.random.SeedSequence([13446, seed, w.m, nq]))
+    rest = np.setdiff1d(np.arange(w.m, dtype=np.int64), w.qidx)
+    pick = rng.choice(rest, size=min(nq, rest.size), replace=False)
+    return np.ascontiguousarray(w.P[pick])

@@ -138,12 +138,15 @@ def test_bf16_masters_batch():
     idx.close()
 
 
+@pytest.mark.parametrize("d", [45, 72])
 @pytest.mark.parametrize("masters", ["bf16", "f32"])
-def test_batch_of_many_queries(masters):
+def test_batch_of_many_queries(masters, d):
     """A dense batch of 80 queries (a full 64-query threshold tile and a
-    ragged one) over a dimension that is not a multiple of 32: exact answers
-    equal the oracle's, with and without the rank table."""
-    w = W.make("batch", n=3000, m=4000, d=45, nq=80)
+    ragged one), n and nq even so the threshold tiles take their 16-byte
+    stores: d = 45 (not a multiple of 32, per-element operand staging) and
+    d = 72 (BF16 operands staged 16 bytes at a time, then a ragged chunk);
+    exact answers equal the oracle's, with and without the rank table."""
+    w = W.make("batch", n=3000, m=4000, d=d, nq=80)
     ks = np.array([(7 * i) % 40 + 1 for i in range(80)], np.int32)
     R = O.ranks(w.U, w.P, w.Qv)
     # the generator's BF16 bits, widened exactly for FP32 masters
