@@ -285,6 +285,17 @@ rkr_status rkr_query_batch(rkr_index *idx, int32_t nq, const void *Qm, const int
  */
 rkr_status rkr_rank_table(const rkr_index *idx, double *t_out, uint32_t *cnt_out);
 
+/*
+ * Check of the error bound the exact ranks rest on, over every (user, item)
+ * pair of the index: for each, the matrix-core score s_hat of the index's
+ * score kind and the FP64 spec dot s(u,p) of the master values, and the
+ * bound eps the count kernels use for that user and item block.  Writes the
+ * largest |s_hat - s(u,p)| / eps (rounded up to FP32) to *max_ratio_out and
+ * the number of pairs with a ratio above 1 (a broken bound; the exactness
+ * of every rank needs 0) to *over_out [host].  Costs d FP64 fma per pair.
+ */
+rkr_status rkr_score_error(rkr_index *idx, double *max_ratio_out, int64_t *over_out);
+
 /* Exact Def. 1 rank of q for every user: ranks_out [device, n int32]. */
 rkr_status rkr_ranks(rkr_index *idx, const void *q, int32_t *ranks_out);
 

@@ -590,6 +590,48 @@ static rkr_status build_rank_table(rkr_index *x, int samples) {
 }
 
 // ---------------------------------------------------------------------------
+// check of the error bound (every user x every item)
+// ---------------------------------------------------------------------------
+extern "C" rkr_status rkr_score_error(rkr_index *x, double *max_ratio_out, int64_t *over_out) {
+    g_err.clear();
+    if (!x || !max_ratio_out || !over_out) return fail(RKR_E_INVALID, "NULL argument");
+    hipStream_t st = x->st;
+    x->sc.reset();
+    uint32_t *out = (uint32_t *)x->sc.take(8);
+    if (!out) return fail(RKR_E_NOMEM, "scratch");
+    HIPCK(launch_fill_u32(out, 0, 2, st));
+    if (x->m > 0) {
+        PairSet ps;
+        TaskSet ts;
+        const int xv = x->sk == SK_F32 ? 0 : 2;
+        CountArgs a = count_args(x, ps, ts, xv);
+        a.ntask = x->n;
+        a.cnt_out = out;
+        a.stat = nullptr;
+        a.emit = nullptr;
+        a.emit_count = nullptr;
+        a.emit_cap = 0;
+        a.um_master = x->Um.p;
+        a.pm_master = x->Pm.p;
+        a.d_master = x->d;
+        a.mk_master = x->mk;
+        const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+        int64_t nsplit = pick_nsplit((x->n + tpw - 1) / tpw, a.nsteps, x->num_cus);
+        a.steps_per_split = (a.nsteps + nsplit - 1) / nsplit;
+        nsplit = (a.nsteps + a.steps_per_split - 1) / a.steps_per_split;
+        HIPCK(launch_count(x->sk, CM_BOUND, a, (int)nsplit, xv, st));
+    }
+    uint32_t h[2] = {0, 0};
+    HIPCK(hipMemcpyAsync(h, out, 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    float r;
+    memcpy(&r, &h[0], 4);
+    *max_ratio_out = (double)r;
+    *over_out = (int64_t)h[1];
+    return RKR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // batch queries
 // ---------------------------------------------------------------------------
 static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int32_t *k, const double *c,

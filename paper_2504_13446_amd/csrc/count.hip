@@ -208,9 +208,9 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         int64_t t = tile * TASKS_PER_WG + (wave * NUB + ub) * USER_BLOCK + l32;
         tix[ub] = t;
         int u;
-        if constexpr (MODE == CM_TABLE) {
+        if constexpr (MODE == CM_TABLE || MODE == CM_BOUND) {
             u = (t < a.ntask) ? (int)t : -1;
-            len[ub] = (u >= 0) ? TABLE_COLS : 0;
+            len[ub] = (u >= 0) ? (MODE == CM_TABLE ? TABLE_COLS : 1) : 0;
             ebase[ub] = 0;
         } else {
             u = (t < a.ntask) ? a.task_user[t] : -1;
@@ -401,6 +401,8 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 if (uid[ub] >= 0) tth[ub][j] = a.ent_th[(int64_t)uid[ub] * TABLE_COLS + j];
         }
 
+    double bound_max = 0.0;     // bound check only
+    uint32_t bound_over = 0;
     int any_live = 0;
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) any_live |= (len[ub] > 0);
@@ -716,6 +718,29 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                 }
                 continue;
             }
+            if constexpr (MODE == CM_BOUND) {
+                // the lane's largest |score - s64| / eps over its real items,
+                // and the number of scores beyond eps (there should be none)
+                if (uid[ub] >= 0) {
+                    const int64_t urow = (int64_t)uid[ub] * a.d_master;
+#pragma unroll
+                    for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int64_t item = item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            if (item < a.m) {
+                                double s64 = 0.0;
+                                for (int k = 0; k < a.d_master; ++k)
+                                    s64 = fma(master_elem(a.um_master, a.mk_master, urow + k),
+                                              master_elem(a.pm_master, a.mk_master, item * a.d_master + k), s64);
+                                const double ratio = fabs((double)acc[ib][ub][r] - s64) / (double)eps;
+                                bound_max = fmax(bound_max, ratio);
+                                bound_over += ratio > 1.0 ? 1u : 0u;
+                            }
+                        }
+                }
+                continue;
+            }
             if constexpr (MODE == CM_TABLE) {
                 // s > hi as an integer median: with order keys (ks, kh) of the
                 // scores and of hi (zeros made +0, so the key order is the
@@ -895,6 +920,11 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
         }
     }
     // ---- write back
+    if constexpr (MODE == CM_BOUND) {
+        if (bound_max > 0.0) atomicMax(&a.cnt_out[0], __float_as_uint(f32_round_up(bound_max)));
+        if (bound_over) atomicAdd(&a.cnt_out[1], bound_over);
+        return;
+    }
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) {
         if (uid[ub] < 0) continue;
@@ -1039,6 +1069,7 @@ static hipError_t dispatch_mode(int mode, const CountArgs &a, int nsplit, int va
     if (mode == CM_SCREEN) return dispatch_nks<SK, CM_SCREEN>(a, nsplit, variant, st);
     if (mode == CM_EXACT) return dispatch_nks<SK, CM_EXACT>(a, nsplit, variant, st);
     if (mode == CM_TABLE) return dispatch_nks<SK, CM_TABLE>(a, nsplit, variant, st);
+    if (mode == CM_BOUND) return dispatch_nks<SK, CM_BOUND>(a, nsplit, variant, st);
     return hipErrorInvalidValue;
 }
 

@@ -106,6 +106,9 @@ struct CountArgs {
     int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
     int hist_min;                 // screening: bucketed counting once some lane of a wave holds
                                   // this many live entries (0: never)
+    const void *um_master;        // bound check only: master user rows [n][d]
+    const void *pm_master;        // bound check only: master item rows in norm order [m][d]
+    int d_master, mk_master;
     // persistent launch: workgroups take tiles from *tile_counter (zeroed before
     // the launch) until it passes ntiles; null = one workgroup per tile
     unsigned long long *tile_counter;
@@ -117,7 +120,13 @@ struct CountArgs {
 // lists); user u's TABLE_COLS thresholds, rounded up to FP32, are read from
 // ent_th[u * TABLE_COLS + j], and cnt_out[u * TABLE_COLS + j] += the count of
 // items certainly above column j (a lower bound of the exact count).
-enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_TABLE = 2 };
+// CM_BOUND: a check of the error bound.  Task t is user t (ntask = n); for
+// every score of a real item the FP64 spec dot is recomputed from the master
+// values (um_master, pm_master: user rows, items in norm order) and the
+// largest |score - s64| / eps (eps: the bound the other modes use for that
+// user and step) goes to cnt_out[0] (FP32 bits, rounded up), the number of
+// scores with ratio above 1 to cnt_out[1].
+enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_TABLE = 2, CM_BOUND = 3 };
 constexpr int TABLE_COLS = 48;
 
 struct DeviceIndex;

@@ -27,7 +27,7 @@ MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
            "rkr_query_table", "rkr_query_table_batch", "rkr_paper_table_build", "rkr_paper_table",
-           "rkr_query_paper_table", "rkr_query_paper_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
+           "rkr_query_paper_table", "rkr_query_paper_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_score_error", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_mlp_adam", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "rkr_query_batch": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rkr_ranks": [vp, vp, vp],
         "rkr_ranks_noalloc": [vp, vp, vp],
+        "rkr_score_error": [vp, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
         "rkr_train": [vp, i32, vp, i32, i32, i32, f32, ctypes.c_uint64],
         "rkr_predict": [vp, i32, vp, vp],
         "rkr_mlp_get": [vp, vp],
@@ -280,6 +281,14 @@ def rkr_ranks(h: int, q: torch.Tensor, n: int) -> torch.Tensor:
     return out
 
 
+def rkr_score_error(h: int):
+    """(largest |score - s64| / eps over every (user, item) pair, pairs above 1)."""
+    r = ctypes.c_double()
+    over = ctypes.c_int64()
+    _check(load().rkr_score_error(h, ctypes.byref(r), ctypes.byref(over)))
+    return r.value, over.value
+
+
 def rkr_ranks_noalloc(h: int, q: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
     """rkr_ranks into a caller-provided int32 tensor, with no device allocation."""
     assert out.dtype == torch.int32 and out.is_contiguous()
@@ -396,6 +405,9 @@ class Index:
 
     def query_batch(self, Q, k, c=None, cand_off=None, cand_ids=None):
         return rkr_query_batch(self.h, Q, k, c, cand_off, cand_ids)
+
+    def score_error(self):
+        return rkr_score_error(self.h)
 
     def ranks(self, q):
         return rkr_ranks(self.h, q, self.n)
