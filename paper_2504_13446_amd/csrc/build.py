@@ -15,8 +15,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "librkr.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["count.hip", "prep.hip", "select.hip", "query.hip", "mlp.hip", "paper_table.hip", "api.cpp"]
-HEADERS = ["rkr_internal.h", "kernels.h", "query.h", "mlp.h", "paper_table.h"]
+SOURCES = ["count.hip", "exact.hip", "prep.hip", "select.hip", "query.hip", "mlp.hip", "paper_table.hip", "api.cpp"]
+HEADERS = ["rkr_internal.h", "tile_common.h", "kernels.h", "query.h", "mlp.h", "paper_table.h"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + HERE, "-Wno-unused-result"]

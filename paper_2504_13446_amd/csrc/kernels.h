@@ -129,9 +129,11 @@ hipError_t scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *total, 
 hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st);
 hipError_t launch_select(const uint64_t *keys, const int64_t *seg_off, const int32_t *kk, int64_t nseg,
                          const int64_t *out_off, uint64_t *out, hipStream_t st);
+// Tasks of the pairs pids[0..N) (ascending, so each user's pairs are a run):
+// one task per user, or, with max_len > 0, one per max_len pairs of a user.
 hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, const int32_t *bound,
                        TaskSet &ts, Scratch &sc, hipStream_t st,
-                       const uint32_t *rem_init = nullptr);
+                       const uint32_t *rem_init = nullptr, int max_len = 0);
 hipError_t launch_iota(int32_t *out, int64_t n, hipStream_t st);
 hipError_t launch_dense_pairs(int64_t n, int nq, int32_t *pair_u, int32_t *pair_q, hipStream_t st);
 hipError_t build_csr_pairs(const int32_t *cand_ids, const int64_t *cand_off_dev, int nq, int64_t total, int64_t n,

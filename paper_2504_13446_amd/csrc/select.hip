@@ -414,8 +414,19 @@ __global__ __launch_bounds__(256) void k_fill_entries(const int32_t *pids, const
     }
 }
 
+// Task starts of a run of one user's pairs cut every max_len pairs: pair i
+// (of run excl[i] + flag[i] - 1, which starts at run_start[...]) starts a task
+// when its position in the run is a multiple of max_len.
+__global__ void k_split_runs(int64_t N, const int32_t *flag, const int64_t *excl, const int64_t *run_start,
+                             int max_len, int32_t *flag_out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int64_t pos = i - run_start[excl[i] + flag[i] - 1];
+    flag_out[i] = (pos % max_len) == 0 ? 1 : 0;
+}
+
 hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, const int32_t *bound,
-                       TaskSet &ts, Scratch &sc, hipStream_t st, const uint32_t *rem_init) {
+                       TaskSet &ts, Scratch &sc, hipStream_t st, const uint32_t *rem_init, int max_len) {
     ts.ntask = 0;
     ts.ntask_pad = 0;
     ts.cap_total = 0;
@@ -430,6 +441,23 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     int64_t ntask = 0;
     if ((e = hipMemcpyAsync(&ntask, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (max_len > 0 && ntask < N) {
+        // runs of one user become tasks of at most max_len pairs
+        int64_t *run_start = (int64_t *)sc.take((ntask + 1) * 8);
+        int32_t *run_user = (int32_t *)sc.take(ntask * 4);
+        int32_t *flag2 = (int32_t *)sc.take(N * 4);
+        int64_t *excl2 = (int64_t *)sc.take(N * 8);
+        if (!run_start || !run_user || !flag2 || !excl2) return hipErrorOutOfMemory;
+        hipLaunchKernelGGL(k_task_starts, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, ps.pair_u, flag, excl,
+                           run_start, run_user);
+        hipLaunchKernelGGL(k_split_runs, dim3(nblocks(N, 256)), dim3(256), 0, st, N, flag, excl, run_start, max_len,
+                           flag2);
+        if ((e = scan_i32(flag2, N, excl2, dtot, sc, st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(&ntask, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        flag = flag2;
+        excl = excl2;
+    }
     const int64_t ntask_pad = (ntask + 511) / 512 * 512;
     const int64_t nblk = ntask_pad / 32;
     if ((e = ts.reserve(ntask_pad, nblk)) != hipSuccess) return e;
