@@ -489,8 +489,9 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
     hipStream_t st = x->st;
     HIPCK(ensure_events(x));
     TaskSet &ts = x->ts_exact;
-    // at most two pairs per task: the exact kernel keeps two in registers
-    hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, nullptr, ts, x->sc, st, nullptr, 2);
+    // one pair per task: the exact kernel folds the pair's threshold into its
+    // accumulators (a user with several pairs gets a task for each)
+    hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, nullptr, ts, x->sc, st, nullptr, 1);
     if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
     const int xv = exact_variant(x);
     const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;

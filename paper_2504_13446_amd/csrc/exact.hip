@@ -3,33 +3,38 @@
 // items certainly above the pair's FP64 threshold, every near tie emitted for
 // the FP64 recheck.
 //
-// Operands, entry lists, band edges, records and outputs are those of the
-// count kernel's exact mode (count.hip).  What differs is the schedule, made
-// for what these passes look like -- one or two pairs per user, so a few
-// compares per score against a 13-MFMA score tile -- where a wave that
-// computes a step's scores and then compares them leaves the matrix cores
-// idle through every compare and waits on its own last MFMA before it:
+// Same operands, entry lists, records and outputs as the count kernel's
+// exact mode (count.hip), with a schedule and a compare made for these
+// passes: one pair per task (the task builder gives a user with several
+// pairs a task for each; the all-ranks passes have one pair per user).
 //
-//  * The loop over item steps is software-pipelined.  While a wave compares
-//    the scores of step st (accumulators `cur`) it computes those of step
-//    st + 1 (accumulators `nxt`); the two are one basic block, and scheduling
-//    groups interleave them: one LDS fragment read and one MFMA, then a few
-//    compare instructions, and so on.  The compare of step st never waits for
-//    an MFMA of step st + 1.
-//  * Per step a lane counts its 32 scores above the first pair's upper edge
-//    and at or above its lower edge; the counts stay per lane (the pair sum is
-//    taken once, at the end); a near tie shows as a difference of the two and
-//    takes the rare path that writes records, after the block.
-//  * Items stream through NBUF LDS stages (direct global -> LDS copies);
+//  * Threshold in the accumulator.  The first MFMA of a step starts from
+//    C = -tf instead of 0 (tf = th, the FP32 value >= the FP64 threshold t64;
+//    in plain mode tf = fl32(t64)), so the step ends with acc = score - tf.
+//    The error bound of the count kernels covers this with one more term in
+//    the FP32 accumulation: |acc - (u^.p^ - th)| <= gamma(dpad + 1) (|u^||p^| +
+//    |th|) <= E_old (1 + 1/dpad) + gamma(dpad + 1) |th|, where E_old is the
+//    usual per-step bound (its FP32 term is gamma(dpad) |u^||p^|, the other
+//    terms are positive) and gamma(n) = 2 n 2^-23.  With E that sum:
+//      acc > E             => s64 > th >= t64          (certainly above)
+//      acc < -(E + th - tl) => s64 < tl <= t64          (certainly not above)
+//    and anything in between is a near tie.  A score then costs one compare
+//    (against ehi = E rounded up) and half a v_min3: a near tie is possible
+//    only where min |acc| <= elo = E + th - tl, which sends the wave to the
+//    rare path that writes records (exact masks there).
+//  * The loop over item steps is software-pipelined.  While a wave counts
+//    step st (accumulators `cur`) it computes step st + 1 (`nxt`); the two
+//    are one basic block, in fixed chunks (one LDS fragment read, one MFMA,
+//    a share of the compares; a scheduling fence after each), so the compare
+//    of step st never waits for an MFMA of step st + 1 and the matrix cores
+//    are fed between compares.  Counts stay per lane; the pair sum is taken
+//    once, at the end.
+//  * Items stream through NBUF LDS stages (buffer loads that write LDS);
 //    the workgroup meets at one barrier per SP steps.  Step st + D is staged
 //    at step st; at a barrier before step st0, the stages of steps up to
 //    st0 + SP have landed (each wave waits until at most the copies of later
 //    steps are in flight), and a stage is overwritten only after a barrier
 //    has followed every read of it.  SP = 2, D = 4 with five stages.
-//  * The users' fragments, the pairs of each lane and their counts live in
-//    registers for the whole scan: a task holds at most two pairs (the task
-//    builder gives a user with more pairs several tasks; the all-ranks passes
-//    have one pair per user), so no list is read inside the loop.
 #include "rkr_internal.h"
 #include "tile_common.h"
 
@@ -168,11 +173,10 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
     const int64_t s_begin = a.step0 + (int64_t)split * a.steps_per_split;
     const int64_t s_end = std::min<int64_t>(s_begin + a.steps_per_split, a.step_end);
 
-    // ---- the lane's user: register-stationary fragments, norms, first pairs
+    // ---- the lane's user: register-stationary fragments, norms, its pair
     const int64_t t = tile * (WAVES_PER_WG * USER_BLOCK) + wave * USER_BLOCK + l32;
     const int u = t < a.ntask ? a.task_user[t] : -1;
-    const int len = u >= 0 ? a.ent_len[split * a.len_stride + t] : 0;
-    const int64_t ebase = u >= 0 ? a.blk_base[t >> 5] + l32 : 0;
+    const bool live = u >= 0 && a.ent_len[split * a.len_stride + t] > 0;
     double un_hat = 0.0, un_del = 0.0, un_full = 0.0;
     if (u >= 0) {
         un_hat = a.unorm3[3 * (int64_t)u + 0];
@@ -189,32 +193,37 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
             bfrag[s] = v;
         }
     }
-    int pid0 = 0, pid1 = 0;
-    float th0 = 0.0f, tl0 = 0.0f, tm0 = 0.0f, th1 = 0.0f, tl1 = 0.0f, tm1 = 0.0f;
-    if (len > 0) {
-        pid0 = a.ent_pid[ebase];
-        th0 = a.ent_th[ebase];
-        tl0 = a.ent_tl[ebase];
-        tm0 = a.ent_tm[ebase];
+    // The pair: pid, the FP32 values th >= t64 >= tl bracketing its FP64
+    // threshold and tm = fl32(t64).  The accumulators start from -tf (tf = th,
+    // or tm in plain mode), so they end at score - tf (see the top of the file).
+    int pid = 0;
+    float th = 0.0f, tl = 0.0f, tm = 0.0f;
+    if (live) {
+        const int64_t e = a.blk_base[t >> 5] + l32;
+        pid = a.ent_pid[e];
+        th = a.ent_th[e];
+        tl = a.ent_tl[e];
+        tm = a.ent_tm[e];
     }
-    if (len > 1) {
-        pid1 = a.ent_pid[ebase + 32];
-        th1 = a.ent_th[ebase + 32];
-        tl1 = a.ent_tl[ebase + 32];
-        tm1 = a.ent_tm[ebase + 32];
-    }
-    uint32_t cnt0 = 0, cnt1 = 0;   // per-lane certain counts of the two register pairs
-    int wlen = len;   // at most 2 (see the top of the file)
+    const float tf = a.plain ? tm : th;
+    f32x16 negt;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) wlen = max(wlen, __shfl_xor(wlen, o, 64));
-    wlen = __builtin_amdgcn_readfirstlane(wlen);
-    if (!__syncthreads_or(len > 0) || s_begin >= s_end) return;
+    for (int r = 0; r < 16; ++r) negt[r] = -tf;
+    // the threshold's share of the error bound, gamma(dpad + 1) |tf|, and the
+    // bracket width th - tl (exact: both are FP32 values one ulp apart at most)
+    const double gam1 = 2.0 * (double)(a.dpad + 1) * 0x1p-23;
+    const double th_term = gam1 * fabs((double)tf);
+    const double bracket = (double)th - (double)tl;
+    const double inflate = 1.0 + 1.0 / (double)a.dpad;
+    // plain verdict of a near tie: score > tm, i.e. acc > tm - th (exact)
+    const float pd = tm - th;
+    uint32_t cnt = 0;   // per-lane certain count of the pair
+    if (!__syncthreads_or(live) || s_begin >= s_end) return;
 
     // ---- near-tie records: a per-wave LDS buffer, flushed with one global
     // atomic when full and at the end.  It is an array of its own, apart from
     // the item stages, so that the compiler can tell that writing a record
-    // does not touch a stage an LDS copy is still filling (it would otherwise
-    // wait for every copy in flight before each record write).
+    // does not touch a stage an LDS copy is still filling.
     int2 *const recbuf = recs + wave * REC_PER_WAVE;
     int rb_n = 0;
     auto flush_records = [&]() {
@@ -227,24 +236,30 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
         rb_n = 0;
     };
 
-    // band edges of a pair for a step's bound eps
-    auto edges = [&](float th, float tl, float eps, float &hi, float &lo) {
-        hi = a.plain ? th : f32_next_up(th + eps);
-        lo = a.plain ? f32_next_up(hi) : f32_next_down(tl - eps);
+    // The band of a step in accumulator units (acc = score - tf): certainly
+    // above when acc > ehi, certainly not above when acc < -elo, a near tie in
+    // between.  From the step's coefficients (staged with its tile).
+    auto band_of = [&](double ca, double cb, double cc, double cabs, float &ehi, float &elo) {
+        if (a.plain) {
+            ehi = 0.0f;                  // acc > 0: the plain FP32 verdict, no near ties
+            elo = -__builtin_inff();
+            return;
+        }
+        const double E = (un_hat * ca + un_del * cb + un_full * cc + cabs) * inflate + th_term;
+        ehi = f32_round_up(E * (1.0 + 1e-9));
+        elo = f32_round_up((E + bracket) * (1.0 + 1e-9));
     };
-    // the step's bound for this lane's user from the coefficients staged with its tile
-    auto step_eps = [&](const uint8_t *tile) -> float {
+    auto band_of_tile = [&](const uint8_t *tile, float &ehi, float &elo) {
         const double *cs = (const double *)(tile + STEP_BYTES);
-        const double E = un_hat * cs[0] + un_del * cs[1] + un_full * cs[2] + cs[3];
-        return f32_round_up(E * (1.0 + 1e-9));
+        band_of(cs[0], cs[1], cs[2], cs[3], ehi, elo);
     };
     // item of score r of block ib in this lane, for a step starting at item0
     auto item_of = [&](int64_t item0, int ib, int r) -> int64_t {
         return item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
     };
-    // near ties of one pair in one step (scores in [lo, hi]) to the record
-    // buffer, each with the plain FP32 verdict (score > fl32(t)) in its top bit
-    auto emit_ties = [&](const f32x16 *acc, bool act, int pid, float hi, float lo, float tm, int64_t item0) {
+    // near ties of the pair in one step to the record buffer, each with the
+    // plain FP32 verdict in its top bit
+    auto emit_ties = [&](const f32x16 *acc, float ehi, float elo, int64_t item0) {
         // bit ib * 16 + r of each mask is score r of block ib (shifted in
         // from the top, so that no per-bit constants are needed)
         uint32_t umask = 0, pmask = 0;
@@ -252,11 +267,11 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
         for (int ib = NIB - 1; ib >= 0; --ib)
 #pragma unroll
             for (int r = 15; r >= 0; --r) {
-                const float sv = acc[ib][r];
-                umask = (umask << 1) | ((sv >= lo && !(sv > hi)) ? 1u : 0u);
-                pmask = (pmask << 1) | ((sv > tm) ? 1u : 0u);
+                const float v = acc[ib][r];
+                umask = (umask << 1) | ((v >= -elo && !(v > ehi)) ? 1u : 0u);
+                pmask = (pmask << 1) | ((v > pd) ? 1u : 0u);
             }
-        if (!act) umask = 0;
+        if (!live) umask = 0;
         const uint32_t nu = __popc(umask);
         // record offsets: with at most one record per lane (the usual case)
         // the lane's rank among the lanes that have one, else a prefix sum
@@ -295,29 +310,6 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
             });
         }
     };
-    // count of one pair over one step (per lane), and whether it has near ties
-    auto count_pair = [&](const f32x16 *acc, float hi, float lo, uint32_t &c, uint32_t &cl) {
-        c = 0;
-        cl = 0;
-#pragma unroll
-        for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float sv = acc[ib][r];
-                c += (sv > hi) ? 1u : 0u;
-                cl += (sv >= lo) ? 1u : 0u;
-            }
-    };
-    // the second pair of the lane (rare: waves whose tasks hold two)
-    auto second_pair = [&](const f32x16 *acc, float eps, int64_t item0) {
-        float hi, lo;
-        edges(th1, tl1, eps, hi, lo);
-        uint32_t c, cl;
-        count_pair(acc, hi, lo, c, cl);
-        const bool act = len > 1;
-        cnt1 += c;
-        if (__ballot(act && cl != c) != 0ull) emit_ties(acc, act, pid1, hi, lo, tm1, item0);
-    };
     // scores of items past the end never count
     auto mask_tail = [&](f32x16 *acc, int64_t item0) {
         if (item0 + NIB * 32 <= a.m) return;
@@ -328,52 +320,53 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
             for (int r = 0; r < 16; ++r)
                 if (ib * 32 + 8 * (r >> 2) + (r & 3) >= lim) acc[ib][r] = -__builtin_inff();
     };
-    // the scores of a step (MFMA block only)
+    // the accumulators of a step (MFMA block only): score - tf
     auto scores = [&](const uint8_t *tile, f32x16 *acc) {
-#pragma unroll
-        for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[ib][r] = 0.0f;
 #pragma unroll
         for (int s = 0; s < NKS; ++s)
 #pragma unroll
             for (int ib = 0; ib < NIB; ++ib) {
                 const FT af = *(const FT *)(tile + ((ib * NKS + s) * 64 + lane) * FB);
-                acc[ib] = mfma_step<SK_BF16>(acc[ib], af, bfrag[s], 127, 127);
+                acc[ib] = mfma_step<SK_BF16>(s == 0 ? negt : acc[ib], af, bfrag[s], 127, 127);
             }
     };
-
-    // The scores of the next step (nxt, from the stage at tn) and the count
-    // of the first pair over the current step (cur) in one block, in a fixed
-    // order: chunk i reads fragment i + PIPE, issues MFMA i and compares the
-    // next share of the current scores; a scheduling fence closes each chunk,
-    // so every MFMA has PIPE fragment reads in flight ahead of it and compare
-    // instructions between it and the next one.
-    auto score_and_count = [&](const uint8_t *tn, f32x16 *nxt, const f32x16 *cur, float hi, float lo,
-                               uint32_t &c, uint32_t &cl) {
+    // The accumulators of the next step (nxt, from the stage at tn) and the
+    // count of the current step (cur) in one block, in a fixed order: chunk i
+    // reads fragment i + PIPE, issues MFMA i and handles the next share of the
+    // current scores (one compare and half a min3 each); a scheduling fence
+    // closes each chunk, so every MFMA has PIPE fragment reads in flight ahead
+    // of it and compare instructions between it and the next one.  side(i)
+    // adds other work of the step to chunk i.  dmin is the smallest |acc| of
+    // the lane: a near tie is possible only if dmin <= elo.
+    auto score_and_count = [&](const uint8_t *tn, f32x16 *nxt, const f32x16 *cur, float ehi, uint32_t &c,
+                               float &dmin, auto &&side) {
         constexpr int NRD = NKS * NIB;
         constexpr int PIPE = NRD < EX_PIPE ? NRD : EX_PIPE;
         auto frag = [&](int i) { return *(const FT *)(tn + (((i % NIB) * NKS + i / NIB) * 64 + lane) * FB); };
-#pragma unroll
-        for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) nxt[ib][r] = 0.0f;
         FT fr[PIPE];
 #pragma unroll
         for (int i = 0; i < PIPE; ++i) fr[i] = frag(i);
         c = 0;
-        cl = 0;
+        dmin = __builtin_inff();
 #pragma unroll
         for (int i = 0; i < NRD; ++i) {
             const FT f = fr[i % PIPE];
             if (i + PIPE < NRD) fr[i % PIPE] = frag(i + PIPE);
-            nxt[i % NIB] = mfma_step<SK_BF16>(nxt[i % NIB], f, bfrag[i / NIB], 127, 127);
-#pragma unroll
-            for (int k = i * NSC / NRD; k < (i + 1) * NSC / NRD; ++k) {
-                const float sv = cur[k / 16][k % 16];
-                c += (sv > hi) ? 1u : 0u;
-                cl += (sv >= lo) ? 1u : 0u;
+            nxt[i % NIB] = mfma_step<SK_BF16>(i < NIB ? negt : nxt[i % NIB], f, bfrag[i / NIB], 127, 127);
+            // scores in pairs (one min3 each), 32 over the NRD chunks
+            const int k0 = (i * NSC / NRD) & ~1, k1 = ((i + 1) * NSC / NRD) & ~1;
+            for (int k = k0; k < k1; k += 2) {
+                const float v0 = cur[k / 16][k % 16], v1 = cur[(k + 1) / 16][(k + 1) % 16];
+                c += (v0 > ehi) ? 1u : 0u;
+                c += (v1 > ehi) ? 1u : 0u;
+                // min(dmin, |v0|, |v1|) in one instruction (fminf would
+                // quieten its operands first; the scores are never NaN)
+                asm("v_min3_f32 %0, %1, |%2|, |%3|" : "=v"(dmin) : "v"(dmin), "v"(v0), "v"(v1));
             }
+            // keep this chunk's share here: the compiler would otherwise
+            // sink it out of the block to where the count is used
+            asm volatile("" : "+v"(c), "+v"(dmin));
+            side(i);
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -400,13 +393,14 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
 
     f32x16 accA[NIB], accB[NIB];
     scores(lds, accA);
-    float eps_cur = step_eps(lds);
+    float ehi, elo;   // the band of the current step
+    band_of_tile(lds, ehi, elo);
     mask_tail(accA, s_begin * (NIB * 32));
     barrier_before(s_begin);
 
     int slot_nxt = 1 % NBUF;      // stage of step st + 1
     int slot_stg = D % NBUF;      // stage of step st + D
-    // One step: stage st + D, compare st (cur) while scoring st + 1 (nxt).
+    // One step: stage st + D, count st (cur) while scoring st + 1 (nxt).
     // The last step of a tile scores a stale stage too (its result is never
     // used): the block then has no branch, and the compare stays in it.
     auto body = [&](f32x16 *cur, f32x16 *nxt, int64_t st) {
@@ -414,17 +408,29 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
             stage(a.plp + (st + D) * (int64_t)STEP_BYTES, lds_base + slot_stg * STAGE, wave_u, lane,
                   a.step_coef + 4 * (st + D));
         const int64_t item0 = st * (NIB * 32);
-        float hi0, lo0;
-        edges(th0, tl0, eps_cur, hi0, lo0);
         const uint8_t *tn = lds + slot_nxt * STAGE;
-        uint32_t c0, cl0;
-        score_and_count(tn, nxt, cur, hi0, lo0, c0, cl0);
-        const float eps_nxt = step_eps(tn);
-        cnt0 += c0;
-        if (__ballot(len > 0 && cl0 != c0) != 0ull) emit_ties(cur, len > 0, pid0, hi0, lo0, tm0, item0);
-        if (wlen > 1) second_pair(cur, eps_cur, item0);
+        uint32_t c;
+        float dmin;
+        // inside the block: the next step's band (coefficients read first,
+        // used half way)
+        constexpr int NRD = NKS * NIB;
+        const double *csp = (const double *)(tn + STEP_BYTES);
+        double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;
+        float ehi_n = 0.0f, elo_n = 0.0f;
+        score_and_count(tn, nxt, cur, ehi, c, dmin, [&](int i) {
+            if (i == 0) {
+                cs0 = csp[0];
+                cs1 = csp[1];
+                cs2 = csp[2];
+                cs3 = csp[3];
+            }
+            if (i == NRD / 2) band_of(cs0, cs1, cs2, cs3, ehi_n, elo_n);
+        });
+        cnt += c;
+        if (__ballot(live && dmin <= elo) != 0ull) emit_ties(cur, ehi, elo, item0);
         mask_tail(nxt, item0 + NIB * 32);
-        eps_cur = eps_nxt;
+        ehi = ehi_n;
+        elo = elo_n;
         slot_nxt = slot_nxt + 1 == NBUF ? 0 : slot_nxt + 1;
         slot_stg = slot_stg + 1 == NBUF ? 0 : slot_stg + 1;
         ++nstep;
@@ -442,19 +448,16 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
 
     // ---- statistics and write-back (exact lists never change in a pass)
     const uint64_t nsc = (uint64_t)(s_end - s_begin);
-    ncmp += nsc * (uint64_t)len * NSC;
-    nslot += nsc * (uint64_t)wlen * NSC;
+    const uint32_t lanes = (uint32_t)__popcll(__ballot(live));
+    ncmp += nsc * (live ? 1u : 0u) * NSC;
+    nslot += nsc * (lanes ? 1u : 0u) * NSC;
     {
-        const uint32_t lanes = (uint32_t)__popcll(__ballot(len > 0));
         const int64_t first = s_begin * (NIB * 32);
         const int64_t last = std::min<int64_t>(s_end * (NIB * 32), a.m);
         if (last > first) nscored += (uint64_t)(lanes / 2) * (uint64_t)(last - first);
     }
-    const uint32_t tot0 = pair_sum(cnt0), tot1 = pair_sum(cnt1);
-    if (u >= 0 && half == 0) {
-        if (len > 0) atomicAdd(&a.cnt_out[pid0], tot0);
-        if (len > 1) atomicAdd(&a.cnt_out[pid1], tot1);
-    }
+    const uint32_t tot = pair_sum(cnt);
+    if (live && half == 0) atomicAdd(&a.cnt_out[pid], tot);
 }
 
 template <int NKS>
@@ -501,8 +504,8 @@ hipError_t launch_exact_nks(const CountArgs &a, int nsplit, hipStream_t st) {
 }  // namespace
 
 // Exact pass with BF16 scores (item steps of 64, one workgroup of 8 waves per
-// 256 tasks and item split); the layouts are padded to nks k-steps, and no
-// task holds more than two pairs.
+// 256 tasks and item split); the layouts are padded to nks k-steps, and every
+// task holds one pair.
 hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st) {
     const int nks = a.nks;
     if (nks <= 4) return launch_exact_nks<4>(a, nsplit, st);

@@ -134,7 +134,7 @@ struct DeviceIndex;
 // launchers (count.hip)
 hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int variant, hipStream_t st);
 // the software-pipelined exact pass for BF16 scores (exact.hip); its tasks
-// hold at most two pairs each
+// hold one pair each
 hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st);
 
 }  // namespace rkr
