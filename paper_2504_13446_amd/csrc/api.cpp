@@ -425,6 +425,12 @@ static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus) {
 // tile; FP32 scores have one tile, v0 = 1 x 1).
 static int exact_variant(const rkr_index *x) { return x->sk == SK_F32 ? 0 : 2; }
 
+// An environment switch that is on when set to "1" (read once).
+static bool env_flag(const char *name) {
+    const char *v = getenv(name);
+    return v && v[0] == '1' && v[1] == 0;
+}
+
 // Live entries per lane from which the screen counts by histogram (bucketed
 // counting) instead of comparing codes one entry at a time (RKR_SCREEN_HIST
 // overrides it; 0: never).  Both count lower bounds of the certain counts.
@@ -520,6 +526,15 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
         HIPCK(hipStreamSynchronize(st));
         x->stats.ms_exact_kernel += event_ms(x->ev[0], x->ev[1]);
         if (ne <= (unsigned long long)x->emit_cap) {
+            if (ts.ntask > ts.nusers) {
+                // users with several tasks were scored once per task: count
+                // their (user, item) scores once in the algorithmic-work counter
+                unsigned long long scored = 0;
+                HIPCK(hipMemcpyAsync(&scored, x->ctr.as<unsigned long long>() + 7, 8, hipMemcpyDeviceToHost, st));
+                HIPCK(hipStreamSynchronize(st));
+                scored -= (unsigned long long)(ts.ntask - ts.nusers) * (unsigned long long)x->m;
+                HIPCK(hipMemcpyAsync(x->ctr.as<unsigned long long>() + 7, &scored, 8, hipMemcpyHostToDevice, st));
+            }
             x->stats.uncertain += (int64_t)ne;
             HIPCK(hipEventRecord(x->ev[2], st));
             HIPCK(launch_recheck(x->emit.as<int2>(), (int64_t)ne, ps.pair_u, ps.t64, x->Um.p, x->Pm.p, x->d, x->mk,
@@ -826,8 +841,14 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         nscreen = nk;
     }
     if (need_screen && nscreen > 0) {
+        // After the rank table about one pair per user is left: BF16 screens
+        // then run the pipelined single-pair kernel (one pair per task; a
+        // user with several gets a task for each).  Dense screens (many pairs
+        // per user) run the count kernel's screening mode.
+        const bool single = table_used && x->sk == SK_BF16 && !env_flag("RKR_SCREEN_GENERIC");
+        const int max_len = single ? 1 : 0;
         hipError_t e = build_tasks(x->allpid.as<int32_t>(), nscreen, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(),
-                                   x->ts_screen, x->sc, st);
+                                   x->ts_screen, x->sc, st, nullptr, max_len);
         if (e != hipSuccess) return fail_hip(e, "build_tasks (screen)");
         // the screening kernel addresses entries with 32-bit byte offsets
         if (x->ts_screen.cap_total >= ((int64_t)1 << 30))
@@ -836,9 +857,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         // a table-pruned screen sees far fewer pairs: tuned on its own
         const std::string key = tune_key(x, nq, npairs) + (table_used ? "/table" : "");
         const int ntv = num_variants(x->sk, x->nks);
-        const int cand = x->tuner.pick(key, 2 * ntv);
-        const int variant = cand % ntv;
-        const bool persistent = cand >= ntv;
+        const int cand = single ? 0 : x->tuner.pick(key, 2 * ntv);
+        const int variant = single ? exact_variant(x) : cand % ntv;
+        const bool persistent = !single && cand >= ntv;
         // The scan runs in phases.  Without the rank table every user stays
         // live through the first quarter or so of P, then users die fast;
         // after the table most pairs die within the first tenth.  After a
@@ -900,7 +921,10 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
                 a.persistent_ctas = x->num_cus;
             }
             HIPCK(hipEventRecord(x->ev[0], st));
-            HIPCK(launch_count(x->sk, CM_SCREEN, a, (int)nsplit, variant, st));
+            if (single)
+                HIPCK(launch_screen1_bf16(a, (int)nsplit, st));
+            else
+                HIPCK(launch_count(x->sk, CM_SCREEN, a, (int)nsplit, variant, st));
             HIPCK(hipEventRecord(x->ev[1], st));
             if (nsplit > 1)
                 HIPCK(q_screen_merge(*cur, (int)nsplit, x->sp_len.as<int32_t>(), x->sp_pid.as<int32_t>(),
@@ -921,13 +945,13 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
             HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &npl, x->sc, st,
                               x->cnt.as<uint32_t>()));
             e = build_tasks(x->surv.as<int32_t>(), npl, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(), *nxt, x->sc,
-                            st, x->cnt.as<uint32_t>());
+                            st, x->cnt.as<uint32_t>(), max_len);
             if (e != hipSuccess) return fail_hip(e, "build_tasks (screen compaction)");
             std::swap(cur, nxt);
         }
         x->stats.ms_screen_kernel = ms_kernel;
-        x->tuner.record(key, cand, ms_kernel, 2 * ntv);
-        x->stats.screen_variant = cand;
+        if (!single) x->tuner.record(key, cand, ms_kernel, 2 * ntv);
+        x->stats.screen_variant = single ? -1 : cand;
         TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
     }

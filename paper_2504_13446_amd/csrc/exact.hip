@@ -152,9 +152,9 @@ __device__ inline void wait_vm_n(int n) {
     }
 }
 
-template <int NKS>
-__device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, int2 *recs, uint64_t &ncmp,
-                                  uint64_t &nslot, uint64_t &nstep, uint64_t &nscored) {
+template <int NKS, bool SCREEN>
+__device__ inline void pass_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, int2 *recs, int *wg_live,
+                                 uint64_t &ncmp, uint64_t &nslot, uint64_t &nstep, uint64_t &nscored) {
     using G = ExactGeom<NKS>;
     using FT = typename FragT<SK_BF16>::T;
     constexpr int NIB = EX_NIB;
@@ -176,7 +176,7 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
     // ---- the lane's user: register-stationary fragments, norms, its pair
     const int64_t t = tile * (WAVES_PER_WG * USER_BLOCK) + wave * USER_BLOCK + l32;
     const int u = t < a.ntask ? a.task_user[t] : -1;
-    const bool live = u >= 0 && a.ent_len[split * a.len_stride + t] > 0;
+    bool live = u >= 0 && a.ent_len[split * a.len_stride + t] > 0;
     double un_hat = 0.0, un_del = 0.0, un_full = 0.0;
     if (u >= 0) {
         un_hat = a.unorm3[3 * (int64_t)u + 0];
@@ -196,16 +196,23 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
     // The pair: pid, the FP32 values th >= t64 >= tl bracketing its FP64
     // threshold and tm = fl32(t64).  The accumulators start from -tf (tf = th,
     // or tm in plain mode), so they end at score - tf (see the top of the file).
-    int pid = 0;
+    // A screening pair carries its remaining budget rem instead (it dies when
+    // rem turns negative), and its lists are the split's own copy.
+    int pid = 0, rem = 0;
     float th = 0.0f, tl = 0.0f, tm = 0.0f;
+    const int64_t e_pair = a.blk_base[t >> 5] + l32 + (SCREEN ? (int64_t)split * a.cap_total : 0);
     if (live) {
-        const int64_t e = a.blk_base[t >> 5] + l32;
-        pid = a.ent_pid[e];
-        th = a.ent_th[e];
-        tl = a.ent_tl[e];
-        tm = a.ent_tm[e];
+        pid = a.ent_pid[e_pair];
+        th = a.ent_th[e_pair];
+        if constexpr (SCREEN) {
+            rem = (int)a.ent_cnt[e_pair];
+        } else {
+            tl = a.ent_tl[e_pair];
+            tm = a.ent_tm[e_pair];
+        }
     }
-    const float tf = a.plain ? tm : th;
+    // (screening entries of plain mode already hold fl32(t) in th)
+    const float tf = (!SCREEN && a.plain) ? tm : th;
     f32x16 negt;
 #pragma unroll
     for (int r = 0; r < 16; ++r) negt[r] = -tf;
@@ -360,8 +367,10 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
                 c += (v0 > ehi) ? 1u : 0u;
                 c += (v1 > ehi) ? 1u : 0u;
                 // min(dmin, |v0|, |v1|) in one instruction (fminf would
-                // quieten its operands first; the scores are never NaN)
-                asm("v_min3_f32 %0, %1, |%2|, |%3|" : "=v"(dmin) : "v"(dmin), "v"(v0), "v"(v1));
+                // quieten its operands first; the scores are never NaN);
+                // screening has no near ties to look for
+                if constexpr (!SCREEN)
+                    asm("v_min3_f32 %0, %1, |%2|, |%3|" : "=v"(dmin) : "v"(dmin), "v"(v0), "v"(v1));
             }
             // keep this chunk's share here: the compiler would otherwise
             // sink it out of the block to where the count is used
@@ -382,11 +391,26 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
               a.step_coef + 4 * (s_begin + k));
     // before the barrier at step st0: steps up to st0 + SP have landed; the
     // copies of later steps (staged up to step st0 - 1 + D) may be in flight
-    auto barrier_before = [&](int64_t st0) {
+    // Screening: the workgroup stops at a barrier once none of its pairs is
+    // live.  "Any live" flags, one slot per barrier, three in rotation: the
+    // slot of barrier b - 1 is cleared after barrier b (every read of it came
+    // before) and written again only after barrier b + 1.
+    int lslot = 0;
+    auto barrier_before = [&](int64_t st0) -> bool {
         const int64_t last = std::min<int64_t>(st0 - 1 + D, s_end - 1);
         const int64_t later = std::max<int64_t>(0, last - (st0 + SP));
         wait_vm_n((int)later * nload);
+        if constexpr (SCREEN) {
+            if (lane == 0 && __ballot(live) != 0ull) atomicOr(&wg_live[lslot], 1);
+        }
         __syncthreads();
+        if constexpr (SCREEN) {
+            const int any = wg_live[lslot];
+            if (tid == 0) wg_live[lslot == 0 ? 2 : lslot - 1] = 0;
+            lslot = lslot == 2 ? 0 : lslot + 1;
+            return any != 0;
+        }
+        return true;
     };
     wait_vm_n((int)(npro - 1) * nload);
     __syncthreads();
@@ -396,7 +420,7 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
     float ehi, elo;   // the band of the current step
     band_of_tile(lds, ehi, elo);
     mask_tail(accA, s_begin * (NIB * 32));
-    barrier_before(s_begin);
+    bool go = barrier_before(s_begin);
 
     int slot_nxt = 1 % NBUF;      // stage of step st + 1
     int slot_stg = D % NBUF;      // stage of step st + D
@@ -426,8 +450,17 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
             }
             if (i == NRD / 2) band_of(cs0, cs1, cs2, cs3, ehi_n, elo_n);
         });
-        cnt += c;
-        if (__ballot(live && dmin <= elo) != 0ull) emit_ties(cur, ehi, elo, item0);
+        if constexpr (SCREEN) {
+            // the budget left after this step's certainly-above items
+            nscored += (uint64_t)(__popcll(__ballot(live)) / 2) *
+                       (uint64_t)std::min<int64_t>(NIB * 32, a.m - item0);
+            ncmp += live ? (uint64_t)NSC : 0;
+            rem -= (int)pair_sum(c);   // both halves of the step's items (lanes l and l + 32)
+            live = live && rem >= 0;
+        } else {
+            cnt += c;
+            if (__ballot(live && dmin <= elo) != 0ull) emit_ties(cur, ehi, elo, item0);
+        }
         mask_tail(nxt, item0 + NIB * 32);
         ehi = ehi_n;
         elo = elo_n;
@@ -436,13 +469,24 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
         ++nstep;
     };
 
-    for (int64_t st = s_begin;;) {
+    for (int64_t st = s_begin; go;) {
         body(accA, accB, st);
         if (++st >= s_end) break;
-        if (SP == 1) barrier_before(st);
+        if (SP == 1 && !barrier_before(st)) break;
         body(accB, accA, st);
         if (++st >= s_end) break;
-        barrier_before(st);
+        if (!barrier_before(st)) break;
+    }
+    if constexpr (SCREEN) {
+        // a workgroup that stops early may still have copies in flight into
+        // its LDS: they land before it ends
+        wait_vm<0>();
+        if (u >= 0 && half == 0) {
+            a.ent_len[split * a.len_stride + t] = live ? 1 : 0;
+            if (live) a.ent_cnt[e_pair] = (uint32_t)rem;
+        }
+        nslot += ncmp;
+        return;
     }
     flush_records();
 
@@ -460,13 +504,15 @@ __device__ inline void exact_tile(const CountArgs &a, const int64_t tile, uint8_
     if (live && half == 0) atomicAdd(&a.cnt_out[pid], tot);
 }
 
-template <int NKS>
-__global__ __launch_bounds__(512) void k_exact(CountArgs a) {
+template <int NKS, bool SCREEN>
+__global__ __launch_bounds__(512) void k_pass(CountArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    __shared__ int2 recs[WAVES_PER_WG * REC_PER_WAVE];
+    __shared__ int2 recs[SCREEN ? 1 : WAVES_PER_WG * REC_PER_WAVE];
+    __shared__ int wg_live[3];
     const int lane = threadIdx.x & 63;
+    if (SCREEN && threadIdx.x < 3) wg_live[threadIdx.x] = 0;   // read after the tile's first barrier
     uint64_t ncmp = 0, nslot = 0, nstep = 0, nscored = 0;
-    exact_tile<NKS>(a, (int64_t)blockIdx.x, lds, recs, ncmp, nslot, nstep, nscored);
+    pass_tile<NKS, SCREEN>(a, (int64_t)blockIdx.x, lds, recs, wg_live, ncmp, nslot, nstep, nscored);
     uint64_t tot = ncmp, tslot = nslot;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -484,8 +530,8 @@ __global__ __launch_bounds__(512) void k_exact(CountArgs a) {
     if (threadIdx.x == 0 && a.stat && nstep) atomicAdd(a.stat + 4, (unsigned long long)(nstep + 1) * FLOP_PER_STEP);
 }
 
-template <int NKS>
-hipError_t launch_exact_nks(const CountArgs &a, int nsplit, hipStream_t st) {
+template <int NKS, bool SCREEN>
+hipError_t launch_pass_nks(const CountArgs &a, int nsplit, hipStream_t st) {
     using G = ExactGeom<NKS>;
     if (a.nks != NKS) return hipErrorInvalidValue;
     constexpr int TASKS_PER_WG = WAVES_PER_WG * USER_BLOCK;
@@ -494,11 +540,21 @@ hipError_t launch_exact_nks(const CountArgs &a, int nsplit, hipStream_t st) {
     CountArgs b = a;
     b.ntiles = ntiles;
     b.tile_counter = nullptr;
-    auto kern = k_exact<NKS>;
+    auto kern = k_pass<NKS, SCREEN>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, G::LDS_BYTES);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)ntiles, (unsigned)nsplit), dim3(512), G::LDS_BYTES, st, b);
     return hipGetLastError();
+}
+
+template <bool SCREEN>
+hipError_t launch_pass(const CountArgs &a, int nsplit, hipStream_t st) {
+    const int nks = a.nks;
+    if (nks <= 4) return launch_pass_nks<4, SCREEN>(a, nsplit, st);
+    if (nks <= 8) return launch_pass_nks<8, SCREEN>(a, nsplit, st);
+    if (nks <= 13) return launch_pass_nks<13, SCREEN>(a, nsplit, st);
+    if (nks <= 20) return launch_pass_nks<20, SCREEN>(a, nsplit, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -506,13 +562,12 @@ hipError_t launch_exact_nks(const CountArgs &a, int nsplit, hipStream_t st) {
 // Exact pass with BF16 scores (item steps of 64, one workgroup of 8 waves per
 // 256 tasks and item split); the layouts are padded to nks k-steps, and every
 // task holds one pair.
-hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st) {
-    const int nks = a.nks;
-    if (nks <= 4) return launch_exact_nks<4>(a, nsplit, st);
-    if (nks <= 8) return launch_exact_nks<8>(a, nsplit, st);
-    if (nks <= 13) return launch_exact_nks<13>(a, nsplit, st);
-    if (nks <= 20) return launch_exact_nks<20>(a, nsplit, st);
-    return hipErrorInvalidValue;
-}
+hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st) { return launch_pass<false>(a, nsplit, st); }
+
+// Screening pass with BF16 scores, one pair per task: a pair's remaining
+// budget loses its certainly-above items; it dies (list length 0) when the
+// budget turns negative, and a workgroup stops once all its pairs are dead.
+// Items and splits as for the screening mode of the count kernel.
+hipError_t launch_screen1_bf16(const CountArgs &a, int nsplit, hipStream_t st) { return launch_pass<true>(a, nsplit, st); }
 
 }  // namespace rkr

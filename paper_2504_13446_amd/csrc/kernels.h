@@ -60,6 +60,7 @@ struct PairSet {
 // Entry lists of a set of tasks (one task = one user and its live pairs).
 struct TaskSet {
     int64_t ntask = 0, ntask_pad = 0, cap_total = 0;
+    int64_t nusers = 0;   // distinct users of the tasks (a user may hold several tasks)
     DBuf b_user, b_len, b_base, b_pid, b_q, b_cnt, b_th, b_tl, b_tm;
     int32_t *task_user = nullptr, *len = nullptr;
     int64_t *blk_base = nullptr;

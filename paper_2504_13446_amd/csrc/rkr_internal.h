@@ -136,5 +136,7 @@ hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int va
 // the software-pipelined exact pass for BF16 scores (exact.hip); its tasks
 // hold one pair each
 hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st);
+// the same kernel as a screening pass, one pair per task
+hipError_t launch_screen1_bf16(const CountArgs &a, int nsplit, hipStream_t st);
 
 }  // namespace rkr

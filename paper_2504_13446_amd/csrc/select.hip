@@ -430,6 +430,7 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     ts.ntask = 0;
     ts.ntask_pad = 0;
     ts.cap_total = 0;
+    ts.nusers = 0;
     if (N <= 0) return hipSuccess;
     hipError_t e;
     int32_t *flag = (int32_t *)sc.take(N * 4);
@@ -441,6 +442,7 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     int64_t ntask = 0;
     if ((e = hipMemcpyAsync(&ntask, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    ts.nusers = ntask;
     if (max_len > 0 && ntask < N) {
         // runs of one user become tasks of at most max_len pairs
         int64_t *run_start = (int64_t *)sc.take((ntask + 1) * 8);
