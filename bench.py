@@ -263,7 +263,8 @@ def main() -> int:
                                              "screen_variant", "table_pruned", "mfma_flop", "scored_pairs",
                                              "scored_seed", "scored_exact")},
         "roofline": {
-            "kernel": "k_count exact mode (BF16 32x32x16 MFMA, 1x2 tile): the seed and refine launches of a step",
+            "kernel": "k_pass<13, false>: the pipelined exact pass (BF16 32x32x16 MFMA, threshold folded into the "
+                      "accumulators): the seed and refine launches of a step",
             "bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": exact_traffic({"workload": w.name, "n": n, "m": m, "d": d, "queries": nq,

@@ -153,8 +153,8 @@ __device__ inline void wait_vm_n(int n) {
 }
 
 template <int NKS, bool SCREEN>
-__device__ inline void pass_tile(const CountArgs &a, const int64_t tile, uint8_t *lds, int2 *recs, int *wg_live,
-                                 uint64_t &ncmp, uint64_t &nslot, uint64_t &nstep, uint64_t &nscored) {
+__device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const int split, uint8_t *lds, int2 *recs,
+                                 int *wg_live, uint64_t &ncmp, uint64_t &nslot, uint64_t &nstep, uint64_t &nscored) {
     using G = ExactGeom<NKS>;
     using FT = typename FragT<SK_BF16>::T;
     constexpr int NIB = EX_NIB;
@@ -169,7 +169,6 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, uint8_t
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);   // the same, known to be uniform
     const int l32 = lane & 31;
     const int half = lane >> 5;
-    const int split = blockIdx.y;
     const int64_t s_begin = a.step0 + (int64_t)split * a.steps_per_split;
     const int64_t s_end = std::min<int64_t>(s_begin + a.steps_per_split, a.step_end);
 
@@ -512,7 +511,11 @@ __global__ __launch_bounds__(512) void k_pass(CountArgs a) {
     const int lane = threadIdx.x & 63;
     if (SCREEN && threadIdx.x < 3) wg_live[threadIdx.x] = 0;   // read after the tile's first barrier
     uint64_t ncmp = 0, nslot = 0, nstep = 0, nscored = 0;
-    pass_tile<NKS, SCREEN>(a, (int64_t)blockIdx.x, lds, recs, wg_live, ncmp, nslot, nstep, nscored);
+    // one workgroup per (tile, item split); a mapping that gave each XCD
+    // consecutive tiles of one split (shared items in its L2) measured slower
+    const int split = (int)blockIdx.y;
+    const int64_t tile = blockIdx.x;
+    pass_tile<NKS, SCREEN>(a, tile, split, lds, recs, wg_live, ncmp, nslot, nstep, nscored);
     uint64_t tot = ncmp, tslot = nslot;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
