@@ -296,6 +296,19 @@ rkr_status rkr_rank_table(const rkr_index *idx, double *t_out, uint32_t *cnt_out
  */
 rkr_status rkr_score_error(rkr_index *idx, double *max_ratio_out, int64_t *over_out);
 
+/*
+ * The same check in the form the BF16 exact and screening passes take
+ * (Sec. 4's rank counting with the threshold of query q): for every user u,
+ * th = the least FP32 value >= s(u, q) is folded into the matrix-core
+ * accumulators (they start from -th), and for every (user, item) pair the
+ * result acc is checked against |acc - (s(u,p) - th)| <= E (1 + 1/dpad) +
+ * gamma(dpad + 1) |th|, gamma(n) = 2n 2^-23, E the bound above and dpad the
+ * padded dimension.  q [device, d values of the master type].  Outputs as
+ * rkr_score_error.  RKR_E_UNSUPPORTED unless the score kind is BF16;
+ * RKR_E_INVALID for a non-finite or too large value in q.
+ */
+rkr_status rkr_score_error_at(rkr_index *idx, const void *q, double *max_ratio_out, int64_t *over_out);
+
 /* Exact Def. 1 rank of q for every user: ranks_out [device, n int32]. */
 rkr_status rkr_ranks(rkr_index *idx, const void *q, int32_t *ranks_out);
 

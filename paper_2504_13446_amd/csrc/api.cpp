@@ -648,6 +648,60 @@ extern "C" rkr_status rkr_score_error(rkr_index *x, double *max_ratio_out, int64
     return RKR_OK;
 }
 
+// The same check in the form of the pipelined passes (BF16 scores): the
+// thresholds th = the FP32 values above s64(u, q) folded into the
+// accumulators, checked against their bound.
+extern "C" rkr_status rkr_score_error_at(rkr_index *x, const void *q, double *max_ratio_out, int64_t *over_out) {
+    g_err.clear();
+    if (!x || !q || !max_ratio_out || !over_out) return fail(RKR_E_INVALID, "NULL argument");
+    if (x->sk != SK_BF16) return fail(RKR_E_UNSUPPORTED, "the folded form is the BF16 passes'");
+    hipStream_t st = x->st;
+    x->sc.reset();
+    HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
+    HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
+    int flags = 0;
+    HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (flags) return fail(RKR_E_INVALID, "the query holds a non-finite value or one above 2^50");
+    uint32_t *out = (uint32_t *)x->sc.take(8);
+    double *t64 = (double *)x->sc.take(x->n * 8);
+    float *th = (float *)x->sc.take(x->n * 4);
+    if (!out || !t64 || !th) return fail(RKR_E_NOMEM, "scratch");
+    HIPCK(launch_thresh_dense(x->Um.p, x->n, q, 1, x->d, x->mk, t64, st));
+    HIPCK(q_round_up_f32(t64, x->n, th, st));
+    HIPCK(launch_fill_u32(out, 0, 2, st));
+    if (x->m > 0) {
+        PairSet ps;
+        TaskSet ts;
+        const int xv = 2;
+        CountArgs a = count_args(x, ps, ts, xv);
+        a.ntask = x->n;
+        a.cnt_out = out;
+        a.stat = nullptr;
+        a.emit = nullptr;
+        a.emit_count = nullptr;
+        a.emit_cap = 0;
+        a.um_master = x->Um.p;
+        a.pm_master = x->Pm.p;
+        a.d_master = x->d;
+        a.mk_master = x->mk;
+        a.fold_th = th;
+        const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+        int64_t nsplit = pick_nsplit((x->n + tpw - 1) / tpw, a.nsteps, x->num_cus);
+        a.steps_per_split = (a.nsteps + nsplit - 1) / nsplit;
+        nsplit = (a.nsteps + a.steps_per_split - 1) / a.steps_per_split;
+        HIPCK(launch_count(x->sk, CM_BOUND, a, (int)nsplit, xv, st));
+    }
+    uint32_t h[2] = {0, 0};
+    HIPCK(hipMemcpyAsync(h, out, 8, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    float r;
+    memcpy(&r, &h[0], 4);
+    *max_ratio_out = (double)r;
+    *over_out = (int64_t)h[1];
+    return RKR_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batch queries
 // ---------------------------------------------------------------------------

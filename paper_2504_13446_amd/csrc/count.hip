@@ -134,6 +134,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
     int64_t ebase[NUB];
     double un_hat[NUB], un_del[NUB], un_full[NUB];
     int uscale[NUB];
+    float fth[NUB];   // bound check: the folded threshold (0 without)
     FT bfrag[NUB][NKS];
 #pragma unroll
     for (int ub = 0; ub < NUB; ++ub) {
@@ -152,6 +153,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             if constexpr (MODE == CM_SCREEN) ebase[ub] += (int64_t)split * a.cap_total;
         }
         uid[ub] = u;
+        fth[ub] = (MODE == CM_BOUND && a.fold_th && u >= 0) ? a.fold_th[u] : 0.0f;
         un_hat[ub] = un_del[ub] = un_full[ub] = 0.0;
         uscale[ub] = 127;
         if (u >= 0) {
@@ -483,7 +485,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
 #pragma unroll
             for (int ub = 0; ub < NUB; ++ub)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[ib][ub][r] = 0.0f;
+                for (int r = 0; r < 16; ++r) acc[ib][ub][r] = MODE == CM_BOUND ? -fth[ub] : 0.0f;
         int pscale[NIB];
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib) {
@@ -652,7 +654,13 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
             }
             if constexpr (MODE == CM_BOUND) {
                 // the lane's largest |score - s64| / eps over its real items,
-                // and the number of scores beyond eps (there should be none)
+                // and the number of scores beyond eps (there should be none);
+                // folded: |acc - (s64 - th)| against the folded bound
+                const double fold = (double)fth[ub];
+                const double efold = a.fold_th ? f32_round_up((E * (1.0 + 1.0 / (double)a.dpad) +
+                                                               2.0 * (double)(a.dpad + 1) * 0x1p-23 * fabs(fold)) *
+                                                              (1.0 + 1e-9))
+                                               : (double)eps;
                 if (uid[ub] >= 0) {
                     const int64_t urow = (int64_t)uid[ub] * a.d_master;
 #pragma unroll
@@ -665,7 +673,7 @@ __device__ inline void count_tile(const CountArgs &a, const int64_t tile, uint8_
                                 for (int k = 0; k < a.d_master; ++k)
                                     s64 = fma(master_elem(a.um_master, a.mk_master, urow + k),
                                               master_elem(a.pm_master, a.mk_master, item * a.d_master + k), s64);
-                                const double ratio = fabs((double)acc[ib][ub][r] - s64) / (double)eps;
+                                const double ratio = fabs((double)acc[ib][ub][r] - (s64 - fold)) / efold;
                                 bound_max = fmax(bound_max, ratio);
                                 bound_over += ratio > 1.0 ? 1u : 0u;
                             }

@@ -106,6 +106,8 @@ struct CountArgs {
     int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
     int hist_min;                 // screening: bucketed counting once some lane of a wave holds
                                   // this many live entries (0: never)
+    const float *fold_th;         // bound check only: per-user FP32 threshold folded into the
+                                  // accumulators (the form of the pipelined passes), or null
     const void *um_master;        // bound check only: master user rows [n][d]
     const void *pm_master;        // bound check only: master item rows in norm order [m][d]
     int d_master, mk_master;
@@ -125,7 +127,9 @@ struct CountArgs {
 // values (um_master, pm_master: user rows, items in norm order) and the
 // largest |score - s64| / eps (eps: the bound the other modes use for that
 // user and step) goes to cnt_out[0] (FP32 bits, rounded up), the number of
-// scores with ratio above 1 to cnt_out[1].
+// scores with ratio above 1 to cnt_out[1].  With fold_th, the accumulators
+// start from -th (th = fold_th[u]) as in the pipelined passes, and the check is
+// |acc - (s64 - th)| against their bound E (1 + 1/dpad) + gamma(dpad + 1) |th|.
 enum CountMode { CM_SCREEN = 0, CM_EXACT = 1, CM_TABLE = 2, CM_BOUND = 3 };
 constexpr int TABLE_COLS = 48;
 

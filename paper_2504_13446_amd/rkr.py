@@ -27,7 +27,7 @@ MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",
            "rkr_query_table", "rkr_query_table_batch", "rkr_paper_table_build", "rkr_paper_table",
-           "rkr_query_paper_table", "rkr_query_paper_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_score_error", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
+           "rkr_query_paper_table", "rkr_query_paper_table_batch", "rkr_query_batch", "rkr_ranks", "rkr_ranks_noalloc", "rkr_score_error", "rkr_score_error_at", "rkr_train", "rkr_predict", "rkr_mlp_get", "rkr_mlp_set",
            "rkr_mlp_grad", "rkr_mlp_adam", "rkr_sketch", "rkr_rank_table", "rkr_stats", "rkr_last_error")
 
 
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
         "rkr_ranks": [vp, vp, vp],
         "rkr_ranks_noalloc": [vp, vp, vp],
         "rkr_score_error": [vp, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
+        "rkr_score_error_at": [vp, vp, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
         "rkr_train": [vp, i32, vp, i32, i32, i32, f32, ctypes.c_uint64],
         "rkr_predict": [vp, i32, vp, vp],
         "rkr_mlp_get": [vp, vp],
@@ -289,6 +290,15 @@ def rkr_score_error(h: int):
     return r.value, over.value
 
 
+def rkr_score_error_at(h: int, q: torch.Tensor):
+    """The check in the threshold-folded form of the BF16 passes, thresholds of query q:
+    (largest |acc - (s64 - th)| / bound, pairs above 1)."""
+    r = ctypes.c_double()
+    over = ctypes.c_int64()
+    _check(load().rkr_score_error_at(h, _ptr(q), ctypes.byref(r), ctypes.byref(over)))
+    return r.value, over.value
+
+
 def rkr_ranks_noalloc(h: int, q: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
     """rkr_ranks into a caller-provided int32 tensor, with no device allocation."""
     assert out.dtype == torch.int32 and out.is_contiguous()
@@ -408,6 +418,9 @@ class Index:
 
     def score_error(self):
         return rkr_score_error(self.h)
+
+    def score_error_at(self, q):
+        return rkr_score_error_at(self.h, q)
 
     def ranks(self, q):
         return rkr_ranks(self.h, q, self.n)

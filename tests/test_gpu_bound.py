@@ -10,7 +10,9 @@ score of the count kernel and reports the largest |s_hat - s| / eps and the
 number of pairs above 1: over a billion pairs of random data and several
 inputs built to stress the bound (cancellation, extreme and mixed norms,
 entries near the FP32 underflow, integer data, low rank), no pair may exceed
-its bound.
+its bound.  rkr_score_error_at does the same for the form the BF16 exact and
+screening passes take, with the query's thresholds folded into the
+accumulators.
 """
 import numpy as np
 import pytest
@@ -102,6 +104,57 @@ def test_low_rank_uneven_dimension(score):
     """Low-rank data (shared 20-dim basis) at d = 300 with ragged n and m."""
     w = W.make("uneven", n=3_001, m=5_003, d=300, nq=1)
     _check(w.U, w.P, "f32", score)
+
+
+def _check_at(U, P, Q, masters, slack=1.0):
+    """The threshold-folded form of the BF16 passes, for each query of Q."""
+    idx = rkr.Index(rkr.to_device(U, masters), rkr.to_device(P, masters), score="bf16")
+    worst = 0.0
+    try:
+        for j in range(Q.shape[0]):
+            ratio, over = idx.score_error_at(rkr.to_device(Q[j:j + 1], masters)[0])
+            print(f"  folded {masters} n={U.shape[0]} m={P.shape[0]} d={U.shape[1]} query {j}: "
+                  f"max |acc - (s - th)| / bound = {ratio:.4g}, pairs over = {over}", flush=True)
+            assert over == 0
+            assert ratio <= slack
+            worst = max(worst, ratio)
+    finally:
+        idx.close()
+    return worst
+
+
+def test_folded_random_batch_data():
+    """16,384 x 16,384 pairs of the batch workload for two of its queries, and
+    for a query 2^20 times longer (|th| far above every |u||p|: the folded
+    threshold's own rounding dominates)."""
+    w = W.make("batch", n=16_384, m=16_384, nq=2)
+    Q = np.concatenate([W.bf16_bits_to_f32(w.Qv), 2.0 ** 20 * W.bf16_bits_to_f32(w.Qv[:1])])
+    ratio = _check_at(w.U, w.P, _masters(Q, "bf16"), "bf16")
+    assert ratio > 1e-3
+
+
+def test_folded_stress_inputs():
+    """Cancellation, extreme norms and integer data, each with a query equal to
+    an item (thresholds among the scores) and a zero query (th = 0)."""
+    rng = np.random.default_rng(31)
+    n, m, d = 4096, 4096, 128
+    sign = np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
+    cases = [
+        (sign[None, :] * rng.uniform(1e3, 2e3, size=(n, 1)) * (1 + 1e-3 * rng.standard_normal((n, d))),
+         1.0 + 1e-2 * rng.standard_normal((m, d))),
+        (rng.standard_normal((n, d)) * np.exp2(rng.integers(-36, 37, size=(n, 1))),
+         rng.standard_normal((m, d)) * np.exp2(rng.integers(-36, 37, size=(m, 1)))),
+        (rng.integers(-7, 8, size=(n, d)).astype(np.float64), rng.integers(-7, 8, size=(m, d)).astype(np.float64)),
+    ]
+    for U, P in cases:
+        Q = np.stack([P[7], P[m // 2] * 3.0, np.zeros(d)])
+        _check_at(_masters(U, "f32"), _masters(P, "f32"), _masters(Q, "f32"), "f32")
+
+
+def test_folded_uneven_dimension():
+    """Low-rank data at d = 300 with ragged n and m (dpad 304), two queries."""
+    w = W.make("uneven", n=3_001, m=5_003, d=300, nq=2)
+    _check_at(w.U, w.P, w.Qv, "f32")
 
 
 def test_pair_total():
