@@ -555,7 +555,9 @@ def single_all_ranks(rkr, W) -> dict:
     replays of the captured all-ranks graph (median of 10 after warm-up):
     BF16 scores + FP64 recheck, FP32 scores + FP64 recheck (the low-rank
     scores crowd near each threshold, so the narrower FP32 band pays here),
-    and the plain FP32 path (not exact) for the same query."""
+    split BF16 scores (hi + lo per value, three BF16 products per term on the
+    matrix cores, a band about 2^-13 as wide as BF16's) + FP64 recheck, and
+    the plain FP32 path (not exact) for the same query."""
     import torch
     w = W.make("single")
     U = rkr.to_device(w.U, w.dtype)
@@ -563,7 +565,7 @@ def single_all_ranks(rkr, W) -> dict:
     q = rkr.to_device(w.Qv[0], w.dtype)
     res = {"workload": "single", "n_users": w.n, "m_items": w.m, "d": w.d}
     for name, kw in (("bf16_recheck", dict(score="bf16")), ("fp32_recheck", dict(score="f32")),
-                     ("fp32_plain", dict(score="f32", recheck=False))):
+                     ("bf16x3_recheck", dict(score="bf16x3")), ("fp32_plain", dict(score="f32", recheck=False))):
         idx = rkr.Index(U, P, **kw)
         idx.configure(graph=True)
         for _ in range(3):
@@ -580,8 +582,10 @@ def single_all_ranks(rkr, W) -> dict:
         res[name] = {"ms_per_query": round(ms, 3), "gcompare_per_s": round(w.n * w.m / (ms / 1e3) / 1e9, 1),
                      "near_ties_rechecked": int(st["uncertain"]), "graph_replays": int(st["graph_replays"])}
         idx.close()
-    log("single all-ranks: bf16+recheck %.2f ms, fp32+recheck %.2f ms, fp32 plain %.2f ms per query" % (
-        res["bf16_recheck"]["ms_per_query"], res["fp32_recheck"]["ms_per_query"], res["fp32_plain"]["ms_per_query"]))
+    log("single all-ranks: bf16+recheck %.2f ms, fp32+recheck %.2f ms, split bf16+recheck %.2f ms, "
+        "fp32 plain %.2f ms per query" % (
+            res["bf16_recheck"]["ms_per_query"], res["fp32_recheck"]["ms_per_query"],
+            res["bf16x3_recheck"]["ms_per_query"], res["fp32_plain"]["ms_per_query"]))
     return res
 
 

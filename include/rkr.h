@@ -64,7 +64,10 @@ typedef enum { RKR_F32 = 0, RKR_BF16 = 1 } rkr_dtype;
 typedef enum {
     RKR_SCORE_F32 = 0,   /* FP32 inputs, FP32 accumulation              */
     RKR_SCORE_BF16 = 1,  /* BF16 inputs (round to nearest even), FP32 acc */
-    RKR_SCORE_FP8 = 2    /* FP8 e4m3 with a power-of-two scale per vector */
+    RKR_SCORE_FP8 = 2,   /* FP8 e4m3 with a power-of-two scale per vector */
+    RKR_SCORE_BF16X3 = 3 /* split BF16: each value as hi + lo (two BF16), */
+                         /* scores hi.hi + hi.lo + lo.hi over 3d terms,   */
+                         /* FP32 acc (error ~2^-16 relative, d <= 106)    */
 } rkr_score;
 
 typedef struct {

@@ -163,6 +163,7 @@ struct RanksGraph {
 struct rkr_index {
     int64_t n = 0, m = 0;
     int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1;
+    int split = 0;                    // 1: split BF16 scores (sk is SK_BF16, rows of 3d terms)
     int64_t nblk32 = 0, nblk = 0;     // item blocks of 32 (real, allocated: a multiple of 4)
     int num_cus = 256;
     int dev = 0;                      // device the index was built on
@@ -223,19 +224,25 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
         table = opts->rank_table;
         st = (hipStream_t)opts->stream;
     }
-    if (sk != SK_F32 && sk != SK_BF16 && sk != SK_FP8) return fail(RKR_E_INVALID, "unknown score kind");
+    if (sk != SK_F32 && sk != SK_BF16 && sk != SK_FP8 && sk != RKR_SCORE_BF16X3)
+        return fail(RKR_E_INVALID, "unknown score kind");
     if (sketch < 0) return fail(RKR_E_INVALID, "sketch_samples must be >= 0");
     if (table < 0) return fail(RKR_E_INVALID, "rank_table must be >= 0");
+    // split BF16 runs the BF16 kernels on rows of 3d terms
+    const int split = sk == RKR_SCORE_BF16X3 ? 1 : 0;
+    if (split) sk = SK_BF16;
     const int KS = frag_ks(sk);
-    // pad d to a k-step count the count kernels are instantiated for (zero padding)
-    const int nks = nks_bucket(sk, (d + KS - 1) / KS);
+    const int terms = split ? 3 * d : d;
+    // pad to a k-step count the count kernels are instantiated for (zero padding)
+    const int nks = nks_bucket(sk, (terms + KS - 1) / KS);
     if (nks == 0)
-        return fail(RKR_E_UNSUPPORTED, "d too large for this score kind (max " + std::to_string(max_nks(sk) * KS) + ")");
+        return fail(RKR_E_UNSUPPORTED, "d too large for this score kind (max " +
+                                           std::to_string(max_nks(sk) * KS / (split ? 3 : 1)) + ")");
     const int dpad = nks * KS;
 
     rkr_index *x = new (std::nothrow) rkr_index();
     if (!x) return fail(RKR_E_NOMEM, "host allocation failed");
-    x->n = n; x->m = m; x->d = d; x->dpad = dpad; x->nks = nks; x->sk = sk; x->recheck = recheck;
+    x->n = n; x->m = m; x->d = d; x->dpad = dpad; x->nks = nks; x->sk = sk; x->split = split; x->recheck = recheck;
     x->mk = dt == RKR_BF16 ? MK_BF16 : MK_F32;
     x->st = st;
     x->qo.seed_mult = 0;   // chosen per call (see run_batch)
@@ -278,16 +285,21 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
             HIPCK(launch_gather_rows(P, x->perm.as<int32_t>(), m, d, x->mk, x->Pm.p, st));
         }
         HIPCK(launch_fill_u8(x->plp.as<uint8_t>(), 0, (int64_t)x->nblk * 32 * dpad * es, st));
-        HIPCK(launch_lowprec(x->Um.p, n, d, x->mk, sk, dpad, 0, x->ulp.as<uint8_t>(), x->unorm3.as<double>(),
-                             x->uexp.as<int8_t>(), st));
-        HIPCK(launch_lowprec(x->Pm.p, m, d, x->mk, sk, dpad, 1, x->plp.as<uint8_t>(), x->pnorm3.as<double>(),
-                             x->pexp.as<int8_t>(), st));
+        HIPCK(launch_lowprec(x->Um.p, n, d, x->mk, sk, dpad, 0, split, x->ulp.as<uint8_t>(),
+                             x->unorm3.as<double>(), x->uexp.as<int8_t>(), st));
+        HIPCK(launch_lowprec(x->Pm.p, m, d, x->mk, sk, dpad, 1, split ? 2 : 0, x->plp.as<uint8_t>(),
+                             x->pnorm3.as<double>(), x->pexp.as<int8_t>(), st));
         const double u = ldexp(1.0, -23);
-        const double g32 = sk == SK_F32 ? 2.0 * (dpad + 2) * u : 2.0 * dpad * u;
+        double g32 = sk == SK_F32 ? 2.0 * (dpad + 2) * u : 2.0 * dpad * u;
+        // split BF16: the products summed, |hi.hi| + |hi.lo| + |lo.hi|, stay
+        // below (1 + 2^-5) |u_hat| |p_hat|, and the lo.lo product left out is
+        // below 1.02 * 2^-16 |u| |p| (|lo| <= 2^-8 (1 + 2^-8) |x| per element)
+        if (split) g32 *= 1.0 + 0x1p-5;
+        const double cz = split ? 0x1.06p-16 : 0.0;
         const double u64 = ldexp(1.0, -53);
         const double g64 = d * u64 / (1.0 - d * u64) * 1.01;
         const double eabs = dpad * ldexp(1.0, -100);
-        HIPCK(launch_block_coef(x->pnorm3.as<double>(), m, x->nblk, g32, g64, eabs, x->coef.as<double>(), st));
+        HIPCK(launch_block_coef(x->pnorm3.as<double>(), m, x->nblk, g32, g64, cz, eabs, x->coef.as<double>(), st));
         for (int k = 0; k < 3; ++k) {
             const int nib = 1 << k;
             const int64_t ns = (x->nblk32 + nib - 1) / nib;

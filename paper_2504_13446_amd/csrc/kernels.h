@@ -107,10 +107,12 @@ size_t norm_sort_scratch_bytes(int64_t m);
 hipError_t launch_norm_sort(const double *norms, int64_t m, void *scratch, int32_t *order, hipStream_t st);
 hipError_t launch_gather_rows(const void *src, const int32_t *order, int64_t rows, int d, int mk, void *dst,
                               hipStream_t st);
-hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag, uint8_t *out,
-                          double *norm3, int8_t *exps, hipStream_t st);
-hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64, double eabs,
-                             double *coef, hipStream_t st);
+// split: 0 = one low-precision value per dimension; 1 / 2 = split BF16 rows
+// [hi | hi | lo] (users) / [hi | lo | hi] (items) over 3d of the dpad positions
+hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag, int split,
+                          uint8_t *out, double *norm3, int8_t *exps, hipStream_t st);
+hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64, double cz,
+                             double eabs, double *coef, hipStream_t st);
 hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out,
                             hipStream_t st);
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,

@@ -143,7 +143,12 @@ __device__ inline uint8_t fp8_e4m3_rne(float v, float *dec) {
 // (|x_hat|, |x - x_hat|, |x|), and (FP8) the row's scale exponent.
 // Layout: row-major [rows][dpad] if frag == 0, else fragment order
 //   [row / 32][k-step][lane][FB bytes] with lane = row % 32 + 32 * half.
-__global__ void k_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag,
+// Split BF16 (split != 0): each value is hi = bf16(x) plus lo = bf16(x - hi),
+// x_hat = hi + lo, and the row holds three copies of the d dimensions back to
+// back, [hi | hi | lo] for split == 1 and [hi | lo | hi] for split == 2, so
+// that one dot product of a split-1 row with a split-2 row over 3d terms is
+// hi.hi + hi.lo + lo.hi.
+__global__ void k_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag, int split,
                           uint8_t *out, double *norm3, int8_t *exps) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows) return;
@@ -165,13 +170,23 @@ __global__ void k_lowprec(const void *X, int64_t rows, int d, int mk, int sk, in
     }
     double nh = 0.0, nd = 0.0, nf = 0.0;
     for (int k = 0; k < dpad; ++k) {
-        double x = k < d ? master_elem(X, mk, r * d + k) : 0.0;
+        // position k holds dimension src of copy seg (seg 3 and above: padding)
+        const int seg = split ? k / d : (k < d ? 0 : 3);
+        const int src = split ? k - seg * d : k;
+        double x = seg < 3 ? master_elem(X, mk, r * d + src) : 0.0;
         double xh;
         uint8_t bytes[4];
         if (sk == SK_BF16) {
             float xf = (fabs(x) < 0x1p-50) ? 0.0f : (float)x;
             uint16_t b = bf16_rne(xf);
             xh = (double)__uint_as_float((uint32_t)b << 16);
+            if (split) {
+                // xf - hi is exact in FP32 (the rounding error of hi)
+                const uint16_t bl = bf16_rne((float)((double)xf - xh));
+                const double xl = (double)__uint_as_float((uint32_t)bl << 16);
+                if (seg == (split == 1 ? 2 : 1)) b = bl;
+                xh += xl;            // x_hat = hi + lo, exact in FP64
+            }
             bytes[0] = b & 0xFF; bytes[1] = b >> 8;
         } else if (sk == SK_F32) {
             float xf = (fabs(x) < 0x1p-50) ? 0.0f : (float)x;
@@ -184,10 +199,12 @@ __global__ void k_lowprec(const void *X, int64_t rows, int d, int mk, int sk, in
             xh = ldexp((double)dec, scale_e);
             bytes[0] = b;
         }
-        double dl = x - xh;      // exact: both are FP32-representable, same scale
-        nh = fma(xh, xh, nh);
-        nd = fma(dl, dl, nd);
-        nf = fma(x, x, nf);
+        if (seg == 0) {          // each dimension once
+            double dl = x - xh;  // exact: both are FP32-representable, same scale
+            nh = fma(xh, xh, nh);
+            nd = fma(dl, dl, nd);
+            nf = fma(x, x, nf);
+        }
         int64_t off;
         if (!frag) {
             off = (r * dpad + k) * ES;
@@ -207,11 +224,13 @@ __global__ void k_lowprec(const void *X, int64_t rows, int d, int mk, int sk, in
 }
 
 // Error-bound coefficients per 32-item block (items sorted by norm):
-//   a = g32 * X + Y,  b = X + Y,  c = g64 * Z,  abs
+//   a = g32 * X + Y,  b = X + Y,  c = (g64 + cz) * Z,  abs
 // with X = max |p_hat|, Y = max |delta p|, Z = max |p| over the block, so that
 //   |score - s64(u,p)| <= |u_hat| a + |delta u| b + |u| c + abs.
+// cz is the relative bound of a product the score leaves out (split BF16:
+// lo.lo), 0 otherwise.
 __global__ void k_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64,
-                             double eabs, double *coef) {
+                             double cz, double eabs, double *coef) {
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblk) return;
     double X = 0, Y = 0, Z = 0;
@@ -223,7 +242,7 @@ __global__ void k_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
     const double infl = 1.0 + 0x1p-40;
     coef[4 * b + 0] = (g32 * X + Y) * infl;
     coef[4 * b + 1] = (X + Y) * infl;
-    coef[4 * b + 2] = g64 * Z * infl;
+    coef[4 * b + 2] = (g64 + cz) * Z * infl;
     coef[4 * b + 3] = eabs;
 }
 
@@ -515,19 +534,20 @@ hipError_t launch_gather_rows(const void *src, const int32_t *order, int64_t row
     return hipGetLastError();
 }
 
-hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag,
+hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, int dpad, int frag, int split,
                           uint8_t *out, double *norm3, int8_t *exps, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
+    if (split && (sk != SK_BF16 || 3 * d > dpad)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lowprec, dim3(nblocks(rows, 128)), dim3(128), 0, st, X, rows, d, mk, sk, dpad,
-                       frag, out, norm3, exps);
+                       frag, split, out, norm3, exps);
     return hipGetLastError();
 }
 
 hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64,
-                             double eabs, double *coef, hipStream_t st) {
+                             double cz, double eabs, double *coef, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_coef, dim3(nblocks(nblk, 256)), dim3(256), 0, st, pnorm3, m, nblk, g32,
-                       g64, eabs, coef);
+                       g64, cz, eabs, coef);
     return hipGetLastError();
 }
 

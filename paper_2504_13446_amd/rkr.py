@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(_HERE, "librkr.so")
 
 RKR_OK, RKR_E_INVALID, RKR_E_NOMEM, RKR_E_DEVICE, RKR_E_UNSUPPORTED, RKR_E_STATE = range(6)
 RKR_F32, RKR_BF16 = 0, 1
-RKR_SCORE_F32, RKR_SCORE_BF16, RKR_SCORE_FP8 = 0, 1, 2
-SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8}
+RKR_SCORE_F32, RKR_SCORE_BF16, RKR_SCORE_FP8, RKR_SCORE_BF16X3 = 0, 1, 2, 3
+SCORES = {"f32": RKR_SCORE_F32, "bf16": RKR_SCORE_BF16, "fp8": RKR_SCORE_FP8, "bf16x3": RKR_SCORE_BF16X3}
 MLP_NPARAM = 64 * 18 + 64 + 64 * 64 + 64 + 64 + 1
 TABLE_COLS = 48   # RKR_TABLE_COLS of include/rkr.h
 SYMBOLS = ("rkr_build", "rkr_destroy", "rkr_configure", "rkr_query_exact", "rkr_query_approx",

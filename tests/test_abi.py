@@ -64,6 +64,10 @@ def test_build_validation_before_device_work(L):
     assert "rank_table" in _err(L)
     # d beyond what the count kernel supports for BF16 scoring
     assert L.rkr_build(dummy, 10, dummy, 10, 4000, 0, None, ctypes.byref(h)) == rkr.RKR_E_UNSUPPORTED
+    # split BF16 rows hold 3d terms: d = 107 needs 321 > 320
+    split = rkr.BuildOpts(rkr.RKR_SCORE_BF16X3, 1, 0, 0, None)
+    assert L.rkr_build(dummy, 10, dummy, 10, 107, 0, ctypes.byref(split), ctypes.byref(h)) == rkr.RKR_E_UNSUPPORTED
+    assert "max 106" in _err(L)
     assert h.value is None
     assert L.rkr_build(dummy, 10, dummy, 10, 8, 0, None, None) == rkr.RKR_E_INVALID
 

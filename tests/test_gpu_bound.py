@@ -106,9 +106,9 @@ def test_low_rank_uneven_dimension(score):
     _check(w.U, w.P, "f32", score)
 
 
-def _check_at(U, P, Q, masters, slack=1.0):
+def _check_at(U, P, Q, masters, slack=1.0, score="bf16"):
     """The threshold-folded form of the BF16 passes, for each query of Q."""
-    idx = rkr.Index(rkr.to_device(U, masters), rkr.to_device(P, masters), score="bf16")
+    idx = rkr.Index(rkr.to_device(U, masters), rkr.to_device(P, masters), score=score)
     worst = 0.0
     try:
         for j in range(Q.shape[0]):
@@ -155,6 +155,47 @@ def test_folded_uneven_dimension():
     """Low-rank data at d = 300 with ragged n and m (dpad 304), two queries."""
     w = W.make("uneven", n=3_001, m=5_003, d=300, nq=2)
     _check_at(w.U, w.P, w.Qv, "f32")
+
+
+def _split_stress_cases(rng, n, m, d):
+    sign = np.where(np.arange(d) % 2 == 0, 1.0, -1.0)
+    U1 = rng.standard_normal((n, d)) * np.exp2(rng.integers(-60, -49, size=(n, d)))
+    P1 = rng.standard_normal((m, d)) * np.exp2(rng.integers(-60, -49, size=(m, d)))
+    U1[n // 2:, : d // 4] = rng.standard_normal((n - n // 2, d // 4))
+    P1[m // 2:, : d // 4] = rng.standard_normal((m - m // 2, d // 4))
+    return {
+        "cancellation": (sign[None, :] * rng.uniform(1e3, 2e3, size=(n, 1)) * (1 + 1e-3 * rng.standard_normal((n, d))),
+                         1.0 + 1e-2 * rng.standard_normal((m, d))),
+        "extreme norms": (rng.standard_normal((n, d)) * np.exp2(rng.integers(-36, 37, size=(n, 1)))
+                          * np.exp2(rng.integers(-10, 11, size=(n, d))),
+                          rng.standard_normal((m, d)) * np.exp2(rng.integers(-36, 37, size=(m, 1)))),
+        "near underflow": (U1, P1),
+        "integers": (rng.integers(-7, 8, size=(n, d)).astype(np.float64),
+                     rng.integers(-7, 8, size=(m, d)).astype(np.float64)),
+    }
+
+
+def test_split_bf16_random_and_stress():
+    """Split BF16 scores (hi + lo per value, three products per term): the
+    low-rank single-query data at 16,384 x 16,384, and the stress inputs above
+    at d = 96, against their bound, plain and with a query's thresholds folded
+    in.  The split's bound is about 2^-13 of the BF16 one's width on FP32
+    data, so the checks must also see errors well above zero."""
+    w = W.make("single", n=16_384, m=16_384, nq=2)
+    ratio = _check(w.U, w.P, "f32", "bf16x3")
+    assert ratio > 1e-3
+    _check_at(w.U, w.P, w.Qv, "f32", score="bf16x3")
+    rng = np.random.default_rng(41)
+    n, m, d = 4096, 4096, 96
+    for name, (U, P) in _split_stress_cases(rng, n, m, d).items():
+        print("  split BF16, " + name, flush=True)
+        U32, P32 = _masters(U, "f32"), _masters(P, "f32")
+        _check(U32, P32, "f32", "bf16x3")
+        Q = np.stack([P[5], P[m // 3] * 2.0, np.zeros(d)])
+        _check_at(U32, P32, _masters(Q, "f32"), "f32", score="bf16x3")
+    # BF16 masters: lo is zero, the split score is the BF16 one
+    wb = W.make("small", n=3000, m=5000, d=50, dtype="bf16")
+    _check(wb.U, wb.P, "bf16", "bf16x3")
 
 
 def test_pair_total():

@@ -2,8 +2,8 @@
 
 * The single-query workload (100,000 users x 100,000 items x d = 100, low-rank
   data, FP32 masters): every one of the 100,000 Def. 1 ranks of its query, for
-  BF16 scores + FP64 recheck and FP32 scores + FP64 recheck, eagerly and as a
-  graph replay, equals the oracle's bit for bit (about 1e12 FP64 fma in the
+  BF16, FP32 and split BF16 scores + FP64 recheck, eagerly and as a graph
+  replay, equals the oracle's bit for bit (about 1e12 FP64 fma in the
   oracle: a minute or two on the host's cores).
 * The batch workload (1M users x 1M items x d = 200, 256 queries, k = 100,
   with the rank table): the answer of the query with the smallest k-th rank
@@ -39,7 +39,7 @@ def test_single_query_all_ranks_full_size():
     q = _dev(w.Qv[0], "f32")
     U, P = _dev(w.U, "f32"), _dev(w.P, "f32")
     got = {}
-    for score in ("bf16", "f32"):
+    for score in ("bf16", "f32", "bf16x3"):
         idx = rkr.Index(U, P, score=score)
         got[score] = idx.ranks(q).cpu().numpy()
         st = idx.stats()
@@ -55,7 +55,7 @@ def test_single_query_all_ranks_full_size():
     R = O.ranks(w.U, w.P, w.Qv)[0]
     _log("oracle: 100,000 ranks in %.1f s on %d threads" % (time.time() - t, O.num_threads()))
     wi, wr = O.topk(R, 50)
-    for score in ("bf16", "f32"):
+    for score in ("bf16", "f32", "bf16x3"):
         for key in (score, score + "_graph"):
             bad = np.flatnonzero(got[key] != R)
             assert bad.size == 0, (key, bad[:10], got[key][bad[:10]], R[bad[:10]])

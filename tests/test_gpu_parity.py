@@ -38,7 +38,7 @@ def small():
     return w, O.ranks(w.U, w.P, w.Qv)
 
 
-@pytest.mark.parametrize("score", ["bf16", "f32", "fp8"])
+@pytest.mark.parametrize("score", ["bf16", "f32", "fp8", "bf16x3"])
 def test_small_batch_exact(small, score):
     w, R = small
     idx = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score=score)
@@ -49,7 +49,7 @@ def test_small_batch_exact(small, score):
     idx.close()
 
 
-@pytest.mark.parametrize("score", ["bf16", "f32", "fp8"])
+@pytest.mark.parametrize("score", ["bf16", "f32", "fp8", "bf16x3"])
 def test_small_all_ranks(small, score):
     w, R = small
     idx = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score=score)
@@ -77,7 +77,7 @@ def test_plain_f32_reports_its_disagreement(small):
 
 
 @pytest.mark.parametrize("d", [3, 8, 16])
-@pytest.mark.parametrize("score", ["bf16", "f32", "fp8"])
+@pytest.mark.parametrize("score", ["bf16", "f32", "fp8", "bf16x3"])
 def test_integer_tie_storm(d, score):
     """Entries in {-2..2}: every score is an exact small integer, ties everywhere;
     every near tie must go through the recheck and count as 'not above'."""
@@ -158,9 +158,10 @@ def test_batch_of_many_queries(masters, d):
         idx.close()
 
 
-def test_single_lowrank_scaled_all_ranks():
+@pytest.mark.parametrize("score", ["bf16", "bf16x3"])
+def test_single_lowrank_scaled_all_ranks(score):
     w = W.make("single", n=12000, m=9000)
-    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16")
+    idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score=score)
     got = idx.ranks(_dev(w.Qv[0], "f32")).cpu().numpy()
     sub = np.random.default_rng(0).choice(w.n, 1500, replace=False)
     want = O.ranks(w.U, w.P, w.Qv[0], uids=sub)[0]
