@@ -171,6 +171,7 @@ struct rkr_index {
     // index data
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
     DBuf coef_step[3];    // per-step coefficient maxima for steps of 1, 2, 4 blocks
+    DBuf step_znorm;      // per 64-item step: an upper bound of |p| from that step on
     // per-call buffers
     Scratch sc;
     DBuf pair_u, pair_q, pair_off, qm_pid, t64, cnt, seedflag, keys, sel, selrank, best, cand,
@@ -283,6 +284,9 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
             HIPCK(launch_spec_norm(P, m, d, x->mk, pn, st));
             HIPCK(launch_norm_sort(pn, m, srt, x->perm.as<int32_t>(), st));
             HIPCK(launch_gather_rows(P, x->perm.as<int32_t>(), m, d, x->mk, x->Pm.p, st));
+            const int64_t ns64 = (m + 63) / 64;
+            HIPCK(x->step_znorm.ensure((size_t)ns64 * 8));
+            HIPCK(launch_step_znorm(pn, x->perm.as<int32_t>(), m, ns64, x->step_znorm.as<double>(), st));
         }
         HIPCK(launch_fill_u8(x->plp.as<uint8_t>(), 0, (int64_t)x->nblk * 32 * dpad * es, st));
         HIPCK(launch_lowprec(x->Um.p, n, d, x->mk, sk, dpad, 0, split, x->ulp.as<uint8_t>(),
@@ -488,6 +492,8 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int va
     a.stat = x->ctr.as<unsigned long long>() + 1;
     a.plain = x->recheck ? 0 : 1;
     a.hist_min = screen_hist_min();
+    // the pipelined passes' steps are 64 items (two blocks)
+    a.step_znorm = (nib == 2 && x->m > 0 && !env_flag("RKR_NO_SETTLE")) ? x->step_znorm.as<double>() : nullptr;
     return a;
 }
 

@@ -224,6 +224,49 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // plain verdict of a near tie: score > tm, i.e. acc > tm - th (exact)
     const float pd = tm - th;
     uint32_t cnt = 0;   // per-lane certain count of the pair
+    // Cauchy-Schwarz settle of the exact passes (Lemma 1 over the
+    // norm-sorted items): |s64(u,p)| <= |u||p| (1 + gamma64) and |p| <= Z[st]
+    // from step st on, so from the first step s_set with |u| Z[st] (1 +
+    // 2^-30) < L the pair's verdict is the same for every later item: with
+    // L = tl <= t64 nothing is above; with L = -th everything is.  The
+    // workgroup scores up to the last settle step of its live pairs, and a
+    // pair settled above adds the items it did not score.  (s_set is found
+    // after the first copies are issued, so that its loads overlap them.)
+    int64_t s_set = INT64_MAX;
+    bool set_above = false;
+    auto find_settle = [&]() {
+        // (screening passes stop on their budgets; they do not settle)
+        if constexpr (SCREEN) return;
+        if (!(live && a.step_znorm && !a.plain)) return;
+        const float lpos = tl;
+        const double L = fmax((double)lpos, -(double)th);
+        if (!(L > 0.0)) return;
+        const double nu = un_full * (1.0 + 0x1p-30);
+        // the range's smallest bound first: most pairs never settle in it
+        if (!(nu * a.step_znorm[s_end - 1] < L)) return;
+        int64_t lo = s_begin, hi = s_end - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (nu * a.step_znorm[mid] < L) hi = mid; else lo = mid + 1;
+        }
+        s_set = lo;
+        set_above = th < 0.0f;
+    };
+    // items of the pass's range from step st on (real items only)
+    auto items_from = [&](int64_t st) -> int64_t {
+        return std::max<int64_t>(0, std::min<int64_t>(s_end * (NIB * 32), a.m) - st * (NIB * 32));
+    };
+    // the pass ends before step stop (s_end: it ran to the end)
+    auto settle_rest = [&](int64_t stop) {
+        if (!(live && set_above && stop < s_end)) return;
+        const int64_t rest = items_from(stop);
+        if constexpr (SCREEN) {
+            rem -= (int)rest;
+            live = rem >= 0;
+        } else if (half == 0) {
+            cnt += (uint32_t)rest;
+        }
+    };
     if (!__syncthreads_or(live) || s_begin >= s_end) return;
 
     // ---- near-tie records: a per-wave LDS buffer, flushed with one global
@@ -390,36 +433,54 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
               a.step_coef + 4 * (s_begin + k));
     // before the barrier at step st0: steps up to st0 + SP have landed; the
     // copies of later steps (staged up to step st0 - 1 + D) may be in flight
-    // Screening: the workgroup stops at a barrier once none of its pairs is
-    // live.  "Any live" flags, one slot per barrier, three in rotation: the
-    // slot of barrier b - 1 is cleared after barrier b (every read of it came
-    // before) and written again only after barrier b + 1.
+    find_settle();
+    // Exact: the workgroup scores the steps up to the last settle step of its
+    // live pairs (a maximum taken once; wg_live[0] holds it, in steps past
+    // s_begin).  Screening: it stops at a barrier once none of its pairs
+    // needs the steps from there on (dead or settled), with "any needs"
+    // flags, one slot per barrier, three in rotation: the slot of barrier
+    // b - 1 is cleared after barrier b (every read of it came before) and
+    // written again only after barrier b + 1.
+    if constexpr (!SCREEN) {
+        int need = live ? (int)(std::min<int64_t>(s_set, s_end) - s_begin) : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) need = std::max(need, __shfl_xor(need, o, 64));
+        if (lane == 0) atomicMax(&wg_live[0], need);
+    }
+    wait_vm_n((int)(npro - 1) * nload);
+    __syncthreads();
+    const int64_t s_run = SCREEN ? s_end : s_begin + wg_live[0];
     int lslot = 0;
     auto barrier_before = [&](int64_t st0) -> bool {
-        const int64_t last = std::min<int64_t>(st0 - 1 + D, s_end - 1);
+        // copies of steps past s_run issued before it was known only make
+        // this wait stricter
+        const int64_t last = std::min<int64_t>(st0 - 1 + D, s_run - 1);
         const int64_t later = std::max<int64_t>(0, last - (st0 + SP));
         wait_vm_n((int)later * nload);
-        if constexpr (SCREEN) {
-            if (lane == 0 && __ballot(live) != 0ull) atomicOr(&wg_live[lslot], 1);
-        }
-        __syncthreads();
-        if constexpr (SCREEN) {
+        if constexpr (!SCREEN) {
+            __syncthreads();
+            return true;
+        } else {
+            // (the ballot runs on every lane, outside the lane-0 branch)
+            const bool wave_needs = __ballot(live && st0 < s_set) != 0ull;
+            if (lane == 0 && wave_needs) atomicOr(&wg_live[lslot], 1);
+            __syncthreads();
             const int any = wg_live[lslot];
             if (tid == 0) wg_live[lslot == 0 ? 2 : lslot - 1] = 0;
             lslot = lslot == 2 ? 0 : lslot + 1;
             return any != 0;
         }
-        return true;
     };
-    wait_vm_n((int)(npro - 1) * nload);
-    __syncthreads();
 
     f32x16 accA[NIB], accB[NIB];
-    scores(lds, accA);
-    float ehi, elo;   // the band of the current step
-    band_of_tile(lds, ehi, elo);
-    mask_tail(accA, s_begin * (NIB * 32));
-    bool go = barrier_before(s_begin);
+    float ehi = 0.0f, elo = 0.0f;   // the band of the current step
+    bool go = false;
+    if (s_run > s_begin) {
+        scores(lds, accA);
+        band_of_tile(lds, ehi, elo);
+        mask_tail(accA, s_begin * (NIB * 32));
+        go = barrier_before(s_begin);
+    }
 
     int slot_nxt = 1 % NBUF;      // stage of step st + 1
     int slot_stg = D % NBUF;      // stage of step st + D
@@ -427,7 +488,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // The last step of a tile scores a stale stage too (its result is never
     // used): the block then has no branch, and the compare stays in it.
     auto body = [&](f32x16 *cur, f32x16 *nxt, int64_t st) {
-        if (st + D < s_end)
+        if (st + D < s_run)
             stage(a.plp + (st + D) * (int64_t)STEP_BYTES, lds_base + slot_stg * STAGE, wave_u, lane,
                   a.step_coef + 4 * (st + D));
         const int64_t item0 = st * (NIB * 32);
@@ -468,18 +529,23 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         ++nstep;
     };
 
-    for (int64_t st = s_begin; go;) {
-        body(accA, accB, st);
-        if (++st >= s_end) break;
-        if (SP == 1 && !barrier_before(st)) break;
-        body(accB, accA, st);
-        if (++st >= s_end) break;
-        if (!barrier_before(st)) break;
-    }
+    int64_t st = s_begin;
+    if (go)
+        for (;;) {
+            body(accA, accB, st);
+            if (++st >= s_run) break;
+            if (SP == 1 && !barrier_before(st)) break;
+            body(accB, accA, st);
+            if (++st >= s_run) break;
+            if (!barrier_before(st)) break;
+        }
+    // the pass scored steps s_begin .. stop - 1; a workgroup that stops
+    // early may still have copies in flight into its LDS: they land before
+    // it ends
+    const int64_t stop = go ? st : s_begin;
+    if (stop < s_end) wait_vm<0>();
+    settle_rest(stop);
     if constexpr (SCREEN) {
-        // a workgroup that stops early may still have copies in flight into
-        // its LDS: they land before it ends
-        wait_vm<0>();
         if (u >= 0 && half == 0) {
             a.ent_len[split * a.len_stride + t] = live ? 1 : 0;
             if (live) a.ent_cnt[e_pair] = (uint32_t)rem;
@@ -490,13 +556,13 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     flush_records();
 
     // ---- statistics and write-back (exact lists never change in a pass)
-    const uint64_t nsc = (uint64_t)(s_end - s_begin);
+    const uint64_t nsc = (uint64_t)(stop - s_begin);
     const uint32_t lanes = (uint32_t)__popcll(__ballot(live));
     ncmp += nsc * (live ? 1u : 0u) * NSC;
     nslot += nsc * (lanes ? 1u : 0u) * NSC;
     {
         const int64_t first = s_begin * (NIB * 32);
-        const int64_t last = std::min<int64_t>(s_end * (NIB * 32), a.m);
+        const int64_t last = std::min<int64_t>(stop * (NIB * 32), a.m);
         if (last > first) nscored += (uint64_t)(lanes / 2) * (uint64_t)(last - first);
     }
     const uint32_t tot = pair_sum(cnt);
@@ -509,7 +575,7 @@ __global__ __launch_bounds__(512) void k_pass(CountArgs a) {
     __shared__ int2 recs[SCREEN ? 1 : WAVES_PER_WG * REC_PER_WAVE];
     __shared__ int wg_live[3];
     const int lane = threadIdx.x & 63;
-    if (SCREEN && threadIdx.x < 3) wg_live[threadIdx.x] = 0;   // read after the tile's first barrier
+    if (threadIdx.x < 3) wg_live[threadIdx.x] = 0;   // read after the tile's first barrier
     uint64_t ncmp = 0, nslot = 0, nstep = 0, nscored = 0;
     // one workgroup per (tile, item split); a mapping that gave each XCD
     // consecutive tiles of one split (shared items in its L2) measured slower

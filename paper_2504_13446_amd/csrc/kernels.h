@@ -113,6 +113,10 @@ hipError_t launch_lowprec(const void *X, int64_t rows, int d, int mk, int sk, in
                           uint8_t *out, double *norm3, int8_t *exps, hipStream_t st);
 hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, double g32, double g64, double cz,
                              double eabs, double *coef, hipStream_t st);
+// per 64-item step of the norm-sorted items: an upper bound of |p| from that
+// step on (pn: spec norms by item id, order: sorted position -> id)
+hipError_t launch_step_znorm(const double *pn, const int32_t *order, int64_t m, int64_t nsteps, double *out,
+                             hipStream_t st);
 hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out,
                             hipStream_t st);
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,

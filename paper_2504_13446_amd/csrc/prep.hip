@@ -246,6 +246,17 @@ __global__ void k_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
     coef[4 * b + 3] = eabs;
 }
 
+// Per step of 64 items in norm order: an upper bound of |p| over the step's
+// items and every later one, the spec norm of the step's first item inflated
+// by 1 + 2^-40 (the norms are sorted, non-increasing, and the FP64 sum of
+// squares and its square root are within 2^-41 of |p|^2 and |p| for d <= 4096).
+__global__ void k_step_znorm(const double *pn, const int32_t *order, int64_t m, int64_t nsteps, double *out) {
+    int64_t st = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (st >= nsteps) return;
+    const int64_t i = st * 64;
+    out[st] = i < m ? pn[order[i]] * (1.0 + 0x1p-40) : 0.0;
+}
+
 // Per step of nib consecutive blocks: the maxima of the blocks' coefficients
 // (a step's error bound covers all of its items).
 __global__ void k_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out) {
@@ -548,6 +559,13 @@ hipError_t launch_block_coef(const double *pnorm3, int64_t m, int64_t nblk, doub
     if (nblk <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_coef, dim3(nblocks(nblk, 256)), dim3(256), 0, st, pnorm3, m, nblk, g32,
                        g64, cz, eabs, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_znorm(const double *pn, const int32_t *order, int64_t m, int64_t nsteps, double *out,
+                             hipStream_t st) {
+    if (nsteps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step_znorm, dim3(nblocks(nsteps, 256)), dim3(256), 0, st, pn, order, m, nsteps, out);
     return hipGetLastError();
 }
 

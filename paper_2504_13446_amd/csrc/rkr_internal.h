@@ -103,6 +103,8 @@ struct CountArgs {
     unsigned long long emit_cap;
     unsigned long long *stat;     // [0]: executed compares, [2]: compare lane slots, [4]: matrix-core flop,
                                   // [6]: (user, item) scores of users with a live pair
+    const double *step_znorm;     // pipelined passes: per 64-item step, an upper bound of |p| from
+                                  // that step on (Cauchy-Schwarz settle), or null
     int plain;                    // 1: compare the score with fl32(t) only (no band, no recheck)
     int hist_min;                 // screening: bucketed counting once some lane of a wave holds
                                   // this many live entries (0: never)
