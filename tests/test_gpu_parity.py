@@ -172,6 +172,34 @@ def test_single_lowrank_scaled_all_ranks(score):
     idx.close()
 
 
+@pytest.mark.parametrize("score", ["bf16", "bf16x3"])
+def test_cauchy_schwarz_settle(score):
+    """Items with norms spread over four orders of magnitude and a query 10^5
+    times longer than a typical item: most pairs are settled (Lemma 1 over the
+    norm-sorted items) long before the end of P -- below for q, above for -q
+    -- so workgroups stop early and pairs settled above add the items they did
+    not score.  Every rank must still equal the oracle's, over a ragged m and
+    several item splits, for all users and for a batch; the work counter
+    shows that most (user, item) scores were skipped."""
+    rng = np.random.default_rng(77)
+    n, m, d = 3000, 20_011, 16
+    U = rng.standard_normal((n, d)).astype(np.float32)
+    P = (rng.standard_normal((m, d)) * np.exp(1.5 * rng.standard_normal((m, 1)))).astype(np.float32)
+    e = rng.standard_normal(d)
+    Qv = np.stack([1e5 * e / np.linalg.norm(e), -1e5 * e / np.linalg.norm(e), P[5]]).astype(np.float32)
+    R = O.ranks(U, P, Qv)
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score=score)
+    for i in range(2):
+        got = idx.ranks(_dev(Qv[i], "f32")).cpu().numpy()
+        assert np.array_equal(got, R[i]), (i, np.flatnonzero(got != R[i])[:10])
+        scored = idx.stats()["scored_exact"]
+        assert scored < 0.5 * n * m, (i, scored)
+    ks = np.array([10, 3000, 50], np.int32)
+    ans = _answers(*idx.query_batch(_dev(Qv, "f32"), ks))
+    _check_exact(R, ans, ks)
+    idx.close()
+
+
 @pytest.mark.parametrize("score", ["bf16", "fp8"])
 def test_uneven_candidates_exact_and_approx(score):
     w = W.make("uneven", n=4000, m=2500, d=300, nq=24, cand=(50, 3000))
