@@ -51,7 +51,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
+PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0, "f32": 157.3}
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12     # 32-bit vector lane-ops/s (39.3 T)
 TRAFFIC = os.path.join(ROOT, "profiles", "k_count_exact_batch_1M_traffic.json")
 
@@ -104,7 +104,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--nq", type=int, default=None)
-    ap.add_argument("--score", default=None, choices=["bf16", "fp8", "f32"],
+    ap.add_argument("--score", default=None, choices=["bf16", "fp8", "f32", "bf16x3"],
                     help="score precision (default: fp8 for the uneven workload, else bf16)")
     ap.add_argument("--mode", default=None, choices=["exact", "approx"],
                     help="exact (Def. 2) or approximate (Def. 3, the workload's c); default: approximate "

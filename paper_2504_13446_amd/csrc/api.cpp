@@ -171,6 +171,7 @@ struct rkr_index {
     // index data
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
     DBuf coef_step[3];    // per-step coefficient maxima for steps of 1, 2, 4 blocks
+    DBuf coef32_step[2];  // the same for steps of 1 and 2 blocks, rounded up to FP32
     DBuf step_znorm;      // per 64-item step: an upper bound of |p| from that step on
     // per-call buffers
     Scratch sc;
@@ -309,6 +310,10 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
             const int64_t ns = (x->nblk32 + nib - 1) / nib;
             HIPCK(x->coef_step[k].ensure((size_t)std::max<int64_t>(ns, 1) * 4 * 8));
             HIPCK(launch_step_coef(x->coef.as<double>(), x->nblk, nib, ns, x->coef_step[k].as<double>(), st));
+            if (k < 2) {
+                HIPCK(x->coef32_step[k].ensure((size_t)std::max<int64_t>(ns, 1) * 4 * 4));
+                HIPCK(q_round_up_f32(x->coef_step[k].as<double>(), ns * 4, x->coef32_step[k].as<float>(), st));
+            }
         }
         int flags = 0;
         HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
@@ -348,7 +353,7 @@ extern "C" void rkr_destroy(rkr_index *x) {
     (void)hipStreamSynchronize(x->st);
     DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt, &x->ptab_fmin, &x->ptab_step, &x->ptab_cells,
                     &x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
-                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
+                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->coef32_step[0], &x->coef32_step[1], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
                     &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
                     &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
@@ -420,10 +425,14 @@ static std::string tune_key(const rkr_index *x, int nq, int64_t npairs) {
 }
 
 // Splits of the item range for an exact pass over gx user tiles (one
-// workgroup per CU): the count in 1..16 that minimises rounds x split length,
+// workgroup per CU): the count in 1..max_split that minimises rounds x split length,
 // ceil(gx * ns / cus) / ns (smallest such count on ties).
-static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus) {
-    const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(16, nsteps));
+// an exact pass's splits share nothing but the count they add to: few user
+// tiles (the refine of a batch's survivors) spread over more of them
+static constexpr int64_t kMaxExactSplits = 64;
+
+static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus, int64_t max_split = 16) {
+    const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(max_split, nsteps));
     const int64_t c = std::max(1, cus);
     int64_t best = 1;
     double best_cost = 1e300;
@@ -440,6 +449,13 @@ static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus) {
 // Tile of the exact passes: v2, 1 x 2 blocks per wave (the low-register
 // tile; FP32 scores have one tile, v0 = 1 x 1).
 static int exact_variant(const rkr_index *x) { return x->sk == SK_F32 ? 0 : 2; }
+
+// Users per workgroup of an exact pass (the pipelined pass for BF16 scores,
+// else the count kernel's tile); it sets the item splits of a launch.
+static int exact_tasks_per_wg(const rkr_index *x, int xv) {
+    if (x->sk == SK_BF16 && xv == 2) return pass_tasks_per_wg();
+    return WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+}
 
 // An environment switch that is on when set to "1" (read once).
 static bool env_flag(const char *name) {
@@ -463,6 +479,9 @@ static CountArgs count_args(rkr_index *x, const PairSet &ps, TaskSet &ts, int va
     a.m = x->m;
     a.nks = x->nks;
     a.step_coef = x->coef_step[nib == 1 ? 0 : (nib == 2 ? 1 : 2)].as<double>();
+    a.step_coef_half = x->coef_step[0].as<double>();
+    a.step_coef32 = x->coef32_step[1].as<float>();
+    a.step_coef32_half = x->coef32_step[0].as<float>();
     a.pexp = x->pexp.as<int8_t>();
     a.ulp = x->ulp.as<uint8_t>();
     a.dpad = x->dpad;
@@ -518,11 +537,11 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
     hipError_t e = build_tasks(pids, N, ps, x->recheck ? 0 : 1, nullptr, ts, x->sc, st, nullptr, 1);
     if (e != hipSuccess) return fail_hip(e, "build_tasks (exact)");
     const int xv = exact_variant(x);
-    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+    const int tpw = exact_tasks_per_wg(x, xv);
     const int64_t gx = (ts.ntask + tpw - 1) / tpw;
     CountArgs a = count_args(x, ps, ts, xv);
     const int64_t nsteps = a.nsteps;
-    int64_t nsplit = pick_nsplit(gx, nsteps, x->num_cus);
+    int64_t nsplit = pick_nsplit(gx, nsteps, x->num_cus, kMaxExactSplits);
     HIPCK(ts.reserve_entries(ts.cap_total, (int)nsplit));
     a.ent_cnt = ts.ent_cnt;
     a.steps_per_split = (nsteps + nsplit - 1) / nsplit;
@@ -943,7 +962,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         static const int kPhaseEnd32[] = {3, 6, 9, 12, 16, 20, 32};   // in 32nds of the scan
         HIPCK(ensure_events(x));
         TaskSet *cur = &x->ts_screen, *nxt = &x->ts_screen2;
-        const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
+        const int tpw = single ? pass_tasks_per_wg() : WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
         const int64_t nsteps = count_args(x, ps, *cur, variant).nsteps;
         int64_t s0 = 0;
         double ms_kernel = 0.0;
@@ -1155,7 +1174,7 @@ static rkr_status capture_ranks_graph(rkr_index *x) {
     const int64_t n = x->n;
     const int mes = x->mk == MK_BF16 ? 2 : 4;
     const int xv = exact_variant(x);
-    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+    const int tpw = exact_tasks_per_wg(x, xv);
     const int64_t ntask_pad = (n + 511) / 512 * 512;
     g.emit_cap = std::max<int64_t>(1 << 20, 2 * x->stats.uncertain + 65536);
     if (!g.cs) HIPCK(hipStreamCreateWithFlags(&g.cs, hipStreamNonBlocking));
@@ -1355,7 +1374,7 @@ extern "C" rkr_status rkr_ranks_noalloc(rkr_index *x, const void *q, int32_t *ra
     x->stats.queries = 1;
     x->stats.pairs = n;
     const int xv = exact_variant(x);
-    const int tpw = WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
+    const int tpw = exact_tasks_per_wg(x, xv);
     // first chunk: every user, or as many as leave half of the array to records
     const size_t per_task_max = 36 + 4 * 16;   // entry lists with up to 16 item splits
     int64_t chunk = std::min<int64_t>(n, (int64_t)((kNoAllocBytes - fixed) / 2 / per_task_max));

@@ -47,25 +47,31 @@ namespace {
 #ifndef EX_PIPE
 #define EX_PIPE 4
 #endif
-constexpr int EX_NIB = 2;          // item blocks of 32 per step: 64 items
 constexpr int EX_LDS = 153600;     // LDS for the item stages and the record buffers
 
-template <int NKS>
+// A pass shape: NIB item blocks of 32 per step (64 or 32 items), NW waves per
+// workgroup (32 users each), B32: the band of a step computed in FP32 from
+// coefficients rounded up, instead of FP64.
+template <int NKS, int NIB, int NW, bool B32>
 struct ExactGeom {
     static constexpr int FB = frag_fb(SK_BF16);
-    static constexpr int STEP_BYTES = EX_NIB * NKS * 64 * FB;
+    static constexpr int STEP_BYTES = NIB * NKS * 64 * FB;
     static constexpr int STAGE = STEP_BYTES + 32;   // item tile + the step's four error-bound coefficients
-    static constexpr int REC_BYTES = WAVES_PER_WG * REC_PER_WAVE * 8;
+    static constexpr int COEF_LANES = B32 ? 1 : 2;  // 16-byte copies of the coefficients
+    static constexpr int REC_BYTES = NW * REC_PER_WAVE * 8;
     static constexpr int NBUF_FIT = (EX_LDS - REC_BYTES) / STAGE;
-    static constexpr int NBUF = NBUF_FIT > 5 ? 5 : NBUF_FIT;
+    static constexpr int NBUF_MAX = NIB == 1 ? 9 : 5;
+    static constexpr int NBUF = NBUF_FIT > NBUF_MAX ? NBUF_MAX : NBUF_FIT;
     static_assert(NBUF >= 3, "the pipeline needs three LDS stages");
     // barrier period and staging distance: D >= SP + 1 (steps st0 + 1 .. st0
     // + SP are staged before the barrier at st0) and D <= NBUF - SP + 1 (the
     // stage step st + D overwrites was last read before the previous barrier)
-    static constexpr int SP = NBUF >= 5 ? 2 : 1;
+    static constexpr int SP = NBUF >= 9 ? 4 : (NBUF >= 5 ? 2 : 1);
     static constexpr int D = NBUF - SP + 1;
-    static constexpr int LOADS = (STEP_BYTES + 8191) / 8192;
+    static_assert(D >= SP + 1, "staging distance");
+    static constexpr int LOADS = (STEP_BYTES + NW * 1024 - 1) / (NW * 1024);
     static constexpr int LDS_BYTES = NBUF * STAGE;   // dynamic LDS (the record buffers are a static array)
+    static constexpr int SR = 2 / NIB;               // kernel steps per 64-item step of the host's ranges
 };
 
 // One item step (STEP_BYTES, then the step's 32 bytes of error-bound
@@ -81,7 +87,7 @@ struct ExactGeom {
 // barrier after every read of a stage before it is refilled).  Waits the
 // compiler inserts for its own memory operations stay correct: it can only
 // under-count the operations issued after them, which makes a wait stricter.
-template <int STEP_BYTES, int LOADS>
+template <int STEP_BYTES, int LOADS, int NW, int COEF_LANES>
 struct StageCopy {
     uint32_t voff[LOADS];   // this lane's byte offsets in the step (loop invariant)
     uint32_t lds_off[LOADS + 1];   // the wave's LDS offsets in a stage, then the coefficients'
@@ -90,7 +96,7 @@ struct StageCopy {
         nload = 0;
 #pragma unroll
         for (int j = 0; j < LOADS; ++j) {
-            const int wbase = (j * 512 + wave * 64) * 16;
+            const int wbase = (j * NW * 64 + wave * 64) * 16;
             voff[j] = (uint32_t)(wbase + lane * 16);
             lds_off[j] = (uint32_t)wbase;
             nload += wbase < STEP_BYTES ? 1 : 0;
@@ -111,13 +117,14 @@ struct StageCopy {
                      : "memory");
     }
     // copy step src (and its coefficients) into the stage at LDS offset stage_off
-    __device__ void operator()(const uint8_t *src, uint32_t stage_off, int wave, int lane, const double *coef) const {
+    __device__ void operator()(const uint8_t *src, uint32_t stage_off, int wave, int lane, const void *coef) const {
         const i32x4 rp = rsrc(src, STEP_BYTES);
 #pragma unroll
         for (int j = 0; j < LOADS; ++j)
             if ((int)lds_off[j] < STEP_BYTES) copy16(rp, __builtin_amdgcn_readfirstlane(stage_off + lds_off[j]), voff[j]);
-        if (wave == 0 && lane < 2)
-            copy16(rsrc(coef, 32), __builtin_amdgcn_readfirstlane(stage_off + lds_off[LOADS]), (uint32_t)(lane * 16));
+        if (wave == 0 && lane < COEF_LANES)
+            copy16(rsrc(coef, COEF_LANES * 16), __builtin_amdgcn_readfirstlane(stage_off + lds_off[LOADS]),
+                   (uint32_t)(lane * 16));
     }
 };
 
@@ -152,14 +159,13 @@ __device__ inline void wait_vm_n(int n) {
     }
 }
 
-template <int NKS, bool SCREEN>
+template <int NKS, bool SCREEN, int NIB, int NW, bool B32>
 __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const int split, uint8_t *lds, int2 *recs,
                                  int *wg_live, uint64_t &ncmp, uint64_t &nslot, uint64_t &nstep, uint64_t &nscored) {
-    using G = ExactGeom<NKS>;
+    using G = ExactGeom<NKS, NIB, NW, B32>;
     using FT = typename FragT<SK_BF16>::T;
-    constexpr int NIB = EX_NIB;
     constexpr int FB = G::FB, STEP_BYTES = G::STEP_BYTES, STAGE = G::STAGE, NBUF = G::NBUF;
-    constexpr int SP = G::SP, D = G::D, LOADS = G::LOADS;
+    constexpr int SP = G::SP, D = G::D, LOADS = G::LOADS, SR = G::SR;
     constexpr int KS = frag_ks(SK_BF16), ES = elem_size(SK_BF16);
     constexpr int NSC = NIB * 16;    // scores per lane per step
 
@@ -169,11 +175,20 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);   // the same, known to be uniform
     const int l32 = lane & 31;
     const int half = lane >> 5;
-    const int64_t s_begin = a.step0 + (int64_t)split * a.steps_per_split;
-    const int64_t s_end = std::min<int64_t>(s_begin + a.steps_per_split, a.step_end);
+    // the host's ranges are in 64-item steps; this pass's steps hold NIB * 32 items
+    const int64_t r_begin = a.step0 + (int64_t)split * a.steps_per_split;
+    const int64_t s_begin = r_begin * SR;
+    const int64_t s_end = std::min<int64_t>(std::min<int64_t>(r_begin + a.steps_per_split, a.step_end) * SR,
+                                            (a.m + NIB * 32 - 1) / (NIB * 32));
+    // the step's error-bound coefficients (FP64, or FP32 rounded up)
+    const void *coef_base = B32 ? (const void *)(NIB == 1 ? a.step_coef32_half : a.step_coef32)
+                                : (const void *)(NIB == 1 ? a.step_coef_half : a.step_coef);
+    auto coef_of = [&](int64_t st) -> const void * {
+        return (const uint8_t *)coef_base + st * (B32 ? 16 : 32);
+    };
 
     // ---- the lane's user: register-stationary fragments, norms, its pair
-    const int64_t t = tile * (WAVES_PER_WG * USER_BLOCK) + wave * USER_BLOCK + l32;
+    const int64_t t = tile * (NW * USER_BLOCK) + wave * USER_BLOCK + l32;
     const int u = t < a.ntask ? a.task_user[t] : -1;
     bool live = u >= 0 && a.ent_len[split * a.len_stride + t] > 0;
     double un_hat = 0.0, un_del = 0.0, un_full = 0.0;
@@ -199,7 +214,8 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // rem turns negative), and its lists are the split's own copy.
     int pid = 0, rem = 0;
     float th = 0.0f, tl = 0.0f, tm = 0.0f;
-    const int64_t e_pair = a.blk_base[t >> 5] + l32 + (SCREEN ? (int64_t)split * a.cap_total : 0);
+    // (a tile may reach past the padded task list: its entries are never read)
+    const int64_t e_pair = (t < a.ntask ? a.blk_base[t >> 5] : 0) + l32 + (SCREEN ? (int64_t)split * a.cap_total : 0);
     if (live) {
         pid = a.ent_pid[e_pair];
         th = a.ent_th[e_pair];
@@ -221,6 +237,13 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     const double th_term = gam1 * fabs((double)tf);
     const double bracket = (double)th - (double)tl;
     const double inflate = 1.0 + 1.0 / (double)a.dpad;
+    // the FP32 form of the band: every input rounded up; each of the five
+    // FP32 operations on these non-negative values loses at most a relative
+    // 2^-24 (plus 2^-150 if the result is subnormal), so a final factor 1 +
+    // 2^-20 and an added 2^-126 keep it above the FP64 value
+    const float uh32 = f32_round_up(un_hat), ud32 = f32_round_up(un_del), uf32 = f32_round_up(un_full);
+    const float infl32 = f32_round_up(inflate), tt32 = f32_round_up(th_term);
+    const float br32 = f32_round_up(bracket);
     // plain verdict of a near tie: score > tm, i.e. acc > tm - th (exact)
     const float pd = tm - th;
     uint32_t cnt = 0;   // per-lane certain count of the pair
@@ -234,6 +257,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // after the first copies are issued, so that its loads overlap them.)
     int64_t s_set = INT64_MAX;
     bool set_above = false;
+    auto znorm = [&](int64_t st) { return a.step_znorm[st / SR]; };
     auto find_settle = [&]() {
         // (screening passes stop on their budgets; they do not settle)
         if constexpr (SCREEN) return;
@@ -243,11 +267,11 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         if (!(L > 0.0)) return;
         const double nu = un_full * (1.0 + 0x1p-30);
         // the range's smallest bound first: most pairs never settle in it
-        if (!(nu * a.step_znorm[s_end - 1] < L)) return;
+        if (!(nu * znorm(s_end - 1) < L)) return;
         int64_t lo = s_begin, hi = s_end - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
-            if (nu * a.step_znorm[mid] < L) hi = mid; else lo = mid + 1;
+            if (nu * znorm(mid) < L) hi = mid; else lo = mid + 1;
         }
         s_set = lo;
         set_above = th < 0.0f;
@@ -298,9 +322,25 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         ehi = f32_round_up(E * (1.0 + 1e-9));
         elo = f32_round_up((E + bracket) * (1.0 + 1e-9));
     };
+    auto band_of32 = [&](float ca, float cb, float cc, float cabs, float &ehi, float &elo) {
+        if (a.plain) {
+            ehi = 0.0f;
+            elo = -__builtin_inff();
+            return;
+        }
+        const float e = __builtin_fmaf(__builtin_fmaf(uh32, ca, __builtin_fmaf(ud32, cb, __builtin_fmaf(uf32, cc, cabs))),
+                                       infl32, tt32);
+        ehi = __builtin_fmaf(e, 1.0f + 0x1p-20f, 0x1p-126f);
+        elo = __builtin_fmaf(e + br32, 1.0f + 0x1p-20f, 0x1p-126f);
+    };
     auto band_of_tile = [&](const uint8_t *tile, float &ehi, float &elo) {
-        const double *cs = (const double *)(tile + STEP_BYTES);
-        band_of(cs[0], cs[1], cs[2], cs[3], ehi, elo);
+        if constexpr (B32) {
+            const float *cs = (const float *)(tile + STEP_BYTES);
+            band_of32(cs[0], cs[1], cs[2], cs[3], ehi, elo);
+        } else {
+            const double *cs = (const double *)(tile + STEP_BYTES);
+            band_of(cs[0], cs[1], cs[2], cs[3], ehi, elo);
+        }
     };
     // item of score r of block ib in this lane, for a step starting at item0
     auto item_of = [&](int64_t item0, int ib, int r) -> int64_t {
@@ -423,14 +463,13 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     };
 
     // ---- prologue: stage steps s_begin .. s_begin + D - 1; the first lands
-    const StageCopy<STEP_BYTES, LOADS> stage(wave_u, lane);
+    const StageCopy<STEP_BYTES, LOADS, NW, G::COEF_LANES> stage(wave_u, lane);
     const int nload = stage.nload;
     // the LDS offset of the stages (M0 takes LDS offsets, not generic addresses)
     const uint32_t lds_base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)lds;
     const int64_t npro = std::min<int64_t>(D, s_end - s_begin);
     for (int64_t k = 0; k < npro; ++k)
-        stage(a.plp + (s_begin + k) * (int64_t)STEP_BYTES, lds_base + k * STAGE, wave_u, lane,
-              a.step_coef + 4 * (s_begin + k));
+        stage(a.plp + (s_begin + k) * (int64_t)STEP_BYTES, lds_base + k * STAGE, wave_u, lane, coef_of(s_begin + k));
     // before the barrier at step st0: steps up to st0 + SP have landed; the
     // copies of later steps (staged up to step st0 - 1 + D) may be in flight
     find_settle();
@@ -489,8 +528,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // used): the block then has no branch, and the compare stays in it.
     auto body = [&](f32x16 *cur, f32x16 *nxt, int64_t st) {
         if (st + D < s_run)
-            stage(a.plp + (st + D) * (int64_t)STEP_BYTES, lds_base + slot_stg * STAGE, wave_u, lane,
-                  a.step_coef + 4 * (st + D));
+            stage(a.plp + (st + D) * (int64_t)STEP_BYTES, lds_base + slot_stg * STAGE, wave_u, lane, coef_of(st + D));
         const int64_t item0 = st * (NIB * 32);
         const uint8_t *tn = lds + slot_nxt * STAGE;
         uint32_t c;
@@ -498,8 +536,9 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         // inside the block: the next step's band (coefficients read first,
         // used half way)
         constexpr int NRD = NKS * NIB;
-        const double *csp = (const double *)(tn + STEP_BYTES);
-        double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;
+        using CT = typename std::conditional<B32, float, double>::type;
+        const CT *csp = (const CT *)(tn + STEP_BYTES);
+        CT cs0 = 0, cs1 = 0, cs2 = 0, cs3 = 0;
         float ehi_n = 0.0f, elo_n = 0.0f;
         score_and_count(tn, nxt, cur, ehi, c, dmin, [&](int i) {
             if (i == 0) {
@@ -508,7 +547,12 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
                 cs2 = csp[2];
                 cs3 = csp[3];
             }
-            if (i == NRD / 2) band_of(cs0, cs1, cs2, cs3, ehi_n, elo_n);
+            if (i == NRD / 2) {
+                if constexpr (B32)
+                    band_of32(cs0, cs1, cs2, cs3, ehi_n, elo_n);
+                else
+                    band_of(cs0, cs1, cs2, cs3, ehi_n, elo_n);
+            }
         });
         if constexpr (SCREEN) {
             // the budget left after this step's certainly-above items
@@ -537,7 +581,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             if (SP == 1 && !barrier_before(st)) break;
             body(accB, accA, st);
             if (++st >= s_run) break;
-            if (!barrier_before(st)) break;
+            if ((SP == 2 || ((st - s_begin) & (SP - 1)) == 0) && !barrier_before(st)) break;
         }
     // the pass scored steps s_begin .. stop - 1; a workgroup that stops
     // early may still have copies in flight into its LDS: they land before
@@ -569,10 +613,10 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     if (live && half == 0) atomicAdd(&a.cnt_out[pid], tot);
 }
 
-template <int NKS, bool SCREEN>
-__global__ __launch_bounds__(512) void k_pass(CountArgs a) {
+template <int NKS, bool SCREEN, int NIB, int NW, bool B32>
+__global__ __launch_bounds__(NW * 64) void k_pass(CountArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    __shared__ int2 recs[SCREEN ? 1 : WAVES_PER_WG * REC_PER_WAVE];
+    __shared__ int2 recs[SCREEN ? 1 : NW * REC_PER_WAVE];
     __shared__ int wg_live[3];
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 3) wg_live[threadIdx.x] = 0;   // read after the tile's first barrier
@@ -581,7 +625,7 @@ __global__ __launch_bounds__(512) void k_pass(CountArgs a) {
     // consecutive tiles of one split (shared items in its L2) measured slower
     const int split = (int)blockIdx.y;
     const int64_t tile = blockIdx.x;
-    pass_tile<NKS, SCREEN>(a, tile, split, lds, recs, wg_live, ncmp, nslot, nstep, nscored);
+    pass_tile<NKS, SCREEN, NIB, NW, B32>(a, tile, split, lds, recs, wg_live, ncmp, nslot, nstep, nscored);
     uint64_t tot = ncmp, tslot = nslot;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -593,40 +637,64 @@ __global__ __launch_bounds__(512) void k_pass(CountArgs a) {
         atomicAdd(a.stat + 2, (unsigned long long)tslot);
         atomicAdd(a.stat + 6, (unsigned long long)nscored);
     }
-    // executed matrix-core flop: 8 x 32 users by 64 items over the padded dimension per step
+    // executed matrix-core flop: NW x 32 users by NIB x 32 items over the padded dimension per step
     // (a tile runs one score block more than it has steps: the prologue's)
-    constexpr unsigned long long FLOP_PER_STEP = 2ull * WAVES_PER_WG * USER_BLOCK * EX_NIB * 32 * NKS * frag_ks(SK_BF16);
+    constexpr unsigned long long FLOP_PER_STEP = 2ull * NW * USER_BLOCK * NIB * 32 * NKS * frag_ks(SK_BF16);
     if (threadIdx.x == 0 && a.stat && nstep) atomicAdd(a.stat + 4, (unsigned long long)(nstep + 1) * FLOP_PER_STEP);
 }
 
-template <int NKS, bool SCREEN>
+template <int NKS, bool SCREEN, int NIB, int NW, bool B32>
 hipError_t launch_pass_nks(const CountArgs &a, int nsplit, hipStream_t st) {
-    using G = ExactGeom<NKS>;
+    using G = ExactGeom<NKS, NIB, NW, B32>;
     if (a.nks != NKS) return hipErrorInvalidValue;
-    constexpr int TASKS_PER_WG = WAVES_PER_WG * USER_BLOCK;
+    constexpr int TASKS_PER_WG = NW * USER_BLOCK;
     const int64_t ntiles = (a.ntask + TASKS_PER_WG - 1) / TASKS_PER_WG;
     if (ntiles == 0) return hipSuccess;
     CountArgs b = a;
     b.ntiles = ntiles;
     b.tile_counter = nullptr;
-    auto kern = k_pass<NKS, SCREEN>;
+    auto kern = k_pass<NKS, SCREEN, NIB, NW, B32>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, G::LDS_BYTES);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)ntiles, (unsigned)nsplit), dim3(512), G::LDS_BYTES, st, b);
+    hipLaunchKernelGGL(kern, dim3((unsigned)ntiles, (unsigned)nsplit), dim3(NW * 64), G::LDS_BYTES, st, b);
     return hipGetLastError();
+}
+
+// The pass shape: 0 = 64-item steps, 8 waves, FP64 band; 1 = the same with
+// the FP32 band; 2 = 32-item steps, 12 waves (three per SIMD), FP32 band.
+// RKR_PASS_SHAPE overrides the default (for measurements).
+int pass_shape() {
+    static const int s = [] {
+        const char *v = getenv("RKR_PASS_SHAPE");
+        const int k = v ? atoi(v) : 2;
+        return k >= 0 && k <= 2 ? k : 2;
+    }();
+    return s;
+}
+
+template <bool SCREEN, int NIB, int NW, bool B32>
+hipError_t launch_pass_shape(const CountArgs &a, int nsplit, hipStream_t st) {
+    const int nks = a.nks;
+    if (nks <= 4) return launch_pass_nks<4, SCREEN, NIB, NW, B32>(a, nsplit, st);
+    if (nks <= 8) return launch_pass_nks<8, SCREEN, NIB, NW, B32>(a, nsplit, st);
+    if (nks <= 13) return launch_pass_nks<13, SCREEN, NIB, NW, B32>(a, nsplit, st);
+    if (nks <= 20) return launch_pass_nks<20, SCREEN, NIB, NW, B32>(a, nsplit, st);
+    return hipErrorInvalidValue;
 }
 
 template <bool SCREEN>
 hipError_t launch_pass(const CountArgs &a, int nsplit, hipStream_t st) {
-    const int nks = a.nks;
-    if (nks <= 4) return launch_pass_nks<4, SCREEN>(a, nsplit, st);
-    if (nks <= 8) return launch_pass_nks<8, SCREEN>(a, nsplit, st);
-    if (nks <= 13) return launch_pass_nks<13, SCREEN>(a, nsplit, st);
-    if (nks <= 20) return launch_pass_nks<20, SCREEN>(a, nsplit, st);
-    return hipErrorInvalidValue;
+    switch (pass_shape()) {
+    case 1: return launch_pass_shape<SCREEN, 2, 8, true>(a, nsplit, st);
+    case 0: return launch_pass_shape<SCREEN, 2, 8, false>(a, nsplit, st);
+    default: return launch_pass_shape<SCREEN, 1, 12, true>(a, nsplit, st);
+    }
 }
 
 }  // namespace
+
+// Tasks per workgroup of the pipelined passes (users per tile).
+int pass_tasks_per_wg() { return (pass_shape() == 2 ? 12 : 8) * USER_BLOCK; }
 
 // Exact pass with BF16 scores (item steps of 64, one workgroup of 8 waves per
 // 256 tasks and item split); the layouts are padded to nks k-steps, and every

@@ -69,6 +69,9 @@ struct CountArgs {
     int64_t m;
     int nks;                      // k-steps per vector
     const double *step_coef;      // [nsteps][4]: a, b, c, abs   (error-bound coefficients)
+    const double *step_coef_half; // the same per 32-item block (pipelined passes with 32-item steps)
+    const float *step_coef32;     // pipelined passes: step_coef rounded up to FP32, per 64 items
+    const float *step_coef32_half;//   and per 32 items
     const int8_t *pexp;           // FP8: per-item power-of-two scale exponent (sorted order)
     // users, low precision, row-major [n][dpad]
     const uint8_t *ulp;
@@ -142,6 +145,8 @@ hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int va
 // the software-pipelined exact pass for BF16 scores (exact.hip); its tasks
 // hold one pair each
 hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st);
+// tasks per workgroup of the pipelined passes (their tile of users)
+int pass_tasks_per_wg();
 // the same kernel as a screening pass, one pair per task
 hipError_t launch_screen1_bf16(const CountArgs &a, int nsplit, hipStream_t st);
 
