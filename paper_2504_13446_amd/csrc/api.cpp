@@ -190,7 +190,9 @@ struct rkr_index {
     int ptab_tau = 0;
     bool has_ptab = false;
     int64_t emit_cap = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // events: 0..3 an exact pass and its recheck; 4..9 the stage boundaries of
+    // a batch; 10..23 its screening phases
+    hipEvent_t ev[24] = {};
     rkr_query_opts qo{};
     rkr_query_stats stats{};
     Tuner tuner;
@@ -414,7 +416,10 @@ static hipError_t ensure_events(rkr_index *x) {
 // Elapsed milliseconds between two recorded events (after a stream sync).
 static double event_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();   // a timing left out is no error of the call
+        return 0.0;
+    }
     return (double)ms;
 }
 static std::string tune_key(const rkr_index *x, int nq, int64_t npairs) {
@@ -424,20 +429,25 @@ static std::string tune_key(const rkr_index *x, int nq, int64_t npairs) {
     return b;
 }
 
-// Splits of the item range for an exact pass over gx user tiles (one
-// workgroup per CU): the count in 1..max_split that minimises rounds x split length,
-// ceil(gx * ns / cus) / ns (smallest such count on ties).
-// an exact pass's splits share nothing but the count they add to: few user
-// tiles (the refine of a batch's survivors) spread over more of them
+// An exact pass's splits share nothing but the count they add to: few user
+// tiles (the refine of a batch's survivors) spread over more of them.
 static constexpr int64_t kMaxExactSplits = 64;
+
+// Splits of the item range for a pass over gx user tiles (one workgroup per
+// CU): the count in 1..max_split that minimises rounds x (split length + a
+// workgroup's fixed cost), ceil(gx * ns / cus) * (nsteps / ns + overhead)
+// (smallest such count on ties).
 
 static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus, int64_t max_split = 16) {
     const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(max_split, nsteps));
     const int64_t c = std::max(1, cus);
     int64_t best = 1;
     double best_cost = 1e300;
+    // a workgroup's fixed cost (staging ahead, the first barrier, the final
+    // flush) is worth about kSplitOverhead steps of its range
+    constexpr double kSplitOverhead = 24.0;
     for (int64_t ns = 1; ns <= maxs; ++ns) {
-        const double cost = (double)((gx * ns + c - 1) / c) / (double)ns;
+        const double cost = (double)((gx * ns + c - 1) / c) * ((double)nsteps / (double)ns + kSplitOverhead);
         if (cost < best_cost - 1e-12) {
             best_cost = cost;
             best = ns;
@@ -550,37 +560,46 @@ static rkr_status exact_count(rkr_index *x, const PairSet &ps, const int32_t *pi
         x->emit_cap = 1 << 22;
         HIPCK(x->emit.ensure((size_t)x->emit_cap * 8));
     }
+    unsigned long long *ctr = x->ctr.as<unsigned long long>();
     for (int attempt = 0; attempt < 4; ++attempt) {
         a.emit = x->emit.as<int2>();
         a.emit_cap = (unsigned long long)x->emit_cap;
+        // the work counters as they were, for a retry (slots 8..15)
+        HIPCK(hipMemcpyAsync(ctr + 8, ctr, 64, hipMemcpyDeviceToDevice, st));
         HIPCK(q_zero_at(pids, N, x->cnt.as<uint32_t>(), st));
         HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 2, st));   // emit counter (64-bit)
         HIPCK(hipEventRecord(x->ev[0], st));
         HIPCK(launch_count(x->sk, CM_EXACT, a, (int)nsplit, xv, st));
         HIPCK(hipEventRecord(x->ev[1], st));
+        // users with several tasks were scored once per task: count their
+        // (user, item) scores once in the algorithmic-work counter
+        if (ts.d_nusers)
+            HIPCK(q_scored_fix(ctr + 7, ts.ntask, ts.d_nusers, x->m, st));
+        // the recheck reads the record count on the device (at most the
+        // buffer's size); one read-back then tells whether the buffer held them all
+        HIPCK(hipEventRecord(x->ev[2], st));
+        HIPCK(launch_recheck_dev(x->emit.as<int2>(), ctr, (int64_t)x->emit_cap, ps.pair_u, ps.t64, x->Um.p, x->Pm.p,
+                                 x->d, x->mk, x->cnt.as<uint32_t>(), ctr + 2, st));
+        HIPCK(hipEventRecord(x->ev[3], st));
         unsigned long long ne = 0;
-        HIPCK(hipMemcpyAsync(&ne, x->ctr.p, 8, hipMemcpyDeviceToHost, st));
+        HIPCK(hipMemcpyAsync(&ne, ctr, 8, hipMemcpyDeviceToHost, st));
         HIPCK(hipStreamSynchronize(st));
         x->stats.ms_exact_kernel += event_ms(x->ev[0], x->ev[1]);
         if (ne <= (unsigned long long)x->emit_cap) {
-            if (ts.ntask > ts.nusers) {
-                // users with several tasks were scored once per task: count
-                // their (user, item) scores once in the algorithmic-work counter
+            if (!ts.d_nusers && ts.ntask > ts.nusers) {
                 unsigned long long scored = 0;
-                HIPCK(hipMemcpyAsync(&scored, x->ctr.as<unsigned long long>() + 7, 8, hipMemcpyDeviceToHost, st));
+                HIPCK(hipMemcpyAsync(&scored, ctr + 7, 8, hipMemcpyDeviceToHost, st));
                 HIPCK(hipStreamSynchronize(st));
                 scored -= (unsigned long long)(ts.ntask - ts.nusers) * (unsigned long long)x->m;
-                HIPCK(hipMemcpyAsync(x->ctr.as<unsigned long long>() + 7, &scored, 8, hipMemcpyHostToDevice, st));
+                HIPCK(hipMemcpyAsync(ctr + 7, &scored, 8, hipMemcpyHostToDevice, st));
             }
             x->stats.uncertain += (int64_t)ne;
-            HIPCK(hipEventRecord(x->ev[2], st));
-            HIPCK(launch_recheck(x->emit.as<int2>(), (int64_t)ne, ps.pair_u, ps.t64, x->Um.p, x->Pm.p, x->d, x->mk,
-                                 x->cnt.as<uint32_t>(), x->ctr.as<unsigned long long>() + 2, st));
-            HIPCK(hipEventRecord(x->ev[3], st));
-            HIPCK(hipStreamSynchronize(st));
             x->stats.ms_recheck_kernel += event_ms(x->ev[2], x->ev[3]);
             return RKR_OK;
         }
+        // the buffer overflowed: the counts are incomplete; the counters go
+        // back to where they were and the pass runs again
+        HIPCK(hipMemcpyAsync(ctr + 1, ctr + 9, 56, hipMemcpyDeviceToDevice, st));
         x->stats.emit_retries += 1;
         const int64_t max_emit = max_emit_records(x);
         if ((int64_t)ne + (int64_t)(ne / 4) > max_emit && N > 1) {
@@ -773,6 +792,11 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     x->stats.queries = nq;
     x->sc.reset();
     const int d = x->d;
+    // stage boundaries as events (read once, at the end): thresholds, seeds,
+    // screen, refine, answer
+    HIPCK(ensure_events(x));
+    hipEvent_t *sev = x->ev + 4, *pev = x->ev + 10;
+    HIPCK(hipEventRecord(sev[0], st));
     // query values
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(Qm, (int64_t)nq * d, x->mk, x->flags.as<int>(), st));
@@ -825,8 +849,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         if (flags & 1) return fail(RKR_E_INVALID, "a query holds a non-finite value");
         if (flags & 2) return fail(RKR_E_INVALID, "a query holds a value with magnitude above 2^50");
     }
-    const double t1 = now_ms();
-    x->stats.ms_thresh = t1 - t0;
+    HIPCK(hipEventRecord(sev[1], st));
 
     // ---- 3. seeds
     std::vector<int64_t> seloff(nq + 1, 0), bestoff(nq + 1, 0);
@@ -883,23 +906,23 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(q_mark_selected(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->seedflag.as<uint8_t>(), st));
     HIPCK(x->seedpid.ensure(nsel * 4));
     HIPCK(x->allpid.ensure(npairs * 4));
-    int64_t nseed = 0;
     // seeds (counted exactly below) and the other pairs (the ones to screen;
-    // with a rank table the filter lists them instead)
-    HIPCK(q_split_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), &nseed,
+    // with a rank table the filter lists them instead); every query selects
+    // S[q] distinct pairs of its own, so there are nsel seeds
+    const int64_t nseed = nsel;
+    HIPCK(q_split_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), nullptr,
                         table_on ? nullptr : x->allpid.as<int32_t>(), st, x->sc));
     x->stats.seed_pairs = nseed;
     // ---- 4. exact count of the seeds
     HIPCK(x->cnt.ensure(npairs * 4));
-    HIPCK(x->ctr.ensure(64));
-    HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 16, st));
+    HIPCK(x->ctr.ensure(256));
+    HIPCK(launch_fill_u32(x->ctr.as<uint32_t>(), 0, 64, st));
+    unsigned long long *ctr_d = x->ctr.as<unsigned long long>();
     rkr_status rs = exact_count(x, ps, x->seedpid.as<int32_t>(), nseed);
     if (rs != RKR_OK) return rs;
     x->stats.ms_seed_kernel = x->stats.ms_exact_kernel;
-    unsigned long long scored_after_seed = 0;
-    HIPCK(hipMemcpyAsync(&scored_after_seed, x->ctr.as<unsigned long long>() + 7, 8, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    x->stats.scored_seed = (int64_t)scored_after_seed;
+    // the work counter after the seeds (slot 16), read with the others at the end
+    HIPCK(hipMemcpyAsync(ctr_d + 16, ctr_d + 7, 8, hipMemcpyDeviceToDevice, st));
     // ---- 5. per-query bound
     HIPCK(q_rank_keys_sel(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->cnt.as<uint32_t>(),
                           x->selrank.as<uint64_t>(), st));
@@ -909,9 +932,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(x->seedkth.ensure(nq * 4));
     HIPCK(q_bounds(x->best.as<uint64_t>(), x->bestoff.as<int64_t>(), x->kdev.as<int32_t>(),
                    c ? x->cdev.as<double>() : nullptr, nq, x->bound.as<int32_t>(), x->seedkth.as<int32_t>(), st));
-    HIPCK(hipStreamSynchronize(st));
-    const double t2 = now_ms();
-    x->stats.ms_seed = t2 - t1;
+    HIPCK(hipEventRecord(sev[2], st));
 
     // ---- 6. screen every pair against its bound
     bool need_screen = false;
@@ -965,6 +986,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         const int tpw = single ? pass_tasks_per_wg() : WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
         const int64_t nsteps = count_args(x, ps, *cur, variant).nsteps;
         int64_t s0 = 0;
+        bool ph_timed[sizeof kPhaseEnd32 / sizeof kPhaseEnd32[0]] = {};
         double ms_kernel = 0.0;
         x->stats.screen_ctas = 0;
         for (int ph = 0; ph < (int)(sizeof kPhaseEnd32 / sizeof kPhaseEnd32[0]) && s0 < nsteps; ++ph) {
@@ -1011,21 +1033,38 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
                 a.tile_counter = x->ctr.as<unsigned long long>() + 4;
                 a.persistent_ctas = x->num_cus;
             }
-            HIPCK(hipEventRecord(x->ev[0], st));
+            HIPCK(hipEventRecord(pev[2 * ph], st));
             if (single)
                 HIPCK(launch_screen1_bf16(a, (int)nsplit, st));
             else
                 HIPCK(launch_count(x->sk, CM_SCREEN, a, (int)nsplit, variant, st));
-            HIPCK(hipEventRecord(x->ev[1], st));
+            HIPCK(hipEventRecord(pev[2 * ph + 1], st));
+            ph_timed[ph] = true;
             if (nsplit > 1)
                 HIPCK(q_screen_merge(*cur, (int)nsplit, x->sp_len.as<int32_t>(), x->sp_pid.as<int32_t>(),
                                      x->sp_cnt.as<uint32_t>(), st));
-            HIPCK(hipStreamSynchronize(st));
-            ms_kernel += event_ms(x->ev[0], x->ev[1]);
             x->stats.screen_ctas = std::max<int64_t>(x->stats.screen_ctas,
                                                      pers_phase ? std::min<int64_t>(x->num_cus, tiles) : tiles * nsplit);
             s0 = s1;
             if (s0 >= nsteps) break;
+            if (single) {
+                // one pair per task: compact after every phase (one read-back,
+                // the count of live pairs), budgets at cnt[pid]
+                TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
+                int64_t npl = 0;
+                HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &npl, x->sc, st,
+                                  x->cnt.as<uint32_t>()));
+                if (npl == 0) {                          // every screened pair is dead
+                    cur->ntask = 0;
+                    break;
+                }
+                e = build_tasks(x->surv.as<int32_t>(), npl, ps, x->recheck ? 0 : 1, x->bound.as<int32_t>(), *nxt,
+                                x->sc, st, x->cnt.as<uint32_t>(), max_len);
+                if (e != hipSuccess) return fail_hip(e, "build_tasks (screen compaction)");
+                std::swap(cur, nxt);
+                continue;
+            }
+            HIPCK(hipStreamSynchronize(st));
             int64_t nlive = 0;
             HIPCK(q_count_live(cur->len, cur->ntask, x->ctr.as<unsigned long long>() + 6, &nlive, st));
             if (nlive == 0) break;                       // every screened pair is dead
@@ -1040,64 +1079,63 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
             if (e != hipSuccess) return fail_hip(e, "build_tasks (screen compaction)");
             std::swap(cur, nxt);
         }
+        TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
+        HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
+        // (q_survivors read its count back: every phase has ended)
+        for (int ph = 0; ph < (int)(sizeof ph_timed / sizeof ph_timed[0]); ++ph)
+            if (ph_timed[ph]) ms_kernel += event_ms(pev[2 * ph], pev[2 * ph + 1]);
         x->stats.ms_screen_kernel = ms_kernel;
         if (!single) x->tuner.record(key, cand, ms_kernel, 2 * ntv);
         x->stats.screen_variant = single ? -1 : cand;
-        TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
-        HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
     }
-    unsigned long long scored_before_refine = 0;
-    HIPCK(hipMemcpyAsync(&scored_before_refine, x->ctr.as<unsigned long long>() + 7, 8, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    const double t3 = now_ms();
-    x->stats.ms_screen = t3 - t2;
+    // the work counter before the refine (slot 17)
+    HIPCK(hipMemcpyAsync(ctr_d + 17, ctr_d + 7, 8, hipMemcpyDeviceToDevice, st));
+    HIPCK(hipEventRecord(sev[3], st));
     x->stats.survivors = nsurv;
     // ---- 7. refine the survivors
     rs = exact_count(x, ps, x->surv.as<int32_t>(), nsurv);
     if (rs != RKR_OK) return rs;
     x->stats.refined_pairs = nsurv;
-    HIPCK(hipStreamSynchronize(st));
-    const double t4 = now_ms();
-    x->stats.ms_refine = t4 - t3;
+    HIPCK(hipEventRecord(sev[4], st));
 
-    // ---- 8. answer: k best (rank, id) among seeds and survivors
-    std::vector<int32_t> hq(nq, 0);
+    // ---- 8. answer: k best (rank, id) among seeds and survivors; the
+    // candidate lists per query (its seeds, then its survivors) are laid out
+    // on the device
     HIPCK(x->qcount.ensure(nq * 4));
     HIPCK(launch_fill_u32(x->qcount.as<uint32_t>(), 0, nq, st));
     HIPCK(q_count_by_query(x->surv.as<int32_t>(), nsurv, ps.pair_q, x->qcount.as<int32_t>(), st));
-    HIPCK(hipMemcpyAsync(hq.data(), x->qcount.p, nq * 4, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    std::vector<int64_t> candoff(nq + 1, 0);
-    for (int q = 0; q < nq; ++q) candoff[q + 1] = candoff[q] + S[q] + hq[q];
     HIPCK(x->candoff.ensure((nq + 1) * 8));
     HIPCK(x->cursor.ensure(nq * 4));
-    HIPCK(x->candkeys.ensure(candoff[nq] * 8));
+    HIPCK(x->candkeys.ensure((nsel + nsurv) * 8));
     HIPCK(x->ans.ensure(ksum * 8));
-    HIPCK(hipMemcpyAsync(x->candoff.p, candoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
-    HIPCK(hipMemcpyAsync(x->cursor.p, Sv.data(), nq * 4, hipMemcpyHostToDevice, st));
+    HIPCK(q_cand_offsets(x->qcount.as<int32_t>(), x->sdev.as<int32_t>(), nq, x->candoff.as<int64_t>(), x->sc, st));
+    HIPCK(hipMemcpyAsync(x->cursor.p, x->sdev.p, nq * 4, hipMemcpyDeviceToDevice, st));
     HIPCK(q_cand_keys(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->surv.as<int32_t>(), nsurv,
                       ps.pair_u, ps.pair_q, x->cnt.as<uint32_t>(), x->candoff.as<int64_t>(), x->cursor.as<int32_t>(),
                       x->candkeys.as<uint64_t>(), st));
     HIPCK(launch_select(x->candkeys.as<uint64_t>(), x->candoff.as<int64_t>(), x->kdev.as<int32_t>(), nq,
                         x->bestoff.as<int64_t>(), x->ans.as<uint64_t>(), st));
     HIPCK(q_write_answer(x->ans.as<uint64_t>(), ksum, ids_out, ranks_out, st));
-    unsigned long long ctr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, 64, hipMemcpyDeviceToHost, st));
+    HIPCK(hipEventRecord(sev[5], st));
+    // one read-back of the counters and the survivors per query
+    unsigned long long ctr[32] = {};
+    std::vector<int32_t> hq(nq, 0);
+    HIPCK(hipMemcpyAsync(ctr, x->ctr.p, sizeof ctr, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(hq.data(), x->qcount.p, nq * 4, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     x->stats.compares = (int64_t)ctr[1];
     x->stats.flips = (int64_t)ctr[2];
+    x->stats.compare_slots = (int64_t)ctr[3];
     x->stats.mfma_flop = (int64_t)ctr[5];
     x->stats.scored_pairs = (int64_t)ctr[7];
-    x->stats.scored_exact = (int64_t)scored_after_seed + (int64_t)(ctr[7] - scored_before_refine);
-    {
-        unsigned long long slots = 0;
-        HIPCK(hipMemcpyAsync(&slots, x->ctr.as<unsigned long long>() + 3, 8, hipMemcpyDeviceToHost, st));
-        HIPCK(hipStreamSynchronize(st));
-        x->stats.compare_slots = (int64_t)slots;
-    }
-    const double t5 = now_ms();
-    x->stats.ms_select = t5 - t4;
-    x->stats.ms_total = t5 - t0;
+    x->stats.scored_seed = (int64_t)ctr[16];
+    x->stats.scored_exact = (int64_t)ctr[16] + (int64_t)(ctr[7] - ctr[17]);
+    x->stats.ms_thresh = event_ms(sev[0], sev[1]);
+    x->stats.ms_seed = event_ms(sev[1], sev[2]);
+    x->stats.ms_screen = event_ms(sev[2], sev[3]);
+    x->stats.ms_refine = event_ms(sev[3], sev[4]);
+    x->stats.ms_select = event_ms(sev[4], sev[5]);
+    x->stats.ms_total = now_ms() - t0;
     if (c) {
         int64_t settled = 0;
         for (int q = 0; q < nq; ++q) settled += (hq[q] == 0);
@@ -1139,7 +1177,7 @@ static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     HIPCK(x->t64.ensure(n * 8));
     HIPCK(x->cnt.ensure(n * 4));
     HIPCK(x->allpid.ensure(n * 4));
-    HIPCK(x->ctr.ensure(64));
+    HIPCK(x->ctr.ensure(256));
     ps.pair_u = x->pair_u.as<int32_t>();
     ps.pair_q = x->pair_q.as<int32_t>();
     ps.t64 = x->t64.as<double>();
@@ -1694,7 +1732,7 @@ extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_
     HIPCK(x->pair_q.ensure(npairs * 4));
     HIPCK(x->t64.ensure(npairs * 8));
     HIPCK(x->cnt.ensure(npairs * 4));
-    HIPCK(x->ctr.ensure(64));
+    HIPCK(x->ctr.ensure(256));
     ps.pair_u = x->pair_u.as<int32_t>();
     ps.pair_q = x->pair_q.as<int32_t>();
     ps.t64 = x->t64.as<double>();

@@ -34,7 +34,14 @@
 //    at step st; at a barrier before step st0, the stages of steps up to
 //    st0 + SP have landed (each wave waits until at most the copies of later
 //    steps are in flight), and a stage is overwritten only after a barrier
-//    has followed every read of it.  SP = 2, D = 4 with five stages.
+//    has followed every read of it.
+//  * Shape.  A step holds 32 items (one MFMA block) and a workgroup 12 waves
+//    of 32 users: at about 160 VGPRs three waves share a SIMD, so a wave
+//    waiting on LDS or the barrier leaves two to feed the matrix core (the
+//    64-item, 8-wave shape needs 229 VGPRs: two waves per SIMD).  Nine
+//    stages of 13 KB, SP = 4, D = 6.  The band of a step is computed in FP32
+//    from per-step coefficients rounded up to FP32 (five FMAs instead of a
+//    dozen FP64 operations and two conversions); see band_of32.
 #include "rkr_internal.h"
 #include "tile_common.h"
 

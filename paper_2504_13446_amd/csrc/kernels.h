@@ -61,6 +61,7 @@ struct PairSet {
 struct TaskSet {
     int64_t ntask = 0, ntask_pad = 0, cap_total = 0;
     int64_t nusers = 0;   // distinct users of the tasks (a user may hold several tasks)
+    const int64_t *d_nusers = nullptr;   // single-pair task sets: the same count, left on the device
     DBuf b_user, b_len, b_base, b_pid, b_q, b_cnt, b_th, b_tl, b_tm;
     int32_t *task_user = nullptr, *len = nullptr;
     int64_t *blk_base = nullptr;

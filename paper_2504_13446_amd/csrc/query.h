@@ -52,6 +52,11 @@ hipError_t q_screen_merge(TaskSet &ts, int ns, const int32_t *sp_len, const int3
                           const uint32_t *sp_rem, hipStream_t st);
 // number of tasks whose list is not empty
 hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, int64_t *count, hipStream_t st);
+// *scored -= (ntask - *nusers) * m, on the device
+hipError_t q_scored_fix(unsigned long long *scored, int64_t ntask, const int64_t *nusers, int64_t m, hipStream_t st);
+// cand_off[0..nq] = exclusive scan of qcount[q] + seeds[q]
+hipError_t q_cand_offsets(const int32_t *qcount, const int32_t *seeds, int nq, int64_t *cand_off, Scratch &sc,
+                          hipStream_t st);
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
                             hipStream_t st);
 hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t nsel,

@@ -610,7 +610,7 @@ hipError_t q_mark_selected(const QView &v, const uint64_t *sel, const int64_t *s
 static hipError_t flag_compact(const uint8_t *flag, int64_t N, int32_t *out1, int64_t *count1, int32_t *out0,
                                Scratch &sc, hipStream_t st) {
     if (N <= 0) {
-        *count1 = 0;
+        if (count1) *count1 = 0;
         return hipSuccess;
     }
     const int64_t nb = (N + FC_CHUNK - 1) / FC_CHUNK;
@@ -624,6 +624,7 @@ static hipError_t flag_compact(const uint8_t *flag, int64_t N, int32_t *out1, in
     hipLaunchKernelGGL(k_flag_scatter, dim3((unsigned)nb), dim3(FC_BS), 0, st, flag, N, (const int64_t *)offs, out1,
                        out0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!count1) return hipSuccess;   // the caller knows the count
     if ((e = hipMemcpyAsync(count1, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }
@@ -748,6 +749,27 @@ hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, 
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     *count = (int64_t)c;
     return hipSuccess;
+}
+// *scored -= (ntask - *nusers) * m: a user with several tasks was scored
+// once per task; the algorithmic-work counter counts its scores once
+__global__ void k_scored_fix(unsigned long long *scored, int64_t ntask, const int64_t *nusers, int64_t m) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *scored -= (unsigned long long)(ntask - *nusers) * (unsigned long long)m;
+}
+hipError_t q_scored_fix(unsigned long long *scored, int64_t ntask, const int64_t *nusers, int64_t m, hipStream_t st) {
+    hipLaunchKernelGGL(k_scored_fix, dim3(1), dim3(64), 0, st, scored, ntask, nusers, m);
+    return hipGetLastError();
+}
+// candidate counts per query (its seeds and its survivors) -> offsets
+__global__ void k_cand_sizes(const int32_t *qcount, const int32_t *seeds, int nq, int32_t *sizes) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) sizes[q] = qcount[q] + seeds[q];
+}
+hipError_t q_cand_offsets(const int32_t *qcount, const int32_t *seeds, int nq, int64_t *cand_off, Scratch &sc,
+                          hipStream_t st) {
+    int32_t *sizes = (int32_t *)sc.take((int64_t)nq * 4);
+    if (!sizes) return hipErrorOutOfMemory;
+    LAUNCH1D(k_cand_sizes, (int64_t)nq, qcount, seeds, nq, sizes);
+    return scan_i32(sizes, nq, cand_off, cand_off + nq, sc, st);
 }
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
                             hipStream_t st) {

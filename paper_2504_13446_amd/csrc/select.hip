@@ -341,6 +341,20 @@ __global__ void k_task_permute(const int64_t *start_in, const int32_t *user_in, 
     len_out[pos] = len_in[t];
 }
 
+// Tasks of one pair each: task t holds pair t of the list; blocks of 32
+// tasks have one entry slot per task, empty blocks none.
+__global__ void k_single_tasks(const int32_t *pids, int64_t N, const int32_t *pair_u, int64_t ntask_pad, int64_t nblk,
+                               int64_t nb_used, int64_t *task_start, int32_t *task_user, int32_t *len,
+                               int64_t *blk_base) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntask_pad) {
+        task_user[t] = t < N ? pair_u[pids[t]] : -1;
+        len[t] = t < N ? 1 : 0;
+    }
+    if (t <= N) task_start[t] = t;
+    if (t <= nblk) blk_base[t] = 32 * (t < nb_used ? t : nb_used);
+}
+
 __global__ void k_block_cap(const int32_t *len, int64_t nblk, int64_t *cap32) {
     int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblk) return;
@@ -431,6 +445,7 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     ts.ntask_pad = 0;
     ts.cap_total = 0;
     ts.nusers = 0;
+    ts.d_nusers = nullptr;
     if (N <= 0) return hipSuccess;
     hipError_t e;
     int32_t *flag = (int32_t *)sc.take(N * 4);
@@ -439,6 +454,33 @@ hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int pl
     if (!flag || !excl || !dtot) return hipErrorOutOfMemory;
     hipLaunchKernelGGL(k_user_change, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, ps.pair_u, flag);
     if ((e = scan_i32(flag, N, excl, dtot, sc, st)) != hipSuccess) return e;
+    if (max_len == 1) {
+        // every pair is a task of its own: the sizes follow from N, so the
+        // lists are laid out with nothing read back (the distinct-user count
+        // stays on the device)
+        const int64_t ntask = N, ntask_pad = (N + 511) / 512 * 512, nblk = ntask_pad / 32;
+        const int64_t nb_used = (N + 31) / 32, cap_total = nb_used * 32;
+        if ((e = ts.reserve(ntask_pad, nblk)) != hipSuccess) return e;
+        int64_t *task_start = (int64_t *)sc.take((ntask + 1) * 8);
+        if (!task_start) return hipErrorOutOfMemory;
+        hipLaunchKernelGGL(k_single_tasks, dim3(nblocks(ntask_pad + 1, 256)), dim3(256), 0, st, pids, N, ps.pair_u,
+                           ntask_pad, nblk, nb_used, task_start, ts.task_user, ts.len, ts.blk_base);
+        if ((e = ts.reserve_entries(cap_total)) != hipSuccess) return e;
+        if (bound)
+            hipLaunchKernelGGL(k_fill_entries<true>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
+                               ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.t64, plain, bound,
+                               rem_init, ts.ent_pid, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+        else
+            hipLaunchKernelGGL(k_fill_entries<false>, dim3((unsigned)nblk), dim3(256), 0, st, pids, task_start, ts.len,
+                               ntask, ts.blk_base, nblk, cap_total, ps.pair_q, ps.t64, plain, bound,
+                               rem_init, ts.ent_pid, ts.ent_cnt, ts.ent_th, ts.ent_tl, ts.ent_tm);
+        ts.ntask = ntask;
+        ts.ntask_pad = ntask_pad;
+        ts.cap_total = cap_total;
+        ts.nusers = -1;
+        ts.d_nusers = dtot;
+        return hipGetLastError();
+    }
     int64_t ntask = 0;
     if ((e = hipMemcpyAsync(&ntask, dtot, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
