@@ -36,6 +36,11 @@ Printed (one JSON line on stdout):
   single_all_ranks  secondary: exact ranks of all 100k users for one query on
                 the single-query workload (graph replays), BF16 + recheck and
                 plain FP32
+  uneven, learned  the other batched workloads, each run as a child process
+                with its own line embedded: 500k x 1M x 300 with 1,024 uneven
+                candidate lists (c = 1.5 and exact), and 1M x 1M x 200 with
+                1,024 queries and the rank estimator trained on 10M triples
+                (c = 1.5 and exact, with and without the estimator)
 Progress goes to stderr.
 """
 from __future__ import annotations
@@ -127,6 +132,9 @@ def main() -> int:
     ap.add_argument("--no-table-compare", action="store_true",
                     help="skip timing the same batch with the rank table switched off")
     ap.add_argument("--cpu-users", type=int, default=0, help="users in the CPU sample (0: auto)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the uneven-list and learned-estimator workloads (run as child processes of "
+                         "the batch bench)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scale for HBM counters)")
     args = ap.parse_args()
@@ -289,6 +297,7 @@ def main() -> int:
     if train_info is not None:
         out["estimator"] = learned_line(idx, run, w, train_info, cvec, rk_np, off, ms_step)
 
+    exact_ans = (ids_np, rk_np, off)
     if mode == "approx":
         # the same workload answered exactly: its time, and the Sec. 5 quality
         # of the approximate answers against it (the returned ranks are exact
@@ -300,6 +309,7 @@ def main() -> int:
         torch.cuda.synchronize()
         ms_e = (time.perf_counter() - t) * 1e3
         se = idx.stats()
+        exact_ans = (ids_e.cpu().numpy(), rk_e.cpu().numpy(), off_e)
         out["exact_same_workload"] = {"ms_per_step": round(ms_e, 2), "queries_per_s": round(nq / (ms_e / 1e3), 2),
                                       "near_ties_rechecked": int(se["uncertain"]),
                                       "recheck_fraction_of_compares": round(se["uncertain"] / max(se["compares"], 1), 6)}
@@ -389,11 +399,38 @@ def main() -> int:
         idx32.close()
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, ids_np, rk_np, off, args.cpu_users)
+        # the sample is checked against the exact answers (in approximate
+        # mode, those of the exact leg)
+        out["cpu_baseline"] = cpu_baseline(w, *exact_ans, args.cpu_users)
     idx.close()
+    if not args.no_secondary and w.name == "batch":
+        out["uneven"] = secondary("uneven", ["--score", "bf16", "--steps", "2", "--warmup", "1"])
+        out["learned"] = secondary("learned", ["--steps", "2", "--warmup", "1"])
     print(json.dumps(out))
     sys.stdout.flush()
     return 0
+
+
+def secondary(workload: str, extra: list) -> dict:
+    """Another workload of the batched path, run as a child process of this
+    one (its own line, embedded): the uneven candidate lists (500k x 1M x
+    300, c = 1.5, BF16 scores) or the learned estimator (1M x 1M x 200,
+    1,024 queries, trained on 10M triples, c = 1.5)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", workload, "--no-cpu", "--no-fp32", "--no-single",
+           "--no-table-compare", "--no-secondary", *extra]
+    log("secondary workload: %s" % " ".join(cmd[2:]))
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    if r.returncode != 0:
+        return {"error": "exit status %d" % r.returncode}
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    keep = ("value", "unit", "ms_per_step", "dtype", "config", "build_ms", "breakdown_ms", "approx_quality",
+            "exact_same_workload", "estimator", "roofline")
+    res = {k: line[k] for k in keep if k in line}
+    res["counters"] = {k: line["counters"][k] for k in ("pairs", "seed_pairs", "survivors", "uncertain", "flips",
+                                                        "table_pruned", "scored_pairs")}
+    res["roofline"] = {k: res["roofline"][k] for k in ("frac", "achieved", "unit", "seed_pass")}
+    return res
 
 
 def learned_line(idx, run, w, train_info, cvec, rk_main, off_main, ms_main) -> dict:

@@ -164,6 +164,7 @@ struct rkr_index {
     int64_t n = 0, m = 0;
     int d = 0, dpad = 0, nks = 0, mk = 0, sk = 0, recheck = 1;
     int split = 0;                    // 1: split BF16 scores (sk is SK_BF16, rows of 3d terms)
+    double g32 = 0.0, g64 = 0.0;      // the error bound's FP32 (matrix-core sums) and FP64 factors
     int64_t nblk32 = 0, nblk = 0;     // item blocks of 32 (real, allocated: a multiple of 4)
     int num_cus = 256;
     int dev = 0;                      // device the index was built on
@@ -172,6 +173,7 @@ struct rkr_index {
     DBuf Um, Pm, perm, ulp, plp, unorm3, pnorm3, uexp, pexp, coef;
     DBuf coef_step[3];    // per-step coefficient maxima for steps of 1, 2, 4 blocks
     DBuf coef32_step[2];  // the same for steps of 1 and 2 blocks, rounded up to FP32
+    DBuf tup, qlp, qnorm3, qxyz;   // bounded FP32 thresholds of a dense batch and the queries' BF16 copies
     DBuf step_znorm;      // per 64-item step: an upper bound of |p| from that step on
     // per-call buffers
     Scratch sc;
@@ -306,6 +308,8 @@ extern "C" rkr_status rkr_build(const void *U, int64_t n, const void *P, int64_t
         const double u64 = ldexp(1.0, -53);
         const double g64 = d * u64 / (1.0 - d * u64) * 1.01;
         const double eabs = dpad * ldexp(1.0, -100);
+        x->g32 = g32;
+        x->g64 = g64;
         HIPCK(launch_block_coef(x->pnorm3.as<double>(), m, x->nblk, g32, g64, cz, eabs, x->coef.as<double>(), st));
         for (int k = 0; k < 3; ++k) {
             const int nib = 1 << k;
@@ -355,7 +359,7 @@ extern "C" void rkr_destroy(rkr_index *x) {
     (void)hipStreamSynchronize(x->st);
     DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt, &x->ptab_fmin, &x->ptab_step, &x->ptab_cells,
                     &x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
-                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->coef32_step[0], &x->coef32_step[1], &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
+                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->coef32_step[0], &x->coef32_step[1], &x->tup, &x->qlp, &x->qnorm3, &x->qxyz, &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
                     &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
                     &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
@@ -463,7 +467,7 @@ static int exact_variant(const rkr_index *x) { return x->sk == SK_F32 ? 0 : 2; }
 // Users per workgroup of an exact pass (the pipelined pass for BF16 scores,
 // else the count kernel's tile); it sets the item splits of a launch.
 static int exact_tasks_per_wg(const rkr_index *x, int xv) {
-    if (x->sk == SK_BF16 && xv == 2) return pass_tasks_per_wg();
+    if (x->sk == SK_BF16 && xv == 2) return pass_tasks_per_wg(x->nks);
     return WAVES_PER_WG * nub_of(x->sk, x->nks, xv) * USER_BLOCK;
 }
 
@@ -837,7 +841,25 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(x->keys.ensure(npairs * 8));
     ps.t64 = x->t64.as<double>();
     const bool keys_fused = dense && x->qo.use_estimator == 0;
-    if (dense)
+    // Dense batches filtered by the rank table: every pair needs its
+    // threshold only for the filter and the seed order, so those get bounded
+    // FP32 values from the matrix cores (t_up >= the FP64 threshold); the FP64
+    // thresholds are computed for the pairs that are counted (seeds, then the
+    // pairs the filter keeps).
+    const bool approx_t = keys_fused && x->has_table && !x->qo.no_table && x->sk == SK_BF16 && !x->split &&
+                          !env_flag("RKR_FP64_THRESHOLDS");
+    if (approx_t) {
+        HIPCK(x->qlp.ensure((size_t)nq * x->dpad * 2));
+        HIPCK(x->qnorm3.ensure((size_t)nq * 3 * 8));
+        HIPCK(x->qxyz.ensure((size_t)nq * 16));
+        HIPCK(x->tup.ensure(npairs * 4));
+        HIPCK(launch_lowprec(Qm, nq, d, x->mk, SK_BF16, x->dpad, 0, 0, x->qlp.as<uint8_t>(), x->qnorm3.as<double>(),
+                             nullptr, st));
+        HIPCK(launch_query_xyz(x->qnorm3.as<double>(), nq, x->g32, x->g64, x->qxyz.as<float4>(), st));
+        HIPCK(launch_thresh_approx(x->ulp.as<uint8_t>(), n, x->dpad, x->nks, x->unorm3.as<double>(),
+                                   x->qlp.as<uint8_t>(), nq, x->qxyz.as<float4>(), x->tup.as<float>(),
+                                   x->keys.as<uint64_t>(), x->num_cus, st));
+    } else if (dense)
         HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st, keys_fused ? x->unorm3.as<double>() : nullptr,
                                   keys_fused ? x->keys.as<uint64_t>() : nullptr));
     else
@@ -912,6 +934,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     const int64_t nseed = nsel;
     HIPCK(q_split_flags(x->seedflag.as<uint8_t>(), npairs, x->seedpid.as<int32_t>(), nullptr,
                         table_on ? nullptr : x->allpid.as<int32_t>(), st, x->sc));
+    if (approx_t)
+        HIPCK(launch_thresh_list(x->seedpid.as<int32_t>(), nseed, ps.pair_u, ps.pair_q, x->Um.p, Qm, d, x->mk, ps.t64,
+                                 st));
     x->stats.seed_pairs = nseed;
     // ---- 4. exact count of the seeds
     HIPCK(x->cnt.ensure(npairs * 4));
@@ -946,9 +971,13 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         // the rank table rules out pairs the screen would drop (Lemma 1 (2))
         HIPCK(x->keep.ensure(npairs));
         HIPCK(q_table_keep(ps, x->seedflag.as<uint8_t>(), x->bound.as<int32_t>(), x->tab_t.as<double>(),
-                           x->tab_cnt.as<uint32_t>(), x->keep.as<uint8_t>(), st));
+                           x->tab_cnt.as<uint32_t>(), x->keep.as<uint8_t>(), st,
+                           approx_t ? x->tup.as<float>() : nullptr));
         int64_t nk = 0;
         HIPCK(q_compact_flags(x->keep.as<uint8_t>(), npairs, x->allpid.as<int32_t>(), &nk, x->sc, st));
+        if (approx_t)
+            HIPCK(launch_thresh_list(x->allpid.as<int32_t>(), nk, ps.pair_u, ps.pair_q, x->Um.p, Qm, d, x->mk, ps.t64,
+                                     st));
         x->stats.table_pruned = nscreen - nk;
         nscreen = nk;
     }
@@ -983,7 +1012,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         static const int kPhaseEnd32[] = {3, 6, 9, 12, 16, 20, 32};   // in 32nds of the scan
         HIPCK(ensure_events(x));
         TaskSet *cur = &x->ts_screen, *nxt = &x->ts_screen2;
-        const int tpw = single ? pass_tasks_per_wg() : WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
+        const int tpw = single ? pass_tasks_per_wg(x->nks) : WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
         const int64_t nsteps = count_args(x, ps, *cur, variant).nsteps;
         int64_t s0 = 0;
         bool ph_timed[sizeof kPhaseEnd32 / sizeof kPhaseEnd32[0]] = {};

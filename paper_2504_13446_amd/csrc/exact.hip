@@ -669,14 +669,16 @@ hipError_t launch_pass_nks(const CountArgs &a, int nsplit, hipStream_t st) {
 
 // The pass shape: 0 = 64-item steps, 8 waves, FP64 band; 1 = the same with
 // the FP32 band; 2 = 32-item steps, 12 waves (three per SIMD), FP32 band.
-// RKR_PASS_SHAPE overrides the default (for measurements).
-int pass_shape() {
-    static const int s = [] {
+// Shape 2 up to 13 k-steps (d <= 208 in BF16); with 20 its registers would
+// spill, so shape 1.  RKR_PASS_SHAPE overrides the choice (for measurements).
+int pass_shape(int nks) {
+    static const int forced = [] {
         const char *v = getenv("RKR_PASS_SHAPE");
-        const int k = v ? atoi(v) : 2;
-        return k >= 0 && k <= 2 ? k : 2;
+        const int k = v ? atoi(v) : -1;
+        return k >= 0 && k <= 2 ? k : -1;
     }();
-    return s;
+    if (forced >= 0) return forced;
+    return nks <= 13 ? 2 : 1;
 }
 
 template <bool SCREEN, int NIB, int NW, bool B32>
@@ -691,7 +693,7 @@ hipError_t launch_pass_shape(const CountArgs &a, int nsplit, hipStream_t st) {
 
 template <bool SCREEN>
 hipError_t launch_pass(const CountArgs &a, int nsplit, hipStream_t st) {
-    switch (pass_shape()) {
+    switch (pass_shape(a.nks)) {
     case 1: return launch_pass_shape<SCREEN, 2, 8, true>(a, nsplit, st);
     case 0: return launch_pass_shape<SCREEN, 2, 8, false>(a, nsplit, st);
     default: return launch_pass_shape<SCREEN, 1, 12, true>(a, nsplit, st);
@@ -701,7 +703,7 @@ hipError_t launch_pass(const CountArgs &a, int nsplit, hipStream_t st) {
 }  // namespace
 
 // Tasks per workgroup of the pipelined passes (users per tile).
-int pass_tasks_per_wg() { return (pass_shape() == 2 ? 12 : 8) * USER_BLOCK; }
+int pass_tasks_per_wg(int nks) { return (pass_shape(nks) == 2 ? 12 : 8) * USER_BLOCK; }
 
 // Exact pass with BF16 scores (item steps of 64, one workgroup of 8 waves per
 // 256 tasks and item split); the layouts are padded to nks k-steps, and every

@@ -120,6 +120,16 @@ hipError_t launch_step_znorm(const double *pn, const int32_t *order, int64_t m, 
                              hipStream_t st);
 hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t nsteps, double *out,
                             hipStream_t st);
+// Bounded FP32 thresholds of a dense batch from the BF16 copies (t_up >= the
+// FP64 threshold, user-major [u * nq + q]) and the default seed keys
+// (query-major), for the rank-table filter; qxyz from launch_query_xyz.
+hipError_t launch_query_xyz(const double *qnorm3, int nq, double g32, double g64, float4 *out, hipStream_t st);
+hipError_t launch_thresh_approx(const uint8_t *ulp, int64_t n, int dpad, int nks, const double *unorm3,
+                                const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up, uint64_t *keys,
+                                int num_cus, hipStream_t st);
+// FP64 thresholds t64[p] of the listed pairs p = pids[0..N)
+hipError_t launch_thresh_list(const int32_t *pids, int64_t N, const int32_t *pair_u, const int32_t *pair_q,
+                              const void *Um, const void *Qm, int d, int mk, double *t64, hipStream_t st);
 hipError_t launch_thresh(const int32_t *pair_u, const int32_t *pair_q, int64_t npairs, const void *Um,
                          const void *Qm, int d, int mk, double *t64, hipStream_t st);
 // with keys (and unorm3), also the default seed keys, query-major [nq][n]

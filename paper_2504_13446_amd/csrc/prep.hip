@@ -2,6 +2,7 @@
 // error-bound coefficients), FP64 thresholds and the FP64 near-tie recheck.
 #include "rkr_internal.h"
 #include "kernels.h"
+#include "tile_common.h"
 
 namespace rkr {
 
@@ -492,6 +493,107 @@ __global__ void k_recheck_dev(const int2 *rec, const unsigned long long *count, 
 }
 
 // ---------------------------------------------------------------------------
+// Bounded thresholds of a dense batch, for the rank-table filter and the seed
+// order (the FP64 thresholds are then computed only for the pairs that are
+// counted).  t^ = u^.q^ on the matrix cores (BF16 copies, products exact,
+// FP32 sums); its distance to the FP64 threshold s64(u, q) is at most
+//   gamma32 |u^||q^| + |du||q^| + |u^||dq| + |du||dq| + gamma64 |u||q|
+//   = a_u X_q + b_u Y_q + c_u Z_q
+// with a = |x^|, b = |x - x^|, c = |x| and X_q = gamma32 a_q + b_q, Y_q =
+// a_q + b_q, Z_q = gamma64 c_q, all rounded up (the same terms as the error
+// bound of the scores, with q in place of p).  Out: t_up >= t^ + that bound
+// (FP32, rounded up; user-major [u * nq + q]) and the default seed keys
+// (query-major [q * n + u]) from -t^ / |u|.
+// ---------------------------------------------------------------------------
+__global__ void k_query_xyz(const double *qnorm3, int nq, double g32, double g64, float4 *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const double a = qnorm3[3 * q], b = qnorm3[3 * q + 1], c = qnorm3[3 * q + 2];
+    const double sl = 1.0 + 0x1p-40;   // the FP64 products' own rounding
+    out[q] = make_float4(f32_round_up((g32 * a + b) * sl), f32_round_up((a + b) * sl), f32_round_up(g64 * c * sl),
+                         0.0f);
+}
+
+// One workgroup of 8 waves per query tile of 256 and a stride of 32-user
+// blocks; wave w holds queries 32w .. 32w + 31 of the tile as register-
+// stationary A operands, the block's users are the B operands (one
+// 32x32x16 MFMA per k-step).  A lane's outputs are one user (its column) and
+// 16 queries (rows): keys go out along the users (256 contiguous bytes per
+// query row); t_up goes through LDS so that each user's row of queries is
+// written contiguously.
+template <int NKS>
+__global__ __launch_bounds__(512) void k_thresh_approx(const uint8_t *ulp, int64_t n, int dpad, const double *unorm3,
+                                                       const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up,
+                                                       uint64_t *keys) {
+    using FT = typename FragT<SK_BF16>::T;
+    constexpr int KS = 16;
+    __shared__ float4 sq[256];
+    __shared__ float stile[32][257];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l32 = lane & 31, half = lane >> 5;
+    const int q0 = blockIdx.y * 256;
+    const int nqt = min(256, nq - q0);
+    FT afr[NKS];
+    {
+        const int q = q0 + wave * 32 + l32;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            FT v{};
+            if (q < nq) v = *(const FT *)(qlp + ((int64_t)q * dpad + s * KS + half * 8) * 2);
+            afr[s] = v;
+        }
+    }
+    if (threadIdx.x < 256) sq[threadIdx.x] = threadIdx.x < nqt ? qxyz[q0 + threadIdx.x] : make_float4(0, 0, 0, 0);
+    __syncthreads();
+    const int64_t nblk = (n + 31) / 32;
+    for (int64_t bk = blockIdx.x; bk < nblk; bk += gridDim.x) {
+        const int64_t ub = bk * 32;
+        const int64_t u = ub + l32;
+        f32x16 acc{};
+        const uint8_t *urow = ulp + ((u < n ? u : 0) * dpad + half * 8) * 2;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            FT bf{};
+            if (u < n) bf = *(const FT *)(urow + s * KS * 2);
+            acc = mfma_step<SK_BF16>(acc, afr[s], bf, 127, 127);
+        }
+        float au = 0.0f, bu = 0.0f, cu = 0.0f, inv = 0.0f;
+        if (u < n) {
+            au = f32_round_up(unorm3[3 * u]);
+            bu = f32_round_up(unorm3[3 * u + 1]);
+            cu = f32_round_up(unorm3[3 * u + 2]);
+            const double nu = unorm3[3 * u + 2];
+            inv = nu > 0.0 ? (float)(1.0 / nu) : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int ql = wave * 32 + 8 * (r >> 2) + 4 * half + (r & 3);   // query within the tile
+            const float4 z = sq[ql];
+            const float th = acc[r];
+            const float dd = __builtin_fmaf(au, z.x, __builtin_fmaf(bu, z.y, cu * z.z));
+            const float sm = th + __builtin_fmaf(dd, 0x1p-20f, dd);
+            stile[l32][ql] = sm + __builtin_fmaf(__builtin_fabsf(sm), 0x1p-22f, 0x1p-126f);
+            if (u < n && ql < nqt)
+                keys[(int64_t)(q0 + ql) * n + u] = ((uint64_t)f32_order_key(-th * inv) << 32) | (uint32_t)u;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 32 * 256; idx += 512) {
+            const int i = idx >> 8, j = idx & 255;
+            if (j < nqt && ub + i < n) t_up[(ub + i) * nq + q0 + j] = stile[i][j];
+        }
+        __syncthreads();
+    }
+}
+
+// FP64 thresholds of the listed pairs only (sequential fma, as in k_thresh).
+__global__ void k_thresh_list(const int32_t *pids, int64_t N, const int32_t *pair_u, const int32_t *pair_q,
+                              const void *Um, const void *Qm, int d, int mk, double *t64) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t p = pids[i];
+    t64[p] = spec_dot_rows(Um, pair_u[p], Qm, pair_q[p], d, mk);
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -606,6 +708,36 @@ hipError_t launch_recheck(const int2 *rec, int64_t nrec, const int32_t *pair_u, 
     if (nrec <= 0) return hipSuccess;
     const unsigned nb = nblocks(std::min<int64_t>(nrec, (int64_t)65536 * 256), 256);
     hipLaunchKernelGGL(k_recheck, dim3(nb), dim3(256), 0, st, rec, nrec, pair_u, t64, Um, Pm, d, mk, cnt, flips);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_xyz(const double *qnorm3, int nq, double g32, double g64, float4 *out, hipStream_t st) {
+    if (nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_query_xyz, dim3(nblocks(nq, 256)), dim3(256), 0, st, qnorm3, nq, g32, g64, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_thresh_approx(const uint8_t *ulp, int64_t n, int dpad, int nks, const double *unorm3,
+                                const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up, uint64_t *keys,
+                                int num_cus, hipStream_t st) {
+    if (n <= 0 || nq <= 0) return hipSuccess;
+    const int64_t nblk = (n + 31) / 32;
+    const dim3 g((unsigned)std::min<int64_t>(nblk, (int64_t)num_cus * 4), (unsigned)((nq + 255) / 256));
+    switch (nks) {
+    case 4: hipLaunchKernelGGL(k_thresh_approx<4>, g, dim3(512), 0, st, ulp, n, dpad, unorm3, qlp, nq, qxyz, t_up, keys); break;
+    case 8: hipLaunchKernelGGL(k_thresh_approx<8>, g, dim3(512), 0, st, ulp, n, dpad, unorm3, qlp, nq, qxyz, t_up, keys); break;
+    case 13: hipLaunchKernelGGL(k_thresh_approx<13>, g, dim3(512), 0, st, ulp, n, dpad, unorm3, qlp, nq, qxyz, t_up, keys); break;
+    case 20: hipLaunchKernelGGL(k_thresh_approx<20>, g, dim3(512), 0, st, ulp, n, dpad, unorm3, qlp, nq, qxyz, t_up, keys); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_thresh_list(const int32_t *pids, int64_t N, const int32_t *pair_u, const int32_t *pair_q,
+                              const void *Um, const void *Qm, int d, int mk, double *t64, hipStream_t st) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_thresh_list, dim3(nblocks(N, 256)), dim3(256), 0, st, pids, N, pair_u, pair_q, Um, Qm, d, mk,
+                       t64);
     return hipGetLastError();
 }
 

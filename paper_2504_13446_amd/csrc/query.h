@@ -72,7 +72,8 @@ hipError_t q_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
 // keep[pid] = 1 for the non-seed pairs the rank table cannot rule out
 // (tab_t, tab_cnt: [n][TABLE_COLS] thresholds and certain counts)
 hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
-                        const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st);
+                        const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st,
+                        const float *t_up = nullptr);
 hipError_t q_round_up_f32(const double *x, int64_t n, float *out, hipStream_t st);
 // the paper's table query (Sec. 4.3) for a dense batch of nq queries (pairs
 // u * nq + q; keys query-major): brackets and estimates, each query's R_lo_k,

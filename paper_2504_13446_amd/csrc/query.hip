@@ -383,7 +383,7 @@ __global__ void k_table_keep(int64_t npairs, int nq, const int32_t *pair_u, cons
 // the users' rows of thresholds and counts go through LDS; the number of
 // columns with t_{u,j} >= t is counted directly.
 constexpr int TK_USERS = 4;
-__global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, const double *t64,
+__global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, const double *t64, const float *t_up,
                                                           const uint8_t *seedflag, const int32_t *bound,
                                                           const double *tab_t, const uint32_t *tab_cnt,
                                                           uint8_t *keep) {
@@ -396,7 +396,9 @@ __global__ __launch_bounds__(256) void k_table_keep_dense(int64_t n, int nq, con
 #pragma unroll
     for (int k = 0; k < TK_USERS; ++k) {
         const bool ok = q < nq && u0 + k < n;
-        t[k] = ok ? t64[(u0 + k) * nq + q] : 0.0;
+        // (an upper bound of the threshold keeps at least the pairs the
+        // threshold itself keeps: the columns at or above it can only be fewer)
+        t[k] = ok ? (t_up ? (double)t_up[(u0 + k) * nq + q] : t64[(u0 + k) * nq + q]) : 0.0;
         sf[k] = ok ? seedflag[(u0 + k) * nq + q] : (uint8_t)1;
     }
     const int32_t B = q < nq ? bound[q] : 0;
@@ -808,7 +810,8 @@ hipError_t q_ranks_out(const uint32_t *cnt, int64_t n, int32_t *ranks, hipStream
 }
 
 hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_t *bound, const double *tab_t,
-                        const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st) {
+                        const uint32_t *tab_cnt, uint8_t *keep, hipStream_t st, const float *t_up) {
+    if (t_up && !ps.dense) return hipErrorInvalidValue;
     if (ps.dense && ps.nq > 0) {
         const int64_t n = ps.npairs / ps.nq;
         // at least TK_USERS * TABLE_COLS threads: they stage the rows
@@ -817,7 +820,7 @@ hipError_t q_table_keep(const PairSet &ps, const uint8_t *seedflag, const int32_
         if (n > 0)
             hipLaunchKernelGGL(k_table_keep_dense, dim3((unsigned)((n + TK_USERS - 1) / TK_USERS),
                                                         (unsigned)((ps.nq + bs - 1) / bs)),
-                               dim3(bs), 0, st, n, ps.nq, ps.t64, seedflag, bound, tab_t, tab_cnt, keep);
+                               dim3(bs), 0, st, n, ps.nq, ps.t64, t_up, seedflag, bound, tab_t, tab_cnt, keep);
         return hipGetLastError();
     }
     LAUNCH1D(k_table_keep, ps.npairs, ps.npairs, 0, ps.pair_u, ps.pair_q, ps.t64, seedflag, bound, tab_t, tab_cnt,

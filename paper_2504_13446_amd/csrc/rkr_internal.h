@@ -145,8 +145,8 @@ hipError_t launch_count(int sk, int mode, const CountArgs &a, int nsplit, int va
 // the software-pipelined exact pass for BF16 scores (exact.hip); its tasks
 // hold one pair each
 hipError_t launch_exact_bf16(const CountArgs &a, int nsplit, hipStream_t st);
-// tasks per workgroup of the pipelined passes (their tile of users)
-int pass_tasks_per_wg();
+// tasks per workgroup of the pipelined passes for nks k-steps (their tile of users)
+int pass_tasks_per_wg(int nks);
 // the same kernel as a screening pass, one pair per task
 hipError_t launch_screen1_bf16(const CountArgs &a, int nsplit, hipStream_t st);
 
