@@ -174,6 +174,12 @@ struct rkr_index {
     DBuf coef_step[3];    // per-step coefficient maxima for steps of 1, 2, 4 blocks
     DBuf coef32_step[2];  // the same for steps of 1 and 2 blocks, rounded up to FP32
     DBuf tup, qlp, qnorm3, qxyz;   // bounded FP32 thresholds of a dense batch and the queries' BF16 copies
+    // pair_u / pair_q currently hold the dense layout of (dp_n users, dp_nq
+    // queries) at these addresses (-1: something else)
+    int64_t dp_n = -1;
+    int dp_nq = -1;
+    const void *dp_u = nullptr, *dp_q = nullptr;
+    size_t dp_ucap = 0, dp_qcap = 0;   // (a buffer that grew was allocated anew)
     DBuf step_znorm;      // per 64-item step: an upper bound of |p| from that step on
     // per-call buffers
     Scratch sc;
@@ -359,7 +365,9 @@ extern "C" void rkr_destroy(rkr_index *x) {
     (void)hipStreamSynchronize(x->st);
     DBuf *bufs[] = {&x->keep, &x->tab_t, &x->tab_th, &x->tab_cnt, &x->ptab_fmin, &x->ptab_step, &x->ptab_cells,
                     &x->Um, &x->Pm, &x->perm, &x->ulp, &x->plp, &x->unorm3, &x->pnorm3, &x->uexp, &x->pexp,
-                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->coef32_step[0], &x->coef32_step[1], &x->tup, &x->qlp, &x->qnorm3, &x->qxyz, &x->pair_u, &x->pair_q, &x->pair_off, &x->qm_pid, &x->t64,
+                    &x->coef, &x->coef_step[0], &x->coef_step[1], &x->coef_step[2], &x->coef32_step[0],
+                    &x->coef32_step[1], &x->tup, &x->qlp, &x->qnorm3, &x->qxyz, &x->pair_u, &x->pair_q,
+                    &x->pair_off, &x->qm_pid, &x->t64,
                     &x->cnt, &x->seedflag, &x->keys, &x->sel, &x->selrank, &x->best, &x->cand,
                     &x->candkeys, &x->ans, &x->seedpid, &x->surv, &x->emit, &x->ctr, &x->bound, &x->seedkth,
                     &x->kdev, &x->sdev, &x->cdev, &x->segoff, &x->seloff, &x->bestoff, &x->candoff, &x->cursor,
@@ -463,6 +471,24 @@ static int64_t pick_nsplit(int64_t gx, int64_t nsteps, int cus, int64_t max_spli
 // Tile of the exact passes: v2, 1 x 2 blocks per wave (the low-register
 // tile; FP32 scores have one tile, v0 = 1 x 1).
 static int exact_variant(const rkr_index *x) { return x->sk == SK_F32 ? 0 : 2; }
+
+// The pairs of a dense batch (pid = u * nq + q) depend on (n, nq) only: the
+// lists are written again only when the shape or the buffers change.
+static hipError_t dense_pairs(rkr_index *x, int64_t n, int nq, hipStream_t st) {
+    if (x->dp_n == n && x->dp_nq == nq && x->dp_u == x->pair_u.p && x->dp_q == x->pair_q.p &&
+        x->dp_ucap == x->pair_u.cap && x->dp_qcap == x->pair_q.cap)
+        return hipSuccess;
+    x->dp_n = -1;
+    hipError_t e = launch_dense_pairs(n, nq, x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), st);
+    if (e != hipSuccess) return e;
+    x->dp_n = n;
+    x->dp_nq = nq;
+    x->dp_u = x->pair_u.p;
+    x->dp_q = x->pair_q.p;
+    x->dp_ucap = x->pair_u.cap;
+    x->dp_qcap = x->pair_q.cap;
+    return hipSuccess;
+}
 
 // Users per workgroup of an exact pass (the pipelined pass for BF16 scores,
 // else the count kernel's tile); it sets the item splits of a launch.
@@ -823,12 +849,13 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(x->segoff.ensure((nq + 1) * 8));
     HIPCK(hipMemcpyAsync(x->segoff.p, segoff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
     if (dense) {
-        HIPCK(launch_dense_pairs(n, nq, ps.pair_u, ps.pair_q, st));
+        HIPCK(dense_pairs(x, n, nq, st));
     } else {
         HIPCK(x->pair_off.ensure((n + 1) * 8));
         HIPCK(x->qm_pid.ensure(npairs * 4));
         ps.pair_off = x->pair_off.as<int64_t>();
         ps.qm_pid = x->qm_pid.as<int32_t>();
+        x->dp_n = -1;   // the CSR layout overwrites the pair lists
         hipError_t e = build_csr_pairs(cand_ids, x->segoff.as<int64_t>(), nq, npairs, n, ps, x->flags.as<int>() + 1,
                                        x->sc, st);
         if (e == hipErrorInvalidValue)
@@ -1033,7 +1060,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
             const bool pers_phase = persistent && tiles >= x->num_cus;
             int64_t nsplit = 1;
             if (tiles < x->num_cus) {
-                nsplit = std::min<int64_t>(pick_nsplit(tiles, s1 - s0, x->num_cus), 16);
+                // (lists of one pair per task merge with any number of splits)
+                const int64_t max_split = single ? kMaxExactSplits : 16;
+                nsplit = std::min<int64_t>(pick_nsplit(tiles, s1 - s0, x->num_cus, max_split), max_split);
                 while (nsplit > 1 && cur->cap_total * nsplit >= ((int64_t)1 << 30)) --nsplit;
                 if (nsplit > 1) {
                     a.steps_per_split = (s1 - s0 + nsplit - 1) / nsplit;
@@ -1071,7 +1100,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
             ph_timed[ph] = true;
             if (nsplit > 1)
                 HIPCK(q_screen_merge(*cur, (int)nsplit, x->sp_len.as<int32_t>(), x->sp_pid.as<int32_t>(),
-                                     x->sp_cnt.as<uint32_t>(), st));
+                                     x->sp_cnt.as<uint32_t>(), st, single));
             x->stats.screen_ctas = std::max<int64_t>(x->stats.screen_ctas,
                                                      pers_phase ? std::min<int64_t>(x->num_cus, tiles) : tiles * nsplit);
             s0 = s1;
@@ -1212,7 +1241,7 @@ static rkr_status ranks_eager(rkr_index *x, const void *q, int32_t *ranks_out) {
     ps.t64 = x->t64.as<double>();
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(q, x->d, x->mk, x->flags.as<int>(), st));
-    HIPCK(launch_dense_pairs(n, 1, ps.pair_u, ps.pair_q, st));
+    HIPCK(dense_pairs(x, n, 1, st));
     HIPCK(launch_thresh_dense(x->Um.p, n, q, 1, x->d, x->mk, ps.t64, st));
     int flags = 0;
     HIPCK(hipMemcpyAsync(&flags, x->flags.p, 4, hipMemcpyDeviceToHost, st));
@@ -1767,7 +1796,7 @@ extern "C" rkr_status rkr_train(rkr_index *x, int32_t nq, const void *Qm, int32_
     ps.t64 = x->t64.as<double>();
     HIPCK(launch_fill_u32(x->flags.as<uint32_t>(), 0, 4, st));
     HIPCK(launch_check_values(Qm, (int64_t)nq * d, x->mk, x->flags.as<int>(), st));
-    HIPCK(launch_dense_pairs(n, nq, ps.pair_u, ps.pair_q, st));
+    HIPCK(dense_pairs(x, n, nq, st));
     HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st));
     // best users by t/|u| (select) + stratified users, marked in a pair flag array
     const int top = (int)std::min<int64_t>(std::min<int64_t>(pairs_per_query / 2, 4096), n);
@@ -1860,7 +1889,7 @@ extern "C" rkr_status rkr_predict(rkr_index *x, int32_t nq, const void *Qm, floa
     HIPCK(x->pair_u.ensure(npairs * 4));
     HIPCK(x->pair_q.ensure(npairs * 4));
     HIPCK(x->t64.ensure(npairs * 8));
-    HIPCK(launch_dense_pairs(n, nq, x->pair_u.as<int32_t>(), x->pair_q.as<int32_t>(), st));
+    HIPCK(dense_pairs(x, n, nq, st));
     HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, x->d, x->mk, x->t64.as<double>(), st));
     HIPCK(est_infer(x->est, nullptr, nullptr, npairs, x->pair_u.as<int32_t>(), x->t64.as<double>(),
                     x->unorm3.as<double>(), out, nq, n, st));

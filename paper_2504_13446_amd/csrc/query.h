@@ -49,7 +49,8 @@ hipError_t q_replicate_u32(const uint32_t *src, int64_t n, uint32_t *dst, int ns
 // every split kept whose summed partial counts stay within the budget, with
 // the budget left (sp_*: the splits' lists, [ns][ntask_pad] and [ns][cap_total])
 hipError_t q_screen_merge(TaskSet &ts, int ns, const int32_t *sp_len, const int32_t *sp_pid,
-                          const uint32_t *sp_rem, hipStream_t st);
+                          const uint32_t *sp_rem, hipStream_t st,
+                          bool one_per_task = false);
 // number of tasks whose list is not empty
 hipError_t q_count_live(const int32_t *len, int64_t n, unsigned long long *dev, int64_t *count, hipStream_t st);
 // *scored -= (ntask - *nusers) * m, on the device

@@ -729,12 +729,39 @@ __global__ void k_screen_merge(int64_t ntask, const int64_t *blk_base, int64_t c
     len[t] = w;
 }
 
+// The same merge for lists of one entry per task, any number of splits.
+__global__ void k_screen_merge1(int64_t ntask, const int64_t *blk_base, int64_t cap_total, int64_t len_stride,
+                                int ns, int32_t *len, uint32_t *rem, const int32_t *sp_len, const uint32_t *sp_rem) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntask || len[t] == 0) return;
+    const int64_t e = blk_base[t >> 5] + (t & 31);
+    const int64_t rem0 = (int32_t)rem[e];
+    int64_t sum = 0;
+    bool alive = true;
+    for (int s = 0; s < ns; ++s) {
+        if (sp_len[(int64_t)s * len_stride + t] == 0) alive = false;
+        else sum += (int32_t)sp_rem[(int64_t)s * cap_total + e];
+    }
+    const int64_t r = sum - (int64_t)(ns - 1) * rem0;
+    if (alive && r >= 0) {
+        rem[e] = (uint32_t)r;
+    } else {
+        len[t] = 0;
+    }
+}
+
 hipError_t q_replicate_u32(const uint32_t *src, int64_t n, uint32_t *dst, int ns, hipStream_t st) {
     LAUNCH1D(k_replicate_u32, n, src, n, dst, ns);
     return hipGetLastError();
 }
 hipError_t q_screen_merge(TaskSet &ts, int ns, const int32_t *sp_len, const int32_t *sp_pid,
-                          const uint32_t *sp_rem, hipStream_t st) {
+                          const uint32_t *sp_rem, hipStream_t st, bool one_per_task) {
+    if (one_per_task) {
+        if (ns < 1) return hipErrorInvalidValue;
+        LAUNCH1D(k_screen_merge1, ts.ntask, ts.ntask, ts.blk_base, ts.cap_total, ts.ntask_pad, ns, ts.len,
+                 ts.ent_cnt, sp_len, sp_rem);
+        return hipGetLastError();
+    }
     if (ns < 1 || ns > MERGE_MAX_SPLITS) return hipErrorInvalidValue;
     LAUNCH1D(k_screen_merge, ts.ntask, ts.ntask, ts.blk_base, ts.cap_total, ts.ntask_pad, ns, ts.len, ts.ent_pid,
              ts.ent_th, ts.ent_cnt, sp_len, sp_pid, sp_rem);
