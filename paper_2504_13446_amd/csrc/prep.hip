@@ -593,6 +593,102 @@ __global__ void k_thresh_list(const int32_t *pids, int64_t N, const int32_t *pai
     t64[p] = spec_dot_rows(Um, pair_u[p], Qm, pair_q[p], d, mk);
 }
 
+// The recheck with the rows staged through LDS: a workgroup takes 256
+// records at a time and walks the dimension in chunks of RC_K elements; for
+// each chunk the 256 user-row and item-row segments are loaded into LDS with
+// coalesced 16-byte loads (eight lanes per 128-byte segment), then each
+// thread extends its own record's FP64 chain over the chunk (k ascending,
+// the same sequence of fma as spec_dot_rows, so the same double).  The rows
+// of one record are read once, in full lines, instead of 16 bytes per lane
+// per load scattered over 64 rows.
+constexpr int RC_REC = 256, RC_K = 32;
+__global__ __launch_bounds__(256) void k_recheck_coop(const int2 *rec, const unsigned long long *count, int64_t cap,
+                                                      const int32_t *pair_u, const double *t64, const void *Um,
+                                                      const void *Pm, int d, int mk, uint32_t *cnt,
+                                                      unsigned long long *flips) {
+    __shared__ float su[RC_REC][RC_K + 1], sp[RC_REC][RC_K + 1];
+    __shared__ int64_t ru[RC_REC], rp[RC_REC];
+    const int tid = threadIdx.x;
+    const int64_t nrec = (int64_t)min((unsigned long long)cap, *count);
+    const int64_t nblk = (nrec + RC_REC - 1) / RC_REC;
+    unsigned long long nflip = 0;
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int64_t i = b * RC_REC + tid;
+        int pid = 0;
+        bool plain = false, real = i < nrec;
+        if (real) {
+            const int2 r = rec[i];
+            pid = r.x;
+            plain = (r.y >> 31) & 1;
+            ru[tid] = pair_u[pid];
+            rp[tid] = r.y & 0x7FFFFFFF;
+        } else {
+            ru[tid] = -1;
+            rp[tid] = -1;
+        }
+        __syncthreads();
+        double acc = 0.0;
+        for (int k0 = 0; k0 < d; k0 += RC_K) {
+            const int kn = min(RC_K, d - k0);
+            if (mk == MK_BF16) {
+                // 8 elements (16 bytes) per lane, 4 lanes per row segment
+                for (int idx = tid; idx < RC_REC * (RC_K / 8) * 2; idx += 256) {
+                    const int which = idx / (RC_REC * (RC_K / 8));
+                    const int j = idx % (RC_REC * (RC_K / 8));
+                    const int row = j / (RC_K / 8), c = (j % (RC_K / 8)) * 8;
+                    const int64_t rr = which ? rp[row] : ru[row];
+                    float *dst = which ? &sp[row][c] : &su[row][c];
+                    const uint16_t *src = (const uint16_t *)(which ? Pm : Um) + rr * d + k0 + c;
+                    if (rr >= 0 && c + 8 <= kn && ((((uintptr_t)src) & 15) == 0)) {
+                        const uint4 v = *(const uint4 *)src;
+                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            dst[2 * e] = __uint_as_float(w[e] << 16);
+                            dst[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            dst[e] = (rr >= 0 && c + e < kn) ? __uint_as_float((uint32_t)src[e] << 16) : 0.0f;
+                    }
+                }
+            } else {
+                // 4 elements (16 bytes) per lane, 8 lanes per row segment
+                for (int idx = tid; idx < RC_REC * (RC_K / 4) * 2; idx += 256) {
+                    const int which = idx / (RC_REC * (RC_K / 4));
+                    const int j = idx % (RC_REC * (RC_K / 4));
+                    const int row = j / (RC_K / 4), c = (j % (RC_K / 4)) * 4;
+                    const int64_t rr = which ? rp[row] : ru[row];
+                    float *dst = which ? &sp[row][c] : &su[row][c];
+                    const float *src = (const float *)(which ? Pm : Um) + rr * d + k0 + c;
+                    if (rr >= 0 && c + 4 <= kn && ((((uintptr_t)src) & 15) == 0)) {
+                        const float4 v = *(const float4 *)src;
+                        dst[0] = v.x;
+                        dst[1] = v.y;
+                        dst[2] = v.z;
+                        dst[3] = v.w;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) dst[e] = (rr >= 0 && c + e < kn) ? src[e] : 0.0f;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int k = 0; k < kn; ++k) acc = fma((double)su[tid][k], (double)sp[tid][k], acc);
+            __syncthreads();
+        }
+        bool flip = false;
+        if (real) {
+            const bool above = acc > t64[pid];
+            if (above) atomicAdd(&cnt[pid], 1u);
+            flip = above != plain;
+        }
+        nflip += (unsigned long long)__popcll(__ballot(flip));
+    }
+    if ((threadIdx.x & 63) == 0 && nflip) atomicAdd(flips, nflip);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -694,11 +790,22 @@ hipError_t launch_thresh_dense(const void *Um, int64_t n, const void *Qm, int nq
     return hipGetLastError();
 }
 
+static bool env_flag_rc(const char *name) {
+    const char *v = getenv(name);
+    return v && v[0] == '1' && v[1] == 0;
+}
+
 hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
                               const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                               unsigned long long *flips, hipStream_t st) {
-    hipLaunchKernelGGL(k_recheck_dev, dim3(2048), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk, cnt,
-                       flips);
+    // FP32 master rows (1.2 KB at d = 300) through LDS in full lines; BF16
+    // rows (half the bytes) measured faster one thread per record
+    if (mk == MK_BF16 || env_flag_rc("RKR_RECHECK_THREAD"))
+        hipLaunchKernelGGL(k_recheck_dev, dim3(2048), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk,
+                           cnt, flips);
+    else
+        hipLaunchKernelGGL(k_recheck_coop, dim3(1024), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk,
+                           cnt, flips);
     return hipGetLastError();
 }
 
