@@ -867,7 +867,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     HIPCK(x->t64.ensure(npairs * 8));
     HIPCK(x->keys.ensure(npairs * 8));
     ps.t64 = x->t64.as<double>();
-    const bool keys_fused = dense && x->qo.use_estimator == 0;
+    // dense batches: the default seed keys come out of the threshold kernel
+    // (with the estimator they pick its candidates)
+    const bool keys_fused = dense;
     // Dense batches filtered by the rank table: every pair needs its
     // threshold only for the filter and the seed order, so those get bounded
     // FP32 values from the matrix cores (t_up >= the FP64 threshold); the FP64
@@ -910,7 +912,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     // counted exactly; no screen, so Def. 3 is not guaranteed
     const bool pruned = c && x->qo.prune_mult > 0;
     const float *pred = nullptr;
-    if (use_est) {
+    if (use_est && !dense) {
         HIPCK(x->est.pred.ensure(npairs * 4));
         HIPCK(est_infer(x->est, nullptr, nullptr, npairs, ps.pair_u, ps.t64, x->unorm3.as<double>(),
                         x->est.pred.as<float>(), 0, 0, st));
@@ -948,8 +950,41 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
     }
     if (!keys_fused)
         HIPCK(q_seed_keys(v, ps.pair_u, ps.t64, x->unorm3.as<double>(), pred, npairs, x->keys.as<uint64_t>(), st));
-    HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
-                        x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));
+    if (use_est && dense) {
+        // The estimator orders the kEstCand * S users of best t/|u| per query
+        // (their FP64 thresholds are its input) and the seeds are the S of
+        // best predicted rank among them: inference over every (user, query)
+        // pair would cost more than the seed pass it is meant to shorten.
+        constexpr int64_t kEstCand = 16;
+        std::vector<int64_t> coff(nq + 1, 0);
+        std::vector<int32_t> Cv(nq);
+        for (int q = 0; q < nq; ++q) {
+            Cv[q] = (int32_t)std::min<int64_t>(dom[q], std::min<int64_t>(4096, std::max<int64_t>(S[q], kEstCand * S[q])));
+            coff[q + 1] = coff[q] + Cv[q];
+        }
+        const int64_t nc = coff[nq];
+        HIPCK(x->est.pred.ensure(nc * 4));
+        int64_t *d_coff = (int64_t *)x->sc.take((nq + 1) * 8);
+        int32_t *d_C = (int32_t *)x->sc.take(nq * 4);
+        uint64_t *csel = (uint64_t *)x->sc.take(nc * 8);
+        uint64_t *ckeys = (uint64_t *)x->sc.take(nc * 8);
+        int32_t *cpid = (int32_t *)x->sc.take(nc * 4);
+        if (!d_coff || !d_C || !csel || !ckeys || !cpid) return fail(RKR_E_NOMEM, "estimator candidates");
+        HIPCK(hipMemcpyAsync(d_coff, coff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
+        HIPCK(hipMemcpyAsync(d_C, Cv.data(), nq * 4, hipMemcpyHostToDevice, st));
+        HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), d_C, nq, d_coff, csel, st));
+        HIPCK(q_est_cand_pids(csel, d_coff, nq, nc, cpid, st));
+        if (approx_t)
+            HIPCK(launch_thresh_list(cpid, nc, ps.pair_u, ps.pair_q, x->Um.p, Qm, d, x->mk, ps.t64, st));
+        HIPCK(est_infer(x->est, nullptr, cpid, nc, ps.pair_u, ps.t64, x->unorm3.as<double>(),
+                        x->est.pred.as<float>(), 0, 0, st));
+        HIPCK(q_est_cand_keys(csel, x->est.pred.as<float>(), nc, ckeys, st));
+        HIPCK(launch_select(ckeys, d_coff, x->sdev.as<int32_t>(), nq, x->seloff.as<int64_t>(),
+                            x->sel.as<uint64_t>(), st));
+    } else {
+        HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
+                            x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));
+    }
     HIPCK(x->seedflag.ensure(npairs));
     HIPCK(launch_fill_u8(x->seedflag.as<uint8_t>(), 0, npairs, st));
     HIPCK(q_mark_selected(v, x->sel.as<uint64_t>(), x->seloff.as<int64_t>(), nsel, x->seedflag.as<uint8_t>(), st));

@@ -798,9 +798,10 @@ static bool env_flag_rc(const char *name) {
 hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, int64_t cap, const int32_t *pair_u,
                               const double *t64, const void *Um, const void *Pm, int d, int mk, uint32_t *cnt,
                               unsigned long long *flips, hipStream_t st) {
-    // FP32 master rows (1.2 KB at d = 300) through LDS in full lines; BF16
-    // rows (half the bytes) measured faster one thread per record
-    if (mk == MK_BF16 || env_flag_rc("RKR_RECHECK_THREAD"))
+    // FP32 master rows of d >= 192 (1.2 KB at d = 300) through LDS in full
+    // lines; BF16 rows and short FP32 rows (d = 100: 35.6 against 28.3 ms
+    // for the single-query workload) measured faster one thread per record
+    if (mk == MK_BF16 || d < 192 || env_flag_rc("RKR_RECHECK_THREAD"))
         hipLaunchKernelGGL(k_recheck_dev, dim3(2048), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk,
                            cnt, flips);
     else

@@ -58,6 +58,11 @@ hipError_t q_scored_fix(unsigned long long *scored, int64_t ntask, const int64_t
 // cand_off[0..nq] = exclusive scan of qcount[q] + seeds[q]
 hipError_t q_cand_offsets(const int32_t *qcount, const int32_t *seeds, int nq, int64_t *cand_off, Scratch &sc,
                           hipStream_t st);
+// dense estimator candidates: pid of each selected key (segments cand_off),
+// and keys (predicted log-rank, user) for the second selection
+hipError_t q_est_cand_pids(const uint64_t *csel, const int64_t *coff, int nq, int64_t nc, int32_t *pids,
+                           hipStream_t st);
+hipError_t q_est_cand_keys(const uint64_t *csel, const float *pred, int64_t nc, uint64_t *keys, hipStream_t st);
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
                             hipStream_t st);
 hipError_t q_cand_keys(const QView &v, const uint64_t *sel, const int64_t *sel_off, int64_t nsel,

@@ -800,6 +800,31 @@ hipError_t q_cand_offsets(const int32_t *qcount, const int32_t *seeds, int nq, i
     LAUNCH1D(k_cand_sizes, (int64_t)nq, qcount, seeds, nq, sizes);
     return scan_i32(sizes, nq, cand_off, cand_off + nq, sc, st);
 }
+// Estimator candidates of a dense batch: the pair of each selected key
+// (low half: the user) and, from the predicted log-ranks, their keys.
+__global__ void k_est_cand_pids(const uint64_t *csel, const int64_t *coff, int nq, int64_t nc, int32_t *pids) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nc) return;
+    int lo = 0, hi = nq - 1;   // the query: the segment holding j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (coff[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    pids[j] = (int32_t)((int64_t)(uint32_t)csel[j] * nq + lo);
+}
+__global__ void k_est_cand_keys(const uint64_t *csel, const float *pred, int64_t nc, uint64_t *keys) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nc) keys[j] = ((uint64_t)f32_order_key(pred[j]) << 32) | (csel[j] & 0xFFFFFFFFull);
+}
+hipError_t q_est_cand_pids(const uint64_t *csel, const int64_t *coff, int nq, int64_t nc, int32_t *pids,
+                           hipStream_t st) {
+    LAUNCH1D(k_est_cand_pids, nc, csel, coff, nq, nc, pids);
+    return hipGetLastError();
+}
+hipError_t q_est_cand_keys(const uint64_t *csel, const float *pred, int64_t nc, uint64_t *keys, hipStream_t st) {
+    LAUNCH1D(k_est_cand_keys, nc, csel, pred, nc, keys);
+    return hipGetLastError();
+}
 hipError_t q_count_by_query(const int32_t *pids, int64_t N, const int32_t *pair_q, int32_t *qcount,
                             hipStream_t st) {
     LAUNCH1D(k_count_by_query, N, pids, N, pair_q, qcount);
