@@ -199,8 +199,8 @@ struct rkr_index {
     bool has_ptab = false;
     int64_t emit_cap = 0;
     // events: 0..3 an exact pass and its recheck; 4..9 the stage boundaries of
-    // a batch; 10..23 its screening phases
-    hipEvent_t ev[24] = {};
+    // a batch; 10..41 its screening phases
+    hipEvent_t ev[42] = {};
     rkr_query_opts qo{};
     rkr_query_stats stats{};
     Tuner tuner;
@@ -488,6 +488,31 @@ static hipError_t dense_pairs(rkr_index *x, int64_t n, int nq, hipStream_t st) {
     x->dp_ucap = x->pair_u.cap;
     x->dp_qcap = x->pair_q.cap;
     return hipSuccess;
+}
+
+// The screen's phase ends, in 64ths of the item scan (the last is 64); a
+// list such as "4,8,12,..,64" in RKR_SCREEN_PHASES replaces them (tuning).
+static constexpr int kMaxPhases = 16;
+static const std::vector<int> &screen_phases() {
+    static const std::vector<int> ends = [] {
+        std::vector<int> v;
+        if (const char *e = getenv("RKR_SCREEN_PHASES")) {
+            int prev = 0;
+            for (const char *p = e; *p;) {
+                char *q = nullptr;
+                const long x = strtol(p, &q, 10);
+                if (q == p) break;
+                if (x > prev && x <= 64 && (int)v.size() < kMaxPhases) {
+                    v.push_back((int)x);
+                    prev = (int)x;
+                }
+                p = *q ? q + 1 : q;
+            }
+        }
+        if (v.empty() || v.back() != 64) v = {2, 4, 8, 12, 16, 24, 32, 48, 64};
+        return v;
+    }();
+    return ends;
 }
 
 // Users per workgroup of an exact pass (the pipelined pass for BF16 scores,
@@ -1071,17 +1096,17 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         // new dense task set, so that later steps run only tiles of live
         // users.  A phase with fewer tiles than compute units is split over
         // item ranges.
-        static const int kPhaseEnd32[] = {3, 6, 9, 12, 16, 20, 32};   // in 32nds of the scan
+        const std::vector<int> &phase_end = screen_phases();   // in 64ths of the scan
         HIPCK(ensure_events(x));
         TaskSet *cur = &x->ts_screen, *nxt = &x->ts_screen2;
         const int tpw = single ? pass_tasks_per_wg(x->nks) : WAVES_PER_WG * nub_of(x->sk, x->nks, variant) * USER_BLOCK;
         const int64_t nsteps = count_args(x, ps, *cur, variant).nsteps;
         int64_t s0 = 0;
-        bool ph_timed[sizeof kPhaseEnd32 / sizeof kPhaseEnd32[0]] = {};
+        bool ph_timed[kMaxPhases] = {};
         double ms_kernel = 0.0;
         x->stats.screen_ctas = 0;
-        for (int ph = 0; ph < (int)(sizeof kPhaseEnd32 / sizeof kPhaseEnd32[0]) && s0 < nsteps; ++ph) {
-            const int64_t s1 = kPhaseEnd32[ph] == 32 ? nsteps : nsteps * kPhaseEnd32[ph] / 32;
+        for (int ph = 0; ph < (int)phase_end.size() && s0 < nsteps; ++ph) {
+            const int64_t s1 = phase_end[ph] == 64 ? nsteps : nsteps * phase_end[ph] / 64;
             if (s1 <= s0) continue;
             CountArgs a = count_args(x, ps, *cur, variant);
             a.step0 = s0;
@@ -1175,7 +1200,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         TView tv{cur->ntask, cur->len, cur->blk_base, cur->ent_pid, cur->ent_cnt};
         HIPCK(q_survivors(tv, x->seedflag.as<uint8_t>(), x->surv.as<int32_t>(), &nsurv, x->sc, st));
         // (q_survivors read its count back: every phase has ended)
-        for (int ph = 0; ph < (int)(sizeof ph_timed / sizeof ph_timed[0]); ++ph)
+        for (int ph = 0; ph < kMaxPhases; ++ph)
             if (ph_timed[ph]) ms_kernel += event_ms(pev[2 * ph], pev[2 * ph + 1]);
         x->stats.ms_screen_kernel = ms_kernel;
         if (!single) x->tuner.record(key, cand, ms_kernel, 2 * ntv);
