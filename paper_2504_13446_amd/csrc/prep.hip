@@ -595,27 +595,68 @@ __global__ void k_thresh_list(const int32_t *pids, int64_t N, const int32_t *pai
 
 // The recheck with the rows staged through LDS: a workgroup takes 256
 // records at a time and walks the dimension in chunks of RC_K elements; for
-// each chunk the 256 user-row and item-row segments are loaded into LDS with
-// coalesced 16-byte loads (eight lanes per 128-byte segment), then each
-// thread extends its own record's FP64 chain over the chunk (k ascending,
-// the same sequence of fma as spec_dot_rows, so the same double).  The rows
-// of one record are read once, in full lines, instead of 16 bytes per lane
-// per load scattered over 64 rows.
+// each chunk the records' item-row segments and their distinct user-row
+// segments are loaded into LDS with coalesced 16-byte loads (eight lanes per
+// 128-byte segment of FP32, four of BF16), then each thread extends its own
+// record's FP64 chain over the chunk (k ascending, the same sequence of fma as
+// spec_dot_rows, so the same double).  A pass emits the near ties of one user
+// together, so a run of records sharing a user loads its row once.
 constexpr int RC_REC = 256, RC_K = 32;
+template <int MK>
+__device__ inline void rc_load_rows(const void *X, const int64_t *rows, int nrows, int d, int k0, int kn,
+                                    float (*dst)[RC_K + 1], int tid) {
+    constexpr int EPL = MK == MK_BF16 ? 8 : 4;   // elements per 16-byte lane load
+    constexpr int LPR = RC_K / EPL;              // lanes per row segment
+    for (int idx = tid; idx < nrows * LPR; idx += 256) {
+        const int row = idx / LPR, c = (idx % LPR) * EPL;
+        const int64_t rr = rows[row];
+        float *o = &dst[row][c];
+        if constexpr (MK == MK_BF16) {
+            const uint16_t *src = (const uint16_t *)X + rr * d + k0 + c;
+            if (rr >= 0 && c + 8 <= kn && ((((uintptr_t)src) & 15) == 0)) {
+                const uint4 v = *(const uint4 *)src;
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    o[2 * e] = __uint_as_float(w[e] << 16);
+                    o[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) o[e] = (rr >= 0 && c + e < kn) ? __uint_as_float((uint32_t)src[e] << 16) : 0.0f;
+            }
+        } else {
+            const float *src = (const float *)X + rr * d + k0 + c;
+            if (rr >= 0 && c + 4 <= kn && ((((uintptr_t)src) & 15) == 0)) {
+                const float4 v = *(const float4 *)src;
+                o[0] = v.x;
+                o[1] = v.y;
+                o[2] = v.z;
+                o[3] = v.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = (rr >= 0 && c + e < kn) ? src[e] : 0.0f;
+            }
+        }
+    }
+}
+template <int MK>
 __global__ __launch_bounds__(256) void k_recheck_coop(const int2 *rec, const unsigned long long *count, int64_t cap,
                                                       const int32_t *pair_u, const double *t64, const void *Um,
-                                                      const void *Pm, int d, int mk, uint32_t *cnt,
+                                                      const void *Pm, int d, uint32_t *cnt,
                                                       unsigned long long *flips) {
     __shared__ float su[RC_REC][RC_K + 1], sp[RC_REC][RC_K + 1];
-    __shared__ int64_t ru[RC_REC], rp[RC_REC];
-    const int tid = threadIdx.x;
+    __shared__ int64_t ru[RC_REC], rp[RC_REC], uu[RC_REC];
+    __shared__ int wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t nrec = (int64_t)min((unsigned long long)cap, *count);
     const int64_t nblk = (nrec + RC_REC - 1) / RC_REC;
     unsigned long long nflip = 0;
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int64_t i = b * RC_REC + tid;
         int pid = 0;
-        bool plain = false, real = i < nrec;
+        bool plain = false;
+        const bool real = i < nrec;
         if (real) {
             const int2 r = rec[i];
             pid = r.x;
@@ -627,55 +668,26 @@ __global__ __launch_bounds__(256) void k_recheck_coop(const int2 *rec, const uns
             rp[tid] = -1;
         }
         __syncthreads();
+        // distinct user rows: a record opens a slot when its user differs
+        // from the previous record's (real records are a prefix of the block)
+        const bool open = real && (tid == 0 || ru[tid] != ru[tid - 1]);
+        const uint64_t bal = __ballot(open);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+        if (lane == 0) wsum[wv] = __popcll(bal);
+        __syncthreads();
+        int slot = __popcll(bal & upto) - 1;
+        for (int k = 0; k < wv; ++k) slot += wsum[k];
+        const int nu = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (open) uu[slot] = ru[tid];
+        __syncthreads();
         double acc = 0.0;
         for (int k0 = 0; k0 < d; k0 += RC_K) {
             const int kn = min(RC_K, d - k0);
-            if (mk == MK_BF16) {
-                // 8 elements (16 bytes) per lane, 4 lanes per row segment
-                for (int idx = tid; idx < RC_REC * (RC_K / 8) * 2; idx += 256) {
-                    const int which = idx / (RC_REC * (RC_K / 8));
-                    const int j = idx % (RC_REC * (RC_K / 8));
-                    const int row = j / (RC_K / 8), c = (j % (RC_K / 8)) * 8;
-                    const int64_t rr = which ? rp[row] : ru[row];
-                    float *dst = which ? &sp[row][c] : &su[row][c];
-                    const uint16_t *src = (const uint16_t *)(which ? Pm : Um) + rr * d + k0 + c;
-                    if (rr >= 0 && c + 8 <= kn && ((((uintptr_t)src) & 15) == 0)) {
-                        const uint4 v = *(const uint4 *)src;
-                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            dst[2 * e] = __uint_as_float(w[e] << 16);
-                            dst[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
-                        }
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e)
-                            dst[e] = (rr >= 0 && c + e < kn) ? __uint_as_float((uint32_t)src[e] << 16) : 0.0f;
-                    }
-                }
-            } else {
-                // 4 elements (16 bytes) per lane, 8 lanes per row segment
-                for (int idx = tid; idx < RC_REC * (RC_K / 4) * 2; idx += 256) {
-                    const int which = idx / (RC_REC * (RC_K / 4));
-                    const int j = idx % (RC_REC * (RC_K / 4));
-                    const int row = j / (RC_K / 4), c = (j % (RC_K / 4)) * 4;
-                    const int64_t rr = which ? rp[row] : ru[row];
-                    float *dst = which ? &sp[row][c] : &su[row][c];
-                    const float *src = (const float *)(which ? Pm : Um) + rr * d + k0 + c;
-                    if (rr >= 0 && c + 4 <= kn && ((((uintptr_t)src) & 15) == 0)) {
-                        const float4 v = *(const float4 *)src;
-                        dst[0] = v.x;
-                        dst[1] = v.y;
-                        dst[2] = v.z;
-                        dst[3] = v.w;
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) dst[e] = (rr >= 0 && c + e < kn) ? src[e] : 0.0f;
-                    }
-                }
-            }
+            rc_load_rows<MK>(Pm, rp, RC_REC, d, k0, kn, sp, tid);
+            rc_load_rows<MK>(Um, uu, nu, d, k0, kn, su, tid);
             __syncthreads();
-            for (int k = 0; k < kn; ++k) acc = fma((double)su[tid][k], (double)sp[tid][k], acc);
+            if (real)
+                for (int k = 0; k < kn; ++k) acc = fma((double)su[slot][k], (double)sp[tid][k], acc);
             __syncthreads();
         }
         bool flip = false;
@@ -801,12 +813,12 @@ hipError_t launch_recheck_dev(const int2 *rec, const unsigned long long *count, 
     // FP32 master rows of d >= 192 (1.2 KB at d = 300) through LDS in full
     // lines; BF16 rows and short FP32 rows (d = 100: 35.6 against 28.3 ms
     // for the single-query workload) measured faster one thread per record
-    if (mk == MK_BF16 || d < 192 || env_flag_rc("RKR_RECHECK_THREAD"))
+    if (mk == MK_BF16 || (d < 192 && !env_flag_rc("RKR_RECHECK_COOP")) || env_flag_rc("RKR_RECHECK_THREAD"))
         hipLaunchKernelGGL(k_recheck_dev, dim3(2048), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk,
                            cnt, flips);
     else
-        hipLaunchKernelGGL(k_recheck_coop, dim3(1024), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm, d, mk,
-                           cnt, flips);
+        hipLaunchKernelGGL(k_recheck_coop<MK_F32>, dim3(1024), dim3(256), 0, st, rec, count, cap, pair_u, t64, Um, Pm,
+                           d, cnt, flips);
     return hipGetLastError();
 }
 
