@@ -672,12 +672,9 @@ hipError_t launch_pass_nks(const CountArgs &a, int nsplit, hipStream_t st) {
 // Shape 2 up to 13 k-steps (d <= 208 in BF16); with 20 its registers would
 // spill, so shape 1.  RKR_PASS_SHAPE overrides the choice (for measurements).
 int pass_shape(int nks) {
-    static const int forced = [] {
-        const char *v = getenv("RKR_PASS_SHAPE");
-        const int k = v ? atoi(v) : -1;
-        return k >= 0 && k <= 2 ? k : -1;
-    }();
-    if (forced >= 0) return forced;
+    const char *v = getenv("RKR_PASS_SHAPE");   // read per launch, so that a process can compare shapes
+    const int forced = v ? atoi(v) : -1;
+    if (forced >= 0 && forced <= 2) return forced;
     return nks <= 13 ? 2 : 1;
 }
 

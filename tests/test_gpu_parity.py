@@ -243,3 +243,29 @@ def test_recheck_of_many_near_ties():
     idx.close()
     assert st["uncertain"] > 65536 * 256, st["uncertain"]
     assert np.array_equal(got, R), np.flatnonzero(got != R)[:10]
+
+
+@pytest.mark.parametrize("shape", ["0", "1", "2"])
+def test_pass_shapes_equal_the_oracle(shape):
+    """Every shape of the pipelined pass (64-item steps with 8 waves and the
+    FP64 band, the same with the FP32 band, 32-item steps with 12 waves and the
+    FP32 band) gives the oracle's exact answers and all-ranks, with and
+    without the rank table, on a ragged shape (n, m not multiples of the
+    tiles; d = 45)."""
+    import os
+    w = W.make("small", n=2900, m=3333, d=45, nq=9)
+    R = O.ranks(w.U, w.P, w.Qv)
+    ks = np.array([1, 4, 10, 25, 7, 60, 2, 33, 10], np.int32)
+    os.environ["RKR_PASS_SHAPE"] = shape
+    try:
+        for table in (0, 512):
+            idx = rkr.Index(_dev(w.U, "f32"), _dev(w.P, "f32"), score="bf16", rank_table=table)
+            ans = _answers(*idx.query_batch(_dev(w.Qv, "f32"), ks))
+            for i, (gi, gr) in enumerate(ans):
+                wi, wr = O.topk(R[i], int(ks[i]))
+                assert np.array_equal(gi, wi) and np.array_equal(gr, wr), (shape, table, i)
+            got = idx.ranks(_dev(w.Qv[3], "f32")).cpu().numpy()
+            assert np.array_equal(got, R[3]), (shape, table)
+            idx.close()
+    finally:
+        del os.environ["RKR_PASS_SHAPE"]
