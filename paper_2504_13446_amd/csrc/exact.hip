@@ -187,6 +187,10 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     const int64_t s_begin = r_begin * SR;
     const int64_t s_end = std::min<int64_t>(std::min<int64_t>(r_begin + a.steps_per_split, a.step_end) * SR,
                                             (a.m + NIB * 32 - 1) / (NIB * 32));
+    // the loop's step numbers in 32 bits, so that its tests are scalar
+    // compares (item numbers are 32-bit in the records, so steps fit)
+    const int sb32 = (int)s_begin, se32 = (int)s_end;
+    const int s_full = (int)(a.m / (NIB * 32));   // steps with no item past the end
     // the step's error-bound coefficients (FP64, or FP32 rounded up)
     const void *coef_base = B32 ? (const void *)(NIB == 1 ? a.step_coef32_half : a.step_coef32)
                                 : (const void *)(NIB == 1 ? a.step_coef_half : a.step_coef);
@@ -407,8 +411,9 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         }
     };
     // scores of items past the end never count
-    auto mask_tail = [&](f32x16 *acc, int64_t item0) {
-        if (item0 + NIB * 32 <= a.m) return;
+    auto mask_tail = [&](f32x16 *acc, int s) {
+        if (s < s_full) return;
+        const int64_t item0 = (int64_t)s * (NIB * 32);
         const int lim = (int)(a.m - item0) - 4 * half;
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib)
@@ -495,14 +500,14 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     }
     wait_vm_n((int)(npro - 1) * nload);
     __syncthreads();
-    const int64_t s_run = SCREEN ? s_end : s_begin + wg_live[0];
+    const int s_run = SCREEN ? se32 : sb32 + __builtin_amdgcn_readfirstlane(wg_live[0]);
     int lslot = 0;
-    auto barrier_before = [&](int64_t st0) -> bool {
+    auto barrier_before = [&](int st0) -> bool {
         // copies of steps past s_run issued before it was known only make
         // this wait stricter
-        const int64_t last = std::min<int64_t>(st0 - 1 + D, s_run - 1);
-        const int64_t later = std::max<int64_t>(0, last - (st0 + SP));
-        wait_vm_n((int)later * nload);
+        const int last = std::min(st0 - 1 + D, s_run - 1);
+        const int later = std::max(0, last - (st0 + SP));
+        wait_vm_n(later * nload);
         if constexpr (!SCREEN) {
             __syncthreads();
             return true;
@@ -521,11 +526,11 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     f32x16 accA[NIB], accB[NIB];
     float ehi = 0.0f, elo = 0.0f;   // the band of the current step
     bool go = false;
-    if (s_run > s_begin) {
+    if (s_run > sb32) {
         scores(lds, accA);
         band_of_tile(lds, ehi, elo);
-        mask_tail(accA, s_begin * (NIB * 32));
-        go = barrier_before(s_begin);
+        mask_tail(accA, sb32);
+        go = barrier_before(sb32);
     }
 
     int slot_nxt = 1 % NBUF;      // stage of step st + 1
@@ -533,10 +538,10 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // One step: stage st + D, count st (cur) while scoring st + 1 (nxt).
     // The last step of a tile scores a stale stage too (its result is never
     // used): the block then has no branch, and the compare stays in it.
-    auto body = [&](f32x16 *cur, f32x16 *nxt, int64_t st) {
+    auto body = [&](f32x16 *cur, f32x16 *nxt, int st) {
         if (st + D < s_run)
-            stage(a.plp + (st + D) * (int64_t)STEP_BYTES, lds_base + slot_stg * STAGE, wave_u, lane, coef_of(st + D));
-        const int64_t item0 = st * (NIB * 32);
+            stage(a.plp + (int64_t)(st + D) * STEP_BYTES, lds_base + slot_stg * STAGE, wave_u, lane, coef_of(st + D));
+        const int64_t item0 = (int64_t)st * (NIB * 32);
         const uint8_t *tn = lds + slot_nxt * STAGE;
         uint32_t c;
         float dmin;
@@ -564,7 +569,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         if constexpr (SCREEN) {
             // the budget left after this step's certainly-above items
             nscored += (uint64_t)(__popcll(__ballot(live)) / 2) *
-                       (uint64_t)std::min<int64_t>(NIB * 32, a.m - item0);
+                       (uint64_t)(st < s_full ? NIB * 32 : (int)(a.m - item0));
             ncmp += live ? (uint64_t)NSC : 0;
             rem -= (int)pair_sum(c);   // both halves of the step's items (lanes l and l + 32)
             live = live && rem >= 0;
@@ -572,7 +577,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             cnt += c;
             if (__ballot(live && dmin <= elo) != 0ull) emit_ties(cur, ehi, elo, item0);
         }
-        mask_tail(nxt, item0 + NIB * 32);
+        mask_tail(nxt, st + 1);
         ehi = ehi_n;
         elo = elo_n;
         slot_nxt = slot_nxt + 1 == NBUF ? 0 : slot_nxt + 1;
@@ -580,7 +585,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         ++nstep;
     };
 
-    int64_t st = s_begin;
+    int st = sb32;
     if (go)
         for (;;) {
             body(accA, accB, st);
@@ -588,7 +593,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             if (SP == 1 && !barrier_before(st)) break;
             body(accB, accA, st);
             if (++st >= s_run) break;
-            if ((SP == 2 || ((st - s_begin) & (SP - 1)) == 0) && !barrier_before(st)) break;
+            if ((SP == 2 || ((st - sb32) & (SP - 1)) == 0) && !barrier_before(st)) break;
         }
     // the pass scored steps s_begin .. stop - 1; a workgroup that stops
     // early may still have copies in flight into its LDS: they land before
