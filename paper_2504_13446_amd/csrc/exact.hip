@@ -358,57 +358,32 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         return item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
     };
     // near ties of the pair in one step to the record buffer, each with the
-    // plain FP32 verdict in its top bit
+    // plain FP32 verdict in its top bit.  One score position at a time: a
+    // wave ballot of the lanes whose score there is a near tie, skipped (a
+    // uniform branch) when there is none, which is nearly always: a step that
+    // gets here usually holds one or two near ties in all of its 64 lanes.
+    // A position adds at most 64 records, so one flush makes room.
+    static_assert(REC_PER_WAVE >= 64, "a score position's records must fit the buffer");
     auto emit_ties = [&](const f32x16 *acc, float ehi, float elo, int64_t item0) {
-        // bit ib * 16 + r of each mask is score r of block ib (shifted in
-        // from the top, so that no per-bit constants are needed)
-        uint32_t umask = 0, pmask = 0;
 #pragma unroll
-        for (int ib = NIB - 1; ib >= 0; --ib)
+        for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
-            for (int r = 15; r >= 0; --r) {
+            for (int r = 0; r < 16; ++r) {
                 const float v = acc[ib][r];
-                umask = (umask << 1) | ((v >= -elo && !(v > ehi)) ? 1u : 0u);
-                pmask = (pmask << 1) | ((v > pd) ? 1u : 0u);
+                const bool tie = live & (v >= -elo) & !(v > ehi);
+                const uint64_t m = __ballot(tie);
+                if (m == 0ull) continue;
+                const int n = (int)__popcll(m);
+                if (rb_n + n > REC_PER_WAVE) flush_records();
+                if (tie) {
+                    const int pos =
+                        rb_n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const int plainbit = (v > pd) ? (int)0x80000000 : 0;
+                    recbuf[pos] = make_int2(pid, (int)item_of(item0, ib, r) | plainbit);
+                }
+                rb_n += n;
             }
-        if (!live) umask = 0;
-        const uint32_t nu = __popc(umask);
-        // record offsets: with at most one record per lane (the usual case)
-        // the lane's rank among the lanes that have one, else a prefix sum
-        uint32_t incl, total;
-        const uint64_t has = __ballot(nu != 0);
-        if (__ballot(nu > 1) == 0ull) {
-            incl = __builtin_amdgcn_mbcnt_hi((uint32_t)(has >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)has, 0u)) + nu;
-            total = (uint32_t)__popcll(has);
-        } else {
-            incl = wave_incl_scan(nu, lane);
-            total = __shfl(incl, 63, 64);
-        }
-        if (rb_n + (int)total > REC_PER_WAVE) flush_records();
-        auto put = [&](auto &&store) {
-            uint32_t mm = umask;
-            while (mm) {
-                const int bit = __ffs(mm) - 1;
-                mm &= mm - 1;
-                const int64_t item = item_of(item0, bit >> 4, bit & 15);
-                const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
-                store(make_int2(pid, (int)item | plainbit));
-            }
-        };
-        if ((int)total <= REC_PER_WAVE) {
-            int pos = rb_n + (int)(incl - nu);
-            put([&](int2 rec) { recbuf[pos++] = rec; });
-            rb_n += (int)total;
-        } else {
-            // more than a buffer's worth at once: straight to the output
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
-            unsigned long long pos = __shfl(base, 0, 64) + (incl - nu);
-            put([&](int2 rec) {
-                if (pos < a.emit_cap) a.emit[pos] = rec;
-                ++pos;
-            });
-        }
     };
     // scores of items past the end never count
     auto mask_tail = [&](f32x16 *acc, int s) {
