@@ -246,7 +246,9 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // bracket width th - tl (exact: both are FP32 values one ulp apart at most)
     const double gam1 = 2.0 * (double)(a.dpad + 1) * 0x1p-23;
     const double th_term = gam1 * fabs((double)tf);
-    const double bracket = (double)th - (double)tl;
+    // (a lane without a live pair gets an empty near-tie band, elo = -inf,
+    // so that the per-step near-tie test is a bare compare)
+    const double bracket = live ? (double)th - (double)tl : -(double)__builtin_inff();
     const double inflate = 1.0 + 1.0 / (double)a.dpad;
     // the FP32 form of the band: every input rounded up; each of the five
     // FP32 operations on these non-negative values loses at most a relative
@@ -254,7 +256,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // 2^-20 and an added 2^-126 keep it above the FP64 value
     const float uh32 = f32_round_up(un_hat), ud32 = f32_round_up(un_del), uf32 = f32_round_up(un_full);
     const float infl32 = f32_round_up(inflate), tt32 = f32_round_up(th_term);
-    const float br32 = f32_round_up(bracket);
+    const float br32 = f32_round_up(bracket);   // -inf without a live pair
     // plain verdict of a near tie: score > tm, i.e. acc > tm - th (exact)
     const float pd = tm - th;
     uint32_t cnt = 0;   // per-lane certain count of the pair
@@ -422,8 +424,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         FT fr[PIPE];
 #pragma unroll
         for (int i = 0; i < PIPE; ++i) fr[i] = frag(i);
-        c = 0;
-        dmin = __builtin_inff();
+        if constexpr (SCREEN) dmin = 0.0f;   // (unused)
 #pragma unroll
         for (int i = 0; i < NRD; ++i) {
             const FT f = fr[i % PIPE];
@@ -433,17 +434,28 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             const int k0 = (i * NSC / NRD) & ~1, k1 = ((i + 1) * NSC / NRD) & ~1;
             for (int k = k0; k < k1; k += 2) {
                 const float v0 = cur[k / 16][k % 16], v1 = cur[(k + 1) / 16][(k + 1) % 16];
-                c += (v0 > ehi) ? 1u : 0u;
-                c += (v1 > ehi) ? 1u : 0u;
+                const uint32_t b = ((v0 > ehi) ? 1u : 0u) + ((v1 > ehi) ? 1u : 0u);
                 // min(dmin, |v0|, |v1|) in one instruction (fminf would
                 // quieten its operands first; the scores are never NaN);
-                // screening has no near ties to look for
-                if constexpr (!SCREEN)
-                    asm("v_min3_f32 %0, %1, |%2|, |%3|" : "=v"(dmin) : "v"(dmin), "v"(v0), "v"(v1));
+                // screening has no near ties to look for.  The first pair
+                // starts both (no constants to move in).
+                if (k == 0) {
+                    c = b;
+                    if constexpr (!SCREEN) asm("v_min_f32 %0, |%1|, |%2|" : "=v"(dmin) : "v"(v0), "v"(v1));
+                } else {
+                    c += b;
+                    if constexpr (!SCREEN)
+                        asm("v_min3_f32 %0, %1, |%2|, |%3|" : "=v"(dmin) : "v"(dmin), "v"(v0), "v"(v1));
+                }
             }
             // keep this chunk's share here: the compiler would otherwise
             // sink it out of the block to where the count is used
-            asm volatile("" : "+v"(c), "+v"(dmin));
+            if (k1 > 0) {
+                if constexpr (SCREEN)
+                    asm volatile("" : "+v"(c));
+                else
+                    asm volatile("" : "+v"(c), "+v"(dmin));
+            }
             side(i);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -550,7 +562,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             live = live && rem >= 0;
         } else {
             cnt += c;
-            if (__ballot(live && dmin <= elo) != 0ull) emit_ties(cur, ehi, elo, item0);
+            if (__ballot(dmin <= elo) != 0ull) emit_ties(cur, ehi, elo, item0);   // (elo = -inf: no live pair)
         }
         mask_tail(nxt, st + 1);
         ehi = ehi_n;
