@@ -253,10 +253,14 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // the FP32 form of the band: every input rounded up; each of the five
     // FP32 operations on these non-negative values loses at most a relative
     // 2^-24 (plus 2^-150 if the result is subnormal), so a final factor 1 +
-    // 2^-20 and an added 2^-126 keep it above the FP64 value
+    // 2^-20 and an added 2^-126 keep it above the FP64 value.  Plain mode
+    // (no near ties, acc > 0 counts) comes out of the same instructions: a
+    // zero factor, threshold term and 2^-126 give ehi = 0, and a bracket of
+    // -inf gives elo = -inf.
     const float uh32 = f32_round_up(un_hat), ud32 = f32_round_up(un_del), uf32 = f32_round_up(un_full);
-    const float infl32 = f32_round_up(inflate), tt32 = f32_round_up(th_term);
-    const float br32 = f32_round_up(bracket);   // -inf without a live pair
+    const float infl32 = a.plain ? 0.0f : f32_round_up(inflate), tt32 = a.plain ? 0.0f : f32_round_up(th_term);
+    const float br32 = a.plain ? -__builtin_inff() : f32_round_up(bracket);   // -inf without a live pair too
+    const float tiny32 = a.plain ? 0.0f : 0x1p-126f;
     // plain verdict of a near tie: score > tm, i.e. acc > tm - th (exact)
     const float pd = tm - th;
     uint32_t cnt = 0;   // per-lane certain count of the pair
@@ -335,16 +339,13 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         ehi = f32_round_up(E * (1.0 + 1e-9));
         elo = f32_round_up((E + bracket) * (1.0 + 1e-9));
     };
+    // (no branch: plain mode's edges come from the set-up values above; the
+    // coefficients are finite, so e is 0 there)
     auto band_of32 = [&](float ca, float cb, float cc, float cabs, float &ehi, float &elo) {
-        if (a.plain) {
-            ehi = 0.0f;
-            elo = -__builtin_inff();
-            return;
-        }
         const float e = __builtin_fmaf(__builtin_fmaf(uh32, ca, __builtin_fmaf(ud32, cb, __builtin_fmaf(uf32, cc, cabs))),
                                        infl32, tt32);
-        ehi = __builtin_fmaf(e, 1.0f + 0x1p-20f, 0x1p-126f);
-        elo = __builtin_fmaf(e + br32, 1.0f + 0x1p-20f, 0x1p-126f);
+        ehi = __builtin_fmaf(e, 1.0f + 0x1p-20f, tiny32);
+        elo = __builtin_fmaf(e + br32, 1.0f + 0x1p-20f, tiny32);
     };
     auto band_of_tile = [&](const uint8_t *tile, float &ehi, float &elo) {
         if constexpr (B32) {

@@ -76,6 +76,27 @@ def test_plain_f32_reports_its_disagreement(small):
     ex.close()
 
 
+def test_plain_bf16_on_exact_integer_scores():
+    """Plain mode of the BF16 passes (no recheck: a score counts when its FP32
+    value exceeds fl32(t), no near ties).  With small integer entries every
+    score, threshold and accumulator is an exact integer in FP32, so the plain
+    verdict is the exact one: the all-ranks pass and the batch pipeline must
+    give the oracle's ranks and answers (Def. 1, Def. 2), ties included."""
+    rng = np.random.default_rng(5)
+    U = rng.integers(-2, 3, size=(3000, 24)).astype(np.float32)
+    P = rng.integers(-2, 3, size=(4100, 24)).astype(np.float32)
+    Qv = P[rng.choice(4100, 6, replace=False)]
+    R = O.ranks(O.widen(U), O.widen(P), O.widen(Qv))
+    idx = rkr.Index(_dev(U, "f32"), _dev(P, "f32"), score="bf16", recheck=False)
+    for i in (0, 3):
+        got = idx.ranks(_dev(Qv[i], "f32")).cpu().numpy()
+        assert np.array_equal(got, R[i]), (i, np.flatnonzero(got != R[i])[:10])
+    ks = np.array([1, 7, 30, 100, 5, 64], np.int32)
+    _check_exact(R, _answers(*idx.query_batch(_dev(Qv, "f32"), ks)), ks)
+    assert idx.stats()["uncertain"] == 0
+    idx.close()
+
+
 @pytest.mark.parametrize("d", [3, 8, 16])
 @pytest.mark.parametrize("score", ["bf16", "f32", "fp8", "bf16x3"])
 def test_integer_tie_storm(d, score):
