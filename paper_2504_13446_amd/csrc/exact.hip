@@ -264,6 +264,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
     // plain verdict of a near tie: score > tm, i.e. acc > tm - th (exact)
     const float pd = tm - th;
     uint32_t cnt = 0;   // per-lane certain count of the pair
+    uint32_t nlive = 0;   // screening: steps scored with a live pair
     // Cauchy-Schwarz settle of the exact passes (Lemma 1 over the
     // norm-sorted items): |s64(u,p)| <= |u||p| (1 + gamma64) and |p| <= Z[st]
     // from step st on, so from the first step s_set with |u| Z[st] (1 +
@@ -558,7 +559,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             // the budget left after this step's certainly-above items
             nscored += (uint64_t)(__popcll(__ballot(live)) / 2) *
                        (uint64_t)(st < s_full ? NIB * 32 : (int)(a.m - item0));
-            ncmp += live ? (uint64_t)NSC : 0;
+            nlive += live ? 1u : 0u;
             rem -= (int)pair_sum(c);   // both halves of the step's items (lanes l and l + 32)
             live = live && rem >= 0;
         } else {
@@ -594,6 +595,7 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
             a.ent_len[split * a.len_stride + t] = live ? 1 : 0;
             if (live) a.ent_cnt[e_pair] = (uint32_t)rem;
         }
+        ncmp += (uint64_t)nlive * NSC;
         nslot += ncmp;
         return;
     }
