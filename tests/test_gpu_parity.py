@@ -76,6 +76,30 @@ def test_plain_f32_reports_its_disagreement(small):
     ex.close()
 
 
+@pytest.mark.parametrize("score", ["bf16", "f32"])
+def test_single_query_entries(small, score):
+    """rkr_query_exact and rkr_query_approx on one query each: the exact call
+    returns the oracle's top-k by (rank, id) (Def. 2); the approximate call
+    returns k distinct users whose reported ranks are upper bounds of their
+    exact ranks, with zero Def. 3 violations at c = 1.5 and c = 2."""
+    w, R = small
+    idx = rkr.Index(_dev(w.U, w.dtype), _dev(w.P, w.dtype), score=score)
+    for i in (0, 5):
+        q = _dev(w.Qv[i], w.dtype)
+        k = int(w.k[i])
+        gi, gr = (t.cpu().numpy() for t in idx.query_exact(q, k))
+        wi, wr = O.topk(R[i], k)
+        assert np.array_equal(gi, wi) and np.array_equal(gr, wr), (score, i)
+        for c in (1.5, 2.0):
+            ai, ar = (t.cpu().numpy() for t in idx.query_approx(q, k, c))
+            assert len(set(ai.tolist())) == k, (score, i, c)
+            true = R[i][ai]
+            assert np.all(ar >= true), (score, i, c)
+            v, _ = O.def3_check(true, wr, c)
+            assert v == 0, (score, i, c)
+    idx.close()
+
+
 def test_plain_bf16_on_exact_integer_scores():
     """Plain mode of the BF16 passes (no recheck: a score counts when its FP32
     value exceeds fl32(t), no near ties).  With small integer entries every
