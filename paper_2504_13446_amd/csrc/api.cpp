@@ -912,7 +912,7 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         HIPCK(launch_query_xyz(x->qnorm3.as<double>(), nq, x->g32, x->g64, x->qxyz.as<float4>(), st));
         HIPCK(launch_thresh_approx(x->ulp.as<uint8_t>(), n, x->dpad, x->nks, x->unorm3.as<double>(),
                                    x->qlp.as<uint8_t>(), nq, x->qxyz.as<float4>(), x->tup.as<float>(),
-                                   x->keys.as<uint64_t>(), x->num_cus, st));
+                                   x->keys.as<uint32_t>(), x->num_cus, st));
     } else if (dense)
         HIPCK(launch_thresh_dense(x->Um.p, n, Qm, nq, d, x->mk, ps.t64, st, keys_fused ? x->unorm3.as<double>() : nullptr,
                                   keys_fused ? x->keys.as<uint64_t>() : nullptr));
@@ -997,7 +997,12 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         if (!d_coff || !d_C || !csel || !ckeys || !cpid) return fail(RKR_E_NOMEM, "estimator candidates");
         HIPCK(hipMemcpyAsync(d_coff, coff.data(), (nq + 1) * 8, hipMemcpyHostToDevice, st));
         HIPCK(hipMemcpyAsync(d_C, Cv.data(), nq * 4, hipMemcpyHostToDevice, st));
-        HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), d_C, nq, d_coff, csel, st));
+        // (with bounded thresholds the seed keys are 32 bits, the user being
+        // the position in the query's row)
+        if (approx_t)
+            HIPCK(launch_select32(x->keys.as<uint32_t>(), x->segoff.as<int64_t>(), d_C, nq, d_coff, csel, st));
+        else
+            HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), d_C, nq, d_coff, csel, st));
         HIPCK(q_est_cand_pids(csel, d_coff, nq, nc, cpid, st));
         if (approx_t)
             HIPCK(launch_thresh_list(cpid, nc, ps.pair_u, ps.pair_q, x->Um.p, Qm, d, x->mk, ps.t64, st));
@@ -1006,6 +1011,9 @@ static rkr_status run_batch(rkr_index *x, int32_t nq, const void *Qm, const int3
         HIPCK(q_est_cand_keys(csel, x->est.pred.as<float>(), nc, ckeys, st));
         HIPCK(launch_select(ckeys, d_coff, x->sdev.as<int32_t>(), nq, x->seloff.as<int64_t>(),
                             x->sel.as<uint64_t>(), st));
+    } else if (approx_t) {
+        HIPCK(launch_select32(x->keys.as<uint32_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
+                              x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));
     } else {
         HIPCK(launch_select(x->keys.as<uint64_t>(), x->segoff.as<int64_t>(), x->sdev.as<int32_t>(), nq,
                             x->seloff.as<int64_t>(), x->sel.as<uint64_t>(), st));

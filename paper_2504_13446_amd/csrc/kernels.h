@@ -125,8 +125,10 @@ hipError_t launch_step_coef(const double *coef, int64_t nblk, int nib, int64_t n
 // (query-major), for the rank-table filter; qxyz from launch_query_xyz.
 hipError_t launch_query_xyz(const double *qnorm3, int nq, double g32, double g64, float4 *out, hipStream_t st);
 hipError_t launch_thresh_approx(const uint8_t *ulp, int64_t n, int dpad, int nks, const double *unorm3,
-                                const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up, uint64_t *keys,
+                                const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up, uint32_t *keys,
                                 int num_cus, hipStream_t st);
+// (keys: the 32-bit order keys of -t^ / |u|, query-major [q * n + u]; the user
+// is the position, for launch_select32)
 // FP64 thresholds t64[p] of the listed pairs p = pids[0..N)
 hipError_t launch_thresh_list(const int32_t *pids, int64_t N, const int32_t *pair_u, const int32_t *pair_q,
                               const void *Um, const void *Qm, int d, int mk, double *t64, hipStream_t st);
@@ -147,6 +149,10 @@ hipError_t scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *total, 
 hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, Scratch &sc, hipStream_t st);
 hipError_t launch_select(const uint64_t *keys, const int64_t *seg_off, const int32_t *kk, int64_t nseg,
                          const int64_t *out_off, uint64_t *out, hipStream_t st);
+// the same over 32-bit keys whose id is their position in the segment (output
+// keys (key << 32 | position), as launch_select's)
+hipError_t launch_select32(const uint32_t *keys, const int64_t *seg_off, const int32_t *kk, int64_t nseg,
+                           const int64_t *out_off, uint64_t *out, hipStream_t st);
 // Tasks of the pairs pids[0..N) (ascending, so each user's pairs are a run):
 // one task per user, or, with max_len > 0, one per max_len pairs of a user.
 hipError_t build_tasks(const int32_t *pids, int64_t N, const PairSet &ps, int plain, const int32_t *bound,

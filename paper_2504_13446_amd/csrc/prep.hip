@@ -503,7 +503,8 @@ __global__ void k_recheck_dev(const int2 *rec, const unsigned long long *count, 
 // a_q + b_q, Z_q = gamma64 c_q, all rounded up (the same terms as the error
 // bound of the scores, with q in place of p).  Out: t_up >= t^ + that bound
 // (FP32, rounded up; user-major [u * nq + q]) and the default seed keys
-// (query-major [q * n + u]) from -t^ / |u|.
+// (query-major [q * n + u]): the 32-bit order keys of -t^ / |u|, the user
+// being the position in the query's row.
 // ---------------------------------------------------------------------------
 __global__ void k_query_xyz(const double *qnorm3, int nq, double g32, double g64, float4 *out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -518,13 +519,13 @@ __global__ void k_query_xyz(const double *qnorm3, int nq, double g32, double g64
 // blocks; wave w holds queries 32w .. 32w + 31 of the tile as register-
 // stationary A operands, the block's users are the B operands (one
 // 32x32x16 MFMA per k-step).  A lane's outputs are one user (its column) and
-// 16 queries (rows): keys go out along the users (256 contiguous bytes per
+// 16 queries (rows): keys go out along the users (128 contiguous bytes per
 // query row); t_up goes through LDS so that each user's row of queries is
 // written contiguously.
 template <int NKS>
 __global__ __launch_bounds__(512) void k_thresh_approx(const uint8_t *ulp, int64_t n, int dpad, const double *unorm3,
                                                        const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up,
-                                                       uint64_t *keys) {
+                                                       uint32_t *keys) {
     using FT = typename FragT<SK_BF16>::T;
     constexpr int KS = 16;
     __shared__ float4 sq[256];
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(512) void k_thresh_approx(const uint8_t *ulp, int64
             const float sm = th + __builtin_fmaf(dd, 0x1p-20f, dd);
             stile[l32][ql] = sm + __builtin_fmaf(__builtin_fabsf(sm), 0x1p-22f, 0x1p-126f);
             if (u < n && ql < nqt)
-                keys[(int64_t)(q0 + ql) * n + u] = ((uint64_t)f32_order_key(-th * inv) << 32) | (uint32_t)u;
+                keys[(int64_t)(q0 + ql) * n + u] = f32_order_key(-th * inv);   // (the user is the position)
         }
         __syncthreads();
         for (int idx = threadIdx.x; idx < 32 * 256; idx += 512) {
@@ -838,7 +839,7 @@ hipError_t launch_query_xyz(const double *qnorm3, int nq, double g32, double g64
 }
 
 hipError_t launch_thresh_approx(const uint8_t *ulp, int64_t n, int dpad, int nks, const double *unorm3,
-                                const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up, uint64_t *keys,
+                                const uint8_t *qlp, int nq, const float4 *qxyz, float *t_up, uint32_t *keys,
                                 int num_cus, hipStream_t st) {
     if (n <= 0 || nq <= 0) return hipSuccess;
     const int64_t nblk = (n + 31) / 32;

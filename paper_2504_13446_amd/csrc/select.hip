@@ -108,7 +108,9 @@ hipError_t scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *total, 
 // segment; K <= SEL_MAX, which every caller's limit on k guarantees).  One
 // workgroup per segment: radix passes over the segment narrow a bucket
 // until the keys at or below it fit in LDS, one more pass gathers them, and a
-// bitonic sort orders them; output sorted ascending.
+// bitonic sort orders them; output sorted ascending.  K32: the segment holds
+// 32-bit keys whose id is their position in the segment, and the key of
+// position i is (key << 32 | i) (the dense seed keys: half the bytes read).
 // ---------------------------------------------------------------------------
 constexpr int SEL_BS = 1024;
 constexpr int SEL_MAX = 4096;
@@ -131,7 +133,8 @@ __device__ inline void lds_bitonic_sort(uint64_t *s, int npow2) {
     }
 }
 
-__global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const int64_t *seg_off,
+template <bool K32>
+__global__ __launch_bounds__(SEL_BS) void k_select(const void *keys, const int64_t *seg_off,
                                                    const int32_t *kk, const int64_t *out_off,
                                                    uint64_t *out) {
     __shared__ uint64_t s[SEL_MAX];
@@ -148,7 +151,33 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
     if (K > len) K = len;
     const int64_t ob = out_off[seg];
     if (K <= 0) return;
-    const uint64_t *x = keys + b;
+    // loads in flight per thread: twice as many 4-byte keys, so that as many
+    // bytes are in flight (the passes are bound by that)
+    constexpr int UNR = K32 ? 2 * SEL_UNROLL : SEL_UNROLL;
+    const uint64_t *x = (const uint64_t *)keys + b;
+    const uint32_t *x32 = (const uint32_t *)keys + b;
+    // UNR keys from positions i0 + r * SEL_BS (those past the end are never
+    // used): all loads are issued before any key is put together, so that
+    // they are in flight at once
+    auto load_keys = [&](int64_t i0, uint64_t *v) {
+        if constexpr (K32) {
+            uint32_t w[UNR];
+#pragma unroll
+            for (int r = 0; r < UNR; ++r) {
+                const int64_t i = i0 + (int64_t)r * SEL_BS;
+                w[r] = i < len ? x32[i] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < UNR; ++r)
+                v[r] = ((uint64_t)w[r] << 32) | (uint64_t)(uint32_t)(i0 + (int64_t)r * SEL_BS);
+        } else {
+#pragma unroll
+            for (int r = 0; r < UNR; ++r) {
+                const int64_t i = i0 + (int64_t)r * SEL_BS;
+                v[r] = i < len ? x[i] : 0ull;
+            }
+        }
+    };
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
     uint64_t T;   // select keys <= T
@@ -171,16 +200,12 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
             __syncthreads();
             const uint64_t pre = sh_prefix, msk = sh_mask;
             uint32_t *hw = hf + (wave % ncopy) * nbins;
-            // SEL_UNROLL independent loads in flight per thread
-            for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * SEL_UNROLL) {
-                uint64_t v[SEL_UNROLL];
+            // UNR independent loads in flight per thread
+            for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * UNR) {
+                uint64_t v[UNR];
+                load_keys(i0, v);
 #pragma unroll
-                for (int r = 0; r < SEL_UNROLL; ++r) {
-                    const int64_t i = i0 + (int64_t)r * SEL_BS;
-                    v[r] = i < len ? x[i] : 0ull;
-                }
-#pragma unroll
-                for (int r = 0; r < SEL_UNROLL; ++r) {
+                for (int r = 0; r < UNR; ++r) {
                     // lanes in the first valid lane's bin add their count in
                     // one atomic (keys that pile into one bin would otherwise
                     // serialise on it); the others add one each
@@ -252,15 +277,11 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
     }
     if (tid == 0) sh_cnt = 0;
     __syncthreads();
-    for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * SEL_UNROLL) {
-        uint64_t v[SEL_UNROLL];
+    for (int64_t i0 = tid; i0 < len; i0 += (int64_t)SEL_BS * UNR) {
+        uint64_t v[UNR];
+        load_keys(i0, v);
 #pragma unroll
-        for (int r = 0; r < SEL_UNROLL; ++r) {
-            const int64_t i = i0 + (int64_t)r * SEL_BS;
-            v[r] = i < len ? x[i] : ~0ull;
-        }
-#pragma unroll
-        for (int r = 0; r < SEL_UNROLL; ++r) {
+        for (int r = 0; r < UNR; ++r) {
             if (i0 + (int64_t)r * SEL_BS < len && v[r] <= T) {
                 uint32_t p = atomicAdd(&sh_cnt, 1u);
                 if (p < SEL_MAX) s[p] = v[r];
@@ -280,7 +301,13 @@ __global__ __launch_bounds__(SEL_BS) void k_select(const uint64_t *keys, const i
 hipError_t launch_select(const uint64_t *keys, const int64_t *seg_off, const int32_t *kk, int64_t nseg,
                          const int64_t *out_off, uint64_t *out, hipStream_t st) {
     if (nseg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select, dim3((unsigned)nseg), dim3(SEL_BS), 0, st, keys, seg_off, kk, out_off, out);
+    hipLaunchKernelGGL(k_select<false>, dim3((unsigned)nseg), dim3(SEL_BS), 0, st, keys, seg_off, kk, out_off, out);
+    return hipGetLastError();
+}
+hipError_t launch_select32(const uint32_t *keys, const int64_t *seg_off, const int32_t *kk, int64_t nseg,
+                           const int64_t *out_off, uint64_t *out, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select<true>, dim3((unsigned)nseg), dim3(SEL_BS), 0, st, keys, seg_off, kk, out_off, out);
     return hipGetLastError();
 }
 
