@@ -34,6 +34,11 @@ def _case(name):
     if name == "iid_f32":
         w = W.make("small", n=4000, m=5000, nq=20)
         return w.U, w.P, w.Qv, "f32"
+    if name == "iid_odd_users":
+        # an odd number of users above one selection workgroup's LDS (4,096
+        # keys): the 32-bit seed keys go through the select's radix passes
+        w = W.make("small", n=9001, m=3000, nq=20)
+        return W.f32_to_bf16_bits(w.U), W.f32_to_bf16_bits(w.P), W.f32_to_bf16_bits(w.Qv), "bf16"
     if name == "integer_ties":
         # every score an integer: thresholds tie exactly with table columns
         U = rng.integers(-3, 4, size=(3000, 8)).astype(np.float32)
@@ -46,7 +51,7 @@ def _case(name):
     return U.astype(np.float32), P.astype(np.float32), P[rng.choice(4000, 20, replace=False)].astype(np.float32), "f32"
 
 
-@pytest.mark.parametrize("case", ["iid_bf16", "iid_f32", "integer_ties", "spread_norms"])
+@pytest.mark.parametrize("case", ["iid_bf16", "iid_f32", "iid_odd_users", "integer_ties", "spread_norms"])
 def test_bounded_thresholds_keep_answers_exact(case):
     U, P, Qv, mk = _case(case)
     ks = np.array([1, 3, 5, 10, 20, 40, 7, 2, 64, 10, 10, 15, 33, 4, 8, 1, 50, 6, 12, 9], np.int32)
