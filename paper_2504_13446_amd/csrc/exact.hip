@@ -362,13 +362,16 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
         return item0 + ib * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
     };
     // near ties of the pair in one step to the record buffer, each with the
-    // plain FP32 verdict in its top bit.  One score position at a time: a
-    // wave ballot of the lanes whose score there is a near tie, skipped (a
-    // uniform branch) when there is none, which is nearly always: a step that
-    // gets here usually holds one or two near ties in all of its 64 lanes.
-    // A position adds at most 64 records, so one flush makes room.
+    // plain FP32 verdict in its top bit.  32-item steps (NIB = 1): one score
+    // position at a time, a wave ballot of the lanes whose score there is a
+    // near tie, skipped (a uniform branch) when there is none, which is nearly
+    // always: a step that gets here usually holds one or two near ties in all
+    // of its 64 lanes.  A position adds at most 64 records, so one flush makes
+    // room.  64-item steps (NIB = 2, the shape for 20 k-steps, where near ties
+    // are many): per-lane bit masks of all 32 positions and one pass over the
+    // set bits (32 ballots cost more there).
     static_assert(REC_PER_WAVE >= 64, "a score position's records must fit the buffer");
-    auto emit_ties = [&](const f32x16 *acc, float ehi, float elo, int64_t item0) {
+    auto emit_by_position = [&](const f32x16 *acc, float ehi, float elo, int64_t item0) {
 #pragma unroll
         for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
@@ -388,6 +391,63 @@ __device__ inline void pass_tile(const CountArgs &a, const int64_t tile, const i
                 }
                 rb_n += n;
             }
+    };
+    auto emit_by_masks = [&](const f32x16 *acc, float ehi, float elo, int64_t item0) {
+        // bit ib * 16 + r of each mask is score r of block ib (shifted in
+        // from the top, so that no per-bit constants are needed)
+        uint32_t umask = 0, pmask = 0;
+#pragma unroll
+        for (int ib = NIB - 1; ib >= 0; --ib)
+#pragma unroll
+            for (int r = 15; r >= 0; --r) {
+                const float v = acc[ib][r];
+                umask = (umask << 1) | ((v >= -elo && !(v > ehi)) ? 1u : 0u);
+                pmask = (pmask << 1) | ((v > pd) ? 1u : 0u);
+            }
+        if (!live) umask = 0;
+        const uint32_t nu = __popc(umask);
+        // record offsets: with at most one record per lane (the usual case)
+        // the lane's rank among the lanes that have one, else a prefix sum
+        uint32_t incl, total;
+        const uint64_t has = __ballot(nu != 0);
+        if (__ballot(nu > 1) == 0ull) {
+            incl = __builtin_amdgcn_mbcnt_hi((uint32_t)(has >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)has, 0u)) + nu;
+            total = (uint32_t)__popcll(has);
+        } else {
+            incl = wave_incl_scan(nu, lane);
+            total = __shfl(incl, 63, 64);
+        }
+        if (rb_n + (int)total > REC_PER_WAVE) flush_records();
+        auto put = [&](auto &&store) {
+            uint32_t mm = umask;
+            while (mm) {
+                const int bit = __ffs(mm) - 1;
+                mm &= mm - 1;
+                const int64_t item = item_of(item0, bit >> 4, bit & 15);
+                const int plainbit = ((pmask >> bit) & 1u) ? (int)0x80000000 : 0;
+                store(make_int2(pid, (int)item | plainbit));
+            }
+        };
+        if ((int)total <= REC_PER_WAVE) {
+            int pos = rb_n + (int)(incl - nu);
+            put([&](int2 rec) { recbuf[pos++] = rec; });
+            rb_n += (int)total;
+        } else {
+            // more than a buffer's worth at once: straight to the output
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(a.emit_count, (unsigned long long)total);
+            unsigned long long pos = __shfl(base, 0, 64) + (incl - nu);
+            put([&](int2 rec) {
+                if (pos < a.emit_cap) a.emit[pos] = rec;
+                ++pos;
+            });
+        }
+    };
+    auto emit_ties = [&](const f32x16 *acc, float ehi, float elo, int64_t item0) {
+        if constexpr (NIB == 1)
+            emit_by_position(acc, ehi, elo, item0);
+        else
+            emit_by_masks(acc, ehi, elo, item0);
     };
     // scores of items past the end never count
     auto mask_tail = [&](f32x16 *acc, int s) {
