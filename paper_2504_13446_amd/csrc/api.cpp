@@ -509,7 +509,7 @@ static const std::vector<int> &screen_phases() {
                 p = *q ? q + 1 : q;
             }
         }
-        if (v.empty() || v.back() != 64) v = {3, 6, 12, 24, 40, 64};
+        if (v.empty() || v.back() != 64) v = {2, 5, 10, 20, 36, 64};
         return v;
     }();
     return ends;
